@@ -1,0 +1,222 @@
+/*
+ * hsym.h - C ABI of the MI355X (gfx950) LOBPCG hot path.
+ *
+ * Problem (Section 3.1, eq. 6 and Algorithm 1 of Shao et al., "Accelerating
+ * nuclear configuration interaction calculations through a preconditioned
+ * block iterative eigensolver"): given a sparse symmetric H and a start block
+ * X0 (n x k), find the k smallest eigenpairs H X = X Theta.  H is handed over
+ * as one stored triangle (Section 4.1), block vectors are row-major
+ * (Section 4.2), the block width exceeds the number of wanted pairs
+ * (Section 3.1, end; Section 5.2 uses 50% extra vectors), and the solver takes
+ * a preconditioner choice (Section 3.2) and a start block (Section 3.3).
+ *
+ * Conventions for every call:
+ *   - every function returns an int status (enum hsym_status); no exception or
+ *     abort crosses the ABI; hsym_last_error() gives a message for the
+ *     calling thread;
+ *   - "device" pointers are HIP device allocations on the current device,
+ *     "host" pointers are ordinary host memory;
+ *   - a stream argument is a hipStream_t passed as void* (NULL = the null
+ *     stream).  Calls marked "async" only enqueue work on that stream;
+ *   - n x m blocks are row-major with a leading dimension (elements between
+ *     consecutive rows) >= m;
+ *   - eigenvalues are ascending; each returned eigenvector is scaled to unit
+ *     2-norm with its largest-magnitude entry positive.
+ *
+ * The library allocates device memory with hipMalloc (matrix, per-call
+ * scratch, solver work blocks) and frees it before returning, except what a
+ * handle owns until it is destroyed.
+ */
+#ifndef HSYM_H
+#define HSYM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum hsym_status {
+    HSYM_OK = 0,
+    HSYM_NOT_CONVERGED = 1,      /* results written, tolerance not met at maxit        */
+    HSYM_E_INVALID_ARG = -1,     /* bad sizes, malformed CSR, NaN/Inf values, NULL ptr */
+    HSYM_E_OUT_OF_MEMORY = -2,   /* device or host allocation failed                   */
+    HSYM_E_DEVICE = -3,          /* a HIP runtime call failed                          */
+    HSYM_E_BREAKDOWN = -4,       /* block lost rank and could not be repaired          */
+    HSYM_E_NUMERIC = -5,         /* NaN/Inf appeared during a solve                    */
+    HSYM_E_UNSUPPORTED = -6      /* block width / option combination not built         */
+};
+
+enum hsym_prec { HSYM_FP64 = 0, HSYM_FP32 = 1 };
+
+/* Preconditioners of Section 3.2 (eq. 11): none, the diagonal of H
+ * ("the extreme case" of a block-diagonal approximation), or the dense 64x64
+ * diagonal blocks of H solved directly with fp64 factors. */
+enum hsym_precond { HSYM_PRECOND_NONE = 0, HSYM_PRECOND_JACOBI = 1, HSYM_PRECOND_BLOCK64 = 2 };
+
+/* hsym_create flags */
+#define HSYM_HOST_PTRS     0x0   /* rowptr/colind/values are host memory (default)   */
+#define HSYM_BUILD_BLOCK64 0x2   /* also build the 64x64 block preconditioner factors */
+/* Tile geometry hint: the block width (1..16) the panel sizes are chosen for,
+ * in bits 8..15 (0 = 16).  Any block width whose LDS footprint fits the chosen
+ * geometry can be used with the handle; a narrower hint gives taller panels. */
+#define HSYM_GEOM_M(m) (((m) & 0xff) << 8)
+
+typedef struct hsym_matrix *hsym_t;
+typedef struct lobpcg_ctx *lobpcg_ctx_t;
+
+typedef struct {
+    int64_t n;
+    int64_t nnz_stored;         /* stored entries incl. the diagonal                  */
+    double norm1;               /* ||H||_1 = max absolute row sum of the full matrix  */
+    int storage;                /* enum hsym_prec of the stored values                */
+    int panel_rows;             /* rows per panel of the tile format                  */
+    int chunk_cols;             /* columns per tile chunk                             */
+    int64_t npanels;
+    int64_t ntiles;
+    int64_t nslots;             /* tiles whose transposed half leaves the panel       */
+    int64_t padded_entries;     /* stored off-diagonal entries after slice padding    */
+    int64_t device_bytes;       /* device memory held by the handle                   */
+    int has_block64;
+} hsym_info_t;
+
+/*
+ * Build a device-resident handle from the upper triangle of H in CSR form
+ * (Section 4.1 stores one triangle; this ABI takes the upper one, which is
+ * the transpose of the paper's lower triangle).
+ *   rowptr  host int64[n+1], rowptr[0]=0, non-decreasing, rowptr[n]=nnz;
+ *   colind  host int32[nnz], row i holds columns >= i, strictly increasing;
+ *           a missing diagonal entry means H_ii = 0;
+ *   values  host, fp64 (values_prec=HSYM_FP64) or fp32 (HSYM_FP32), finite;
+ *   storage precision of the device copy: HSYM_FP64 (plain form) or HSYM_FP32
+ *           (mixed form, Section 4.4 footnote 5: H stored and multiplied in
+ *           single precision); fp64 input is rounded to nearest once;
+ *   flags   HSYM_HOST_PTRS | optional HSYM_BUILD_BLOCK64.
+ * The call copies: the caller may free its arrays on return.  Synchronous.
+ * Errors: HSYM_E_INVALID_ARG for any CSR violation listed above or n < 1 or
+ * n >= 2^31; HSYM_E_OUT_OF_MEMORY; HSYM_E_DEVICE.  *H is NULL on error.
+ */
+int hsym_create(hsym_t *H, int64_t n, const int64_t *rowptr, const int32_t *colind,
+                const void *values, int values_prec, int storage, int flags, void *stream);
+
+/*
+ * Streaming form of hsym_create for inputs too large to hold whole on the
+ * host: begin, then append consecutive row slabs starting at row 0 (each slab
+ * in the same CSR convention, rowptr_local relative to the slab, int64[nrows+1]),
+ * then finish.  Slabs need not align with anything.  The handle is usable only
+ * after finish returns HSYM_OK; on any error the handle is destroyed and *H
+ * (begin) or the passed handle (append/finish) must not be used again.
+ */
+int hsym_create_begin(hsym_t *H, int64_t n, int storage, int flags, void *stream);
+int hsym_create_append(hsym_t H, int64_t nrows, const int64_t *rowptr_local,
+                       const int32_t *colind, const void *values, int values_prec);
+int hsym_create_finish(hsym_t H);
+
+int hsym_destroy(hsym_t H);
+int hsym_info(hsym_t H, hsym_info_t *out);
+
+/*
+ * Y = H X (async).  X, Y device fp64 n x m with leading dimensions ldx, ldy;
+ * m in {1..16}.  H is applied from its stored triangle as D X + U X + U^T X
+ * (U strictly upper, D the diagonal; Section 4.1: each stored block is used
+ * once as itself and once transposed).  With fp32 storage X is rounded to
+ * fp32 and products and sums are fp32; Y is returned in fp64.
+ * X and Y must not overlap.  Errors: HSYM_E_INVALID_ARG, HSYM_E_DEVICE.
+ */
+int spmm_sym(hsym_t H, int m, const double *X, int64_t ldx, double *Y, int64_t ldy,
+             void *stream);
+
+/* Same product on fp32 blocks (fp32 storage only; m in {1..16}). */
+int spmm_sym_f32(hsym_t H, int m, const float *X, int64_t ldx, float *Y, int64_t ldy,
+                 void *stream);
+
+typedef struct {
+    int maxit;              /* default 1000                                          */
+    uint64_t seed;          /* Gaussian start block / rank-repair columns            */
+    int check_every;        /* host convergence check every k iterations (>=1)       */
+    int no_precond_iters;   /* Section 4.3 rule 1, default 3                         */
+    double near;            /* Section 4.3 rules 2-4 threshold, default 0.1          */
+    double guard;           /* shifted denominators kept >= guard*||H||_1, 1e-4       */
+    int keep_history;       /* record per-iteration residual norms                   */
+} lobpcg_opts;
+
+#define HSYM_MAX_BLOCK 16
+#define HSYM_MAX_HISTORY 4096
+
+typedef struct {
+    int iters;                        /* LOBPCG iterations performed                 */
+    int converged;
+    int spmm_calls;                   /* block SpMMs, start block included           */
+    int p_dropped;                    /* iterations where P lost rank and was dropped */
+    int w_replaced;                   /* W columns replaced by random columns         */
+    double theta[HSYM_MAX_BLOCK];     /* all m Ritz values at exit                    */
+    double resnorm[HSYM_MAX_BLOCK];   /* ||r_j|| / ||H||_1 at exit, all m columns     */
+    double seconds;                   /* wall time of the solve                      */
+    double phase_ms[8];               /* spmm, precond, orth, rr_gram, small, update, sync, other */
+    int history_len;
+    double history[HSYM_MAX_HISTORY]; /* max_{j<=nev} rho_j per iteration           */
+} lobpcg_report;
+
+void lobpcg_opts_default(lobpcg_opts *o);
+
+/*
+ * LOBPCG (Algorithm 1) for the nev smallest eigenpairs with block width
+ * block_width (nev <= block_width <= 16, 3*block_width <= n).  tol > 0 is the
+ * relative residual ||H x_j - theta_j x_j|| / (||H||_1 ||x_j||) that each of
+ * the first nev pairs must reach.  X0: device n x block_width fp64 (ld =
+ * block_width) or NULL for a seeded Gaussian block.  evals: host[nev].
+ * evecs: device n x nev fp64 (ld = nev) or NULL.  rep, opts may be NULL.
+ * Block vectors, Gram products, Cholesky-QR, the Rayleigh-Ritz eigensolve and
+ * the convergence test are fp64 for both storage precisions.
+ * Host-synchronous: returns after convergence or maxit (HSYM_NOT_CONVERGED,
+ * results written).
+ */
+int lobpcg_solve(hsym_t H, int nev, int block_width, double tol, const double *X0,
+                 int precond, const lobpcg_opts *opts, double *evals, double *evecs,
+                 lobpcg_report *rep, void *stream);
+
+typedef struct {
+    int maxit;        /* default 2000 (also capped by n)                             */
+    uint64_t seed;    /* Gaussian start vector when v0 is NULL                       */
+} lanczos_opts;
+
+typedef struct {
+    int iters;
+    int converged;
+    double resnorm[HSYM_MAX_BLOCK];  /* Ritz residual / ||H||_1 of the nev pairs     */
+    double seconds;
+    double spmv_ms;
+    double orth_ms;
+} lanczos_report;
+
+/*
+ * Single-vector Lanczos with full re-orthogonalisation (the baseline the paper
+ * replaces; Section 3, opening) with convergence checks on the schedule of
+ * Section 5.2 footnote 7.  nev <= 16.  v0: device fp64[n] or NULL.  evals host[nev];
+ * evecs device n x nev or NULL.  Host-synchronous.
+ */
+int lanczos_solve(hsym_t H, int nev, double tol, const double *v0, const lanczos_opts *opts,
+                  double *evals, double *evecs, lanczos_report *rep, void *stream);
+
+/*
+ * Context/step form of lobpcg_solve for request loops: a context owns its
+ * block vectors on the device; lobpcg_ctx_step advances `count` contexts by
+ * up to `iters` iterations each, sharing one launch per phase among
+ * contexts whose matrices are small.  A context's arithmetic does not depend
+ * on which other contexts are stepped with it.
+ */
+int lobpcg_ctx_create(lobpcg_ctx_t *ctx, hsym_t H, int nev, int block_width, double tol,
+                      const double *X0, int precond, const lobpcg_opts *opts, void *stream);
+int lobpcg_ctx_step(lobpcg_ctx_t *ctxs, int count, int iters);
+int lobpcg_ctx_status(lobpcg_ctx_t ctx, int *done, double *evals, lobpcg_report *rep);
+int lobpcg_ctx_evecs(lobpcg_ctx_t ctx, double *evecs);
+int64_t lobpcg_ctx_device_bytes(lobpcg_ctx_t ctx);
+int lobpcg_ctx_destroy(lobpcg_ctx_t ctx);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *hsym_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

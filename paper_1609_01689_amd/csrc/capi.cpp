@@ -1,0 +1,224 @@
+// C ABI entry points: argument checks, error capture, handle lifetime.
+#include <cstring>
+#include <mutex>
+
+#include "hsym_internal.h"
+
+namespace hsym {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+void fail(int status, const std::string &msg) { throw Error{status, msg}; }
+
+void check_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return;
+    (void)hipGetLastError();
+    int st = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? HSYM_E_OUT_OF_MEMORY : HSYM_E_DEVICE;
+    fail(st, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+Scratch::~Scratch() { if (p) (void)hipFree(p); }
+
+void *Scratch::get(size_t b) {
+    if (b <= bytes && p) return p;
+    if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+    if (hipMalloc(&p, std::max<size_t>(b, 256)) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        fail(HSYM_E_OUT_OF_MEMORY, "scratch allocation of " + std::to_string(b) + " bytes");
+    }
+    bytes = b;
+    return p;
+}
+
+void builder_begin(hsym_matrix *H, int64_t nnz_hint);
+void builder_append(hsym_matrix *H, int64_t nrows, const int64_t *rp, const int32_t *ci, const void *vals,
+                    int vprec);
+void builder_finish(hsym_matrix *H);
+void builder_discard(hsym_matrix *H);
+
+}  // namespace hsym
+
+using namespace hsym;
+
+#define API_BEGIN try {
+#define API_END                                              \
+    }                                                        \
+    catch (Error & e) {                                      \
+        set_error(e.msg);                                    \
+        return e.status;                                     \
+    }                                                        \
+    catch (std::bad_alloc &) {                               \
+        set_error("host allocation failed");                 \
+        return HSYM_E_OUT_OF_MEMORY;                         \
+    }                                                        \
+    catch (std::exception & e) {                             \
+        set_error(e.what());                                 \
+        return HSYM_E_DEVICE;                                \
+    }                                                        \
+    set_error("");                                           \
+    return HSYM_OK;
+
+static void destroy_matrix(hsym_matrix *H) {
+    if (!H) return;
+    builder_discard(H);
+    free_tiles(&H->tiles);
+    if (H->diag64) (void)hipFree(H->diag64);
+    if (H->diag32) (void)hipFree(H->diag32);
+    if (H->pre_q) (void)hipFree(H->pre_q);
+    if (H->pre_lam) (void)hipFree(H->pre_lam);
+    delete H;
+}
+
+extern "C" {
+
+const char *hsym_last_error(void) { return g_last_error.c_str(); }
+
+static int geom_from_flags(int flags) {
+    int g = (flags >> 8) & 0xff;
+    return g ? g : 16;
+}
+
+int hsym_create_begin(hsym_t *out, int64_t n, int storage, int flags, void *stream) {
+    if (out) *out = nullptr;
+    hsym_matrix *H = nullptr;
+    API_BEGIN
+    if (!out) fail(HSYM_E_INVALID_ARG, "NULL handle pointer");
+    if (n < 1 || n >= ((int64_t)1 << 31)) fail(HSYM_E_INVALID_ARG, "n must be in [1, 2^31)");
+    if (storage != HSYM_FP64 && storage != HSYM_FP32) fail(HSYM_E_INVALID_ARG, "storage must be HSYM_FP64 or HSYM_FP32");
+    H = new hsym_matrix();
+    H->n = n;
+    H->storage = storage;
+    H->flags = flags;
+    H->geom_m = geom_from_flags(flags);
+    H->stream = (hipStream_t)stream;
+    HIPCHK(hipGetDevice(&H->device));
+    try {
+        builder_begin(H, 0);
+    } catch (...) {
+        destroy_matrix(H);
+        throw;
+    }
+    *out = H;
+    API_END
+}
+
+int hsym_create_append(hsym_t H, int64_t nrows, const int64_t *rowptr_local, const int32_t *colind,
+                       const void *values, int values_prec) {
+    API_BEGIN
+    if (!H) fail(HSYM_E_INVALID_ARG, "NULL handle");
+    if (values_prec != HSYM_FP64 && values_prec != HSYM_FP32) fail(HSYM_E_INVALID_ARG, "bad values precision");
+    try {
+        builder_append(H, nrows, rowptr_local, colind, values, values_prec);
+    } catch (...) {
+        destroy_matrix(H);
+        throw;
+    }
+    API_END
+}
+
+int hsym_create_finish(hsym_t H) {
+    API_BEGIN
+    if (!H) fail(HSYM_E_INVALID_ARG, "NULL handle");
+    try {
+        builder_finish(H);
+    } catch (...) {
+        destroy_matrix(H);
+        throw;
+    }
+    API_END
+}
+
+int hsym_create(hsym_t *out, int64_t n, const int64_t *rowptr, const int32_t *colind, const void *values,
+                int values_prec, int storage, int flags, void *stream) {
+    if (out) *out = nullptr;
+    API_BEGIN
+    if (!out) fail(HSYM_E_INVALID_ARG, "NULL handle pointer");
+    if (!rowptr) fail(HSYM_E_INVALID_ARG, "NULL rowptr");
+    if (n < 1 || n >= ((int64_t)1 << 31)) fail(HSYM_E_INVALID_ARG, "n must be in [1, 2^31)");
+    if (rowptr[0] != 0) fail(HSYM_E_INVALID_ARG, "rowptr[0] != 0");
+    if (values_prec != HSYM_FP64 && values_prec != HSYM_FP32) fail(HSYM_E_INVALID_ARG, "bad values precision");
+    hsym_t H = nullptr;
+    int st = hsym_create_begin(&H, n, storage, flags, stream);
+    if (st) return st;
+    try {
+        builder_append(H, n, rowptr, colind, values, values_prec);
+        builder_finish(H);
+    } catch (...) {
+        destroy_matrix(H);
+        throw;
+    }
+    *out = H;
+    API_END
+}
+
+int hsym_destroy(hsym_t H) {
+    API_BEGIN
+    if (!H) fail(HSYM_E_INVALID_ARG, "NULL handle");
+    destroy_matrix(H);
+    API_END
+}
+
+int hsym_info(hsym_t H, hsym_info_t *o) {
+    API_BEGIN
+    if (!H || !o) fail(HSYM_E_INVALID_ARG, "NULL argument");
+    if (!H->ready) fail(HSYM_E_INVALID_ARG, "handle not finished");
+    memset(o, 0, sizeof(*o));
+    o->n = H->n;
+    o->nnz_stored = H->nnz;
+    o->norm1 = H->norm1;
+    o->storage = H->storage;
+    o->panel_rows = H->tiles.R;
+    o->chunk_cols = H->tiles.C;
+    o->npanels = H->tiles.npanels;
+    o->ntiles = H->tiles.ntiles;
+    o->nslots = H->tiles.nslots;
+    o->padded_entries = H->tiles.nentries;
+    o->device_bytes = H->bytes;
+    o->has_block64 = H->pre_q != nullptr;
+    API_END
+}
+
+static void check_block(hsym_t H, int m, const void *X, int64_t ldx, const void *Y, int64_t ldy) {
+    if (!H || !H->ready) fail(HSYM_E_INVALID_ARG, "invalid handle");
+    if (m < 1 || m > HSYM_MAX_BLOCK) fail(HSYM_E_INVALID_ARG, "m must be in [1, 16]");
+    if (!X || !Y) fail(HSYM_E_INVALID_ARG, "NULL block");
+    if (ldx < m || ldy < m) fail(HSYM_E_INVALID_ARG, "leading dimension < m");
+}
+
+int spmm_sym(hsym_t H, int m, const double *X, int64_t ldx, double *Y, int64_t ldy, void *stream) {
+    API_BEGIN
+    check_block(H, m, X, ldx, Y, ldy);
+    hipStream_t s = (hipStream_t)stream;
+    void *pp = nullptr;
+    HIPCHK(hipMallocAsync(&pp, spmm_partial_bytes(H, m), s));
+    try {
+        spmm_launch(H, m, X, T_F64, ldx, Y, T_F64, ldy, pp, s);
+    } catch (...) {
+        (void)hipFreeAsync(pp, s);
+        throw;
+    }
+    HIPCHK(hipFreeAsync(pp, s));
+    API_END
+}
+
+int spmm_sym_f32(hsym_t H, int m, const float *X, int64_t ldx, float *Y, int64_t ldy, void *stream) {
+    API_BEGIN
+    check_block(H, m, X, ldx, Y, ldy);
+    if (H->storage != HSYM_FP32) fail(HSYM_E_INVALID_ARG, "spmm_sym_f32 needs fp32 storage");
+    hipStream_t s = (hipStream_t)stream;
+    void *pp = nullptr;
+    HIPCHK(hipMallocAsync(&pp, spmm_partial_bytes(H, m), s));
+    try {
+        spmm_launch(H, m, X, T_F32, ldx, Y, T_F32, ldy, pp, s);
+    } catch (...) {
+        (void)hipFreeAsync(pp, s);
+        throw;
+    }
+    HIPCHK(hipFreeAsync(pp, s));
+    API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Launchers of the block-vector kernels (dense.hip) and the small dense
+// kernels (small.hip).
+#pragma once
+#include "hsym_internal.h"
+
+namespace hsym {
+
+struct GramArgs {
+    const double *a[3];
+    const double *b[3];
+    int na, nb;       // number of n x m blocks on each side
+    int m;
+    int64_t n;
+};
+// out (na*m x nb*m, row-major) = [a]^T [b]; scratch >= gram_scratch_bytes
+void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s);
+size_t gram_scratch_bytes(int64_t n, int K1, int K2);
+
+struct LincombArgs {
+    const double *in[6];   // set 0: in[0..nin), set 1: in[3..3+nin)
+    double *out[4];        // set 0: out[0..nout), set 1: out[2..2+nout)
+    const double *coef;    // (nin*m) x (nout*m), row stride ldc, device
+    int ldc;
+    int nin, nout, nsets, m;
+    int64_t n;
+    const double *theta;   // optional: residual of (set1 out0) - (set0 out0) diag(theta)
+    double *res;
+    double *norm_part;     // lincomb_norm_parts(n) x m
+};
+void lincomb(const LincombArgs &a, hipStream_t s);
+int64_t lincomb_norm_parts(int64_t n);
+void colsum_final(const double *part, int64_t nparts, int m, double *out, hipStream_t s);
+void residual(const double *X, const double *AX, const double *theta, double *R, double *norm_part, int64_t n,
+              int m, hipStream_t s);
+void precond_apply(hsym_matrix *H, int kind, double *W, const double *mu, double delta, int m, hipStream_t s);
+void to_f32(const double *x, float *y, int64_t cnt, hipStream_t s);
+
+// Gaussian block from the counter-based generator (SplitMix64 over a Weyl
+// sequence, Box-Muller cosine branch): entry (i, j) of the stream (seed,
+// purpose).  Only the columns set in `mask` are written (mask = -1: all).
+void gauss_fill(double *V, int64_t n, int m, int64_t ld, uint64_t seed, uint64_t purpose, int mask,
+                hipStream_t s);
+// evecs[:, j] = sign_j X[:, j] for j < nev (ld nev), sign_j making the
+// largest-magnitude entry of column j positive (first such row on ties).
+void sign_fix_copy(const double *X, int m, int nev, int64_t n, double *evecs, double *scratch, hipStream_t s);
+size_t sign_fix_scratch_bytes(int64_t n, int m);
+
+void dots(const double *V, int64_t ldv, int k, const double *w, int64_t n, double *h, hipStream_t s);
+void sub_vh(const double *V, int64_t ldv, const double *h, int k, double *w, int64_t n, hipStream_t s);
+void axpby2(double *w, const double *v1, const double *ab, const double *v0, int64_t n, hipStream_t s);
+void scale_to(const double *w, const double *nrm2, double *v, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// small dense kernels (one workgroup per problem, batched over problems)
+// ---------------------------------------------------------------------------
+// Orthonormalisation of W against B = [X P] (kb = number of basis blocks) and
+// itself, driven by Gram matrices G = [B W]^T W ((kb+1)m x m):
+//   stage 0: coef = [-G_B D; D], D = diag of inverse projected column norms
+//   stage 1: coef = [-G_B L^-T; L^-T] with L L^T = W^T W - G_B^T G_B
+//   stage 2: coef = L^-T with L L^T = W^T W   (second Cholesky-QR pass)
+// flag[0] receives a bit mask of deficient columns (stage 0/1) or 1 when the
+// Cholesky factorisation failed.
+struct OrthArgs {
+    const double *gram;   // (kb+1)m x m
+    double *coef;         // (kb+1)m x m  (stage 2: m x m)
+    int *flag;
+    int kb, m, stage;
+};
+void small_orth(const OrthArgs *a, int count, hipStream_t s);
+
+// Rayleigh-Ritz on the projected matrix A = S^T (H S) (k x k, k = nblk*m,
+// S = [X W P] orthonormal): eigenvalues ascending; coef = [C_X | C_P]
+// (k x 2m): C_X = the m lowest Ritz vectors, C_P an orthonormal basis of the
+// W,P-components of C_X made orthogonal to C_X; theta[0..m).
+struct RRArgs {
+    const double *gram;   // k x k
+    double *coef;         // k x 2m
+    double *theta;        // m
+    double *evals_all;    // k (diagnostics)
+    int *flag;            // sweeps used (>0) or -1 on failure
+    int nblk, m;
+};
+void small_rr(const RRArgs *a, int count, hipStream_t s);
+
+struct OrthWork {
+    double *gbuf;       // >= 48*16 doubles, device
+    double *coef;       // >= 48*16 doubles, device
+    double *gram_scr;   // >= gram_scratch_bytes(n, 3m, m)
+    int *flag_d;        // device int
+    int *flag_h;        // pinned host int
+};
+int orthonormalize_block(int64_t n, int m, double *V, const double *const *B, int kb, uint64_t seed,
+                         OrthWork &w, hipStream_t s);
+
+}  // namespace hsym

@@ -1,0 +1,529 @@
+// Tall-skinny block-vector kernels of the LOBPCG iteration (fp64, row-major
+// n x m blocks with leading dimension m, m <= 16):
+//   - block inner products X^T Y (Section 4.4 "block inner product") on the
+//     fp64 matrix cores, reduced in two deterministic stages;
+//   - linear combinations Y = X G (Section 4.4 "linear combination"), fused
+//     where the iteration allows (the Rayleigh-Ritz update of X, P, AX, AP
+//     together with the next residual R = AX - X Theta and its column norms);
+//   - the preconditioner applies of eq. 11 (diagonal and 64x64 blocks).
+#include "hsym_internal.h"
+#include "dense.h"
+
+namespace hsym {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Gram: G = [A_0 .. A_{na-1}]^T [B_0 .. B_{nb-1}], each block n x m (ld m).
+// Stage 1: every workgroup reduces a contiguous row range into a K1 x K2
+// partial with v_mfma_f64_16x16x4f64; stage 2 sums the partials in order.
+// ---------------------------------------------------------------------------
+// MFMA f64 16x16x4 operand layout: lane l holds A[i=l%16][k=l/16] and
+// B[k=l/16][j=l%16]; accumulator register v of lane l holds D[l/16 + 4v][l%16].
+template <int T1, int T2>
+__global__ __launch_bounds__(256) void k_gram_partial(GramArgs g, double *__restrict__ part, int64_t rows_per_wg) {
+    __shared__ double red[4][T1 * 16][T2 * 16 + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = g.m;
+    const int K1 = g.na * m, K2 = g.nb * m;
+    const int li = lane & 15, lk = lane >> 4;
+    // column this lane feeds for every 16-column tile
+    const double *pa[T1];
+    const double *pb[T2];
+    int ca[T1], cb[T2];
+#pragma unroll
+    for (int t = 0; t < T1; t++) {
+        int c = 16 * t + li;
+        ca[t] = c < K1;
+        int blk = c < K1 ? c / m : 0, col = c < K1 ? c % m : 0;
+        pa[t] = g.a[blk] + col;
+    }
+#pragma unroll
+    for (int t = 0; t < T2; t++) {
+        int c = 16 * t + li;
+        cb[t] = c < K2;
+        int blk = c < K2 ? c / m : 0, col = c < K2 ? c % m : 0;
+        pb[t] = g.b[blk] + col;
+    }
+    double4_t acc[T1][T2];
+#pragma unroll
+    for (int i = 0; i < T1; i++)
+#pragma unroll
+        for (int j = 0; j < T2; j++) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
+    int64_t r_end = r_begin + rows_per_wg;
+    if (r_end > g.n) r_end = g.n;
+    for (int64_t r0 = r_begin + 4 * wave; r0 < r_end; r0 += 16) {
+        const int64_t r = r0 + lk;
+        const bool ok = r < r_end;
+        double av[T1], bv[T2];
+#pragma unroll
+        for (int t = 0; t < T1; t++) av[t] = (ok && ca[t]) ? pa[t][r * m] : 0.0;
+#pragma unroll
+        for (int t = 0; t < T2; t++) bv[t] = (ok && cb[t]) ? pb[t][r * m] : 0.0;
+#pragma unroll
+        for (int i = 0; i < T1; i++)
+#pragma unroll
+            for (int j = 0; j < T2; j++)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < T1; i++)
+#pragma unroll
+        for (int j = 0; j < T2; j++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) red[wave][16 * i + lk + 4 * v][16 * j + li] = acc[i][j][v];
+    __syncthreads();
+    double *out = part + (int64_t)blockIdx.x * K1 * K2;
+    for (int e = tid; e < K1 * K2; e += 256) {
+        int i = e / K2, j = e - (e / K2) * K2;
+        out[e] = red[0][i][j] + red[1][i][j] + red[2][i][j] + red[3][i][j];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gram_final(const double *__restrict__ part, int nparts, int kk,
+                                                    double *__restrict__ out) {
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < kk; e += gridDim.x * 256) {
+        double s = 0.0;
+        for (int p = 0; p < nparts; p++) s += part[(int64_t)p * kk + e];
+        out[e] = s;
+    }
+}
+
+int gram_parts(int64_t n) {
+    int64_t p = (n + 1023) / 1024;
+    if (p > 1024) p = 1024;
+    if (p < 1) p = 1;
+    return (int)p;
+}
+
+size_t gram_scratch_bytes(int64_t n, int K1, int K2) { return (size_t)gram_parts(n) * K1 * K2 * sizeof(double); }
+
+template <int T1, int T2>
+static void gram_launch_t(const GramArgs &g, double *part, int parts, int64_t rpw, hipStream_t s) {
+    hipLaunchKernelGGL((k_gram_partial<T1, T2>), dim3(parts), dim3(256), 0, s, g, part, rpw);
+}
+
+void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s) {
+    const int K1 = g.na * g.m, K2 = g.nb * g.m;
+    const int T1 = (K1 + 15) / 16, T2 = (K2 + 15) / 16;
+    const int parts = gram_parts(g.n);
+    int64_t rpw = (g.n + parts - 1) / parts;
+    rpw = (rpw + 3) / 4 * 4;
+#define GL(a, b) if (T1 == a && T2 == b) { gram_launch_t<a, b>(g, scratch, parts, rpw, s); } else
+    GL(1, 1) GL(1, 2) GL(1, 3) GL(2, 1) GL(2, 2) GL(2, 3) GL(3, 1) GL(3, 2) GL(3, 3)
+        fail(HSYM_E_UNSUPPORTED, "gram shape");
+#undef GL
+    HIPCHK(hipGetLastError());
+    const int kk = K1 * K2;
+    hipLaunchKernelGGL(k_gram_final, dim3((kk + 255) / 256), dim3(256), 0, s, scratch, parts, kk, out);
+    HIPCHK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Linear combinations.  For every row r (one lane per row):
+//   out_o[r, :] = sum_i in_i[r, :] C[i*m:(i+1)*m, o*m:(o+1)*m]
+// for two sets sharing the coefficients (S = [X W P] and AS = [AX AW AP]).
+// Rows are read completely before they are written, so outputs may alias
+// inputs of the same row.  With theta != NULL the kernel also forms the
+// residual R = out_1_0 - out_0_0 diag(theta) of the new X (set 0, output 0)
+// and its product AX (set 1, output 0), writes it to `res` and accumulates the
+// squared column norms of R per workgroup.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(256) void k_lincomb(LincombArgs a) {
+    __shared__ double cs[48 * 32];
+    __shared__ double nred[256 / 64][M];
+    const int m = a.m, nin = a.nin, nout = a.nout;
+    const int kin = nin * m, kout = nout * m;
+    for (int e = threadIdx.x; e < kin * kout; e += 256) {
+        const int i = e / kout, j = e - (e / kout) * kout;
+        cs[e] = a.coef[i * a.ldc + j];
+    }
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double rn[M];
+#pragma unroll
+    for (int k = 0; k < M; k++) rn[k] = 0.0;
+    if (r < a.n) {
+        double xo[M];   // first output of set 0 (kept for the residual)
+        for (int set = 0; set < a.nsets; set++) {
+            double o[2][M];
+#pragma unroll
+            for (int q = 0; q < 2; q++)
+#pragma unroll
+                for (int k = 0; k < M; k++) o[q][k] = 0.0;
+            for (int i = 0; i < nin; i++) {
+                const double *src = a.in[set * 3 + i] + r * m;
+                double v[M];
+#pragma unroll
+                for (int k = 0; k < M; k++) v[k] = k < m ? src[k] : 0.0;
+#pragma unroll
+                for (int k = 0; k < M; k++) {
+                    if (k >= m) break;
+                    const double *crow = cs + (i * m + k) * kout;
+#pragma unroll
+                    for (int q = 0; q < 2; q++) {
+                        if (q >= nout) break;
+#pragma unroll
+                        for (int j = 0; j < M; j++) o[q][j] = fma(v[k], crow[q * m + j], o[q][j]);
+                    }
+                }
+            }
+            for (int q = 0; q < nout; q++) {
+                double *dst = a.out[set * 2 + q] + r * m;
+#pragma unroll
+                for (int j = 0; j < M; j++)
+                    if (j < m) dst[j] = o[q][j];
+            }
+            if (set == 0) {
+#pragma unroll
+                for (int j = 0; j < M; j++) xo[j] = o[0][j];
+            } else if (a.theta) {
+                double *rr = a.res + r * m;
+#pragma unroll
+                for (int j = 0; j < M; j++) {
+                    if (j < m) {
+                        double v = o[0][j] - xo[j] * a.theta[j];
+                        rr[j] = v;
+                        rn[j] = v * v;
+                    }
+                }
+            }
+        }
+    }
+    if (a.theta) {
+        // deterministic workgroup reduction of the squared norms
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int j = 0; j < M; j++) {
+            double v = rn[j];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) nred[wave][j] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < m) {
+            double s = 0.0;
+            for (int w = 0; w < 4; w++) s += nred[w][threadIdx.x];
+            a.norm_part[(int64_t)blockIdx.x * m + threadIdx.x] = s;
+        }
+    }
+}
+
+void lincomb(const LincombArgs &a, hipStream_t s) {
+    if (a.nin * a.m > 48 || a.nout * a.m > 32 || a.nout > 2 || a.nin > 3)
+        fail(HSYM_E_UNSUPPORTED, "lincomb shape");
+    unsigned grid = (unsigned)((a.n + 255) / 256);
+    if (a.m <= 8) hipLaunchKernelGGL(k_lincomb<8>, dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_lincomb<16>, dim3(grid), dim3(256), 0, s, a);
+    HIPCHK(hipGetLastError());
+}
+
+int64_t lincomb_norm_parts(int64_t n) { return (n + 255) / 256; }
+
+// sum of per-workgroup partial column sums (fixed order)
+__global__ void k_colsum_final(const double *__restrict__ part, int64_t nparts, int m, double *__restrict__ out) {
+    const int j = threadIdx.x;
+    if (j >= m) return;
+    double s = 0.0;
+    for (int64_t p = 0; p < nparts; p++) s += part[p * m + j];
+    out[j] = s;
+}
+
+void colsum_final(const double *part, int64_t nparts, int m, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, part, nparts, m, out);
+    HIPCHK(hipGetLastError());
+}
+
+// R = AX - X diag(theta) with squared column norms per workgroup
+template <int M>
+__global__ __launch_bounds__(256) void k_residual(const double *__restrict__ X, const double *__restrict__ AX,
+                                                  const double *__restrict__ theta, double *__restrict__ R,
+                                                  double *__restrict__ norm_part, int64_t n, int m) {
+    __shared__ double nred[4][M];
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double rn[M];
+#pragma unroll
+    for (int j = 0; j < M; j++) rn[j] = 0.0;
+    if (r < n) {
+#pragma unroll
+        for (int j = 0; j < M; j++) {
+            if (j < m) {
+                double v = AX[r * m + j] - X[r * m + j] * theta[j];
+                R[r * m + j] = v;
+                rn[j] = v * v;
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < M; j++) {
+        double v = rn[j];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) nred[wave][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < m) {
+        double s = 0.0;
+        for (int w = 0; w < 4; w++) s += nred[w][threadIdx.x];
+        norm_part[(int64_t)blockIdx.x * m + threadIdx.x] = s;
+    }
+}
+
+void residual(const double *X, const double *AX, const double *theta, double *R, double *norm_part, int64_t n,
+              int m, hipStream_t s) {
+    unsigned grid = (unsigned)((n + 255) / 256);
+    if (m <= 8) hipLaunchKernelGGL(k_residual<8>, dim3(grid), dim3(256), 0, s, X, AX, theta, R, norm_part, n, m);
+    else hipLaunchKernelGGL(k_residual<16>, dim3(grid), dim3(256), 0, s, X, AX, theta, R, norm_part, n, m);
+    HIPCHK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioners (eq. 11): T_j = Htilde - mu_j I, solved directly.
+// The shifted denominators are kept at least delta away from zero.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double guard_den(double d, double delta) {
+    return fabs(d) >= delta ? d : (d >= 0.0 ? delta : -delta);
+}
+
+__global__ __launch_bounds__(256) void k_precond_jacobi(double *__restrict__ W, const double *__restrict__ diag,
+                                                        const double *__restrict__ mu, double delta, int64_t n,
+                                                        int m) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * m) return;
+    const int64_t r = e / m;
+    const int j = (int)(e - r * m);
+    W[e] = W[e] / guard_den(diag[r] - mu[j], delta);
+}
+
+// One workgroup per 64-row chunk: W_b = Q diag(1/g(lambda - mu_j)) Q^T R_b.
+__global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W, const double *__restrict__ Q,
+                                                         const double *__restrict__ lam,
+                                                         const double *__restrict__ mu, double delta, int64_t n,
+                                                         int m) {
+    __shared__ double qs[64][65];
+    __shared__ double rs[64][17];
+    __shared__ double ts[64][17];
+    const int64_t b = blockIdx.x;
+    const int64_t r0 = b * 64;
+    const int rows = (int)((n - r0) < 64 ? (n - r0) : 64);
+    const double *Qb = Q + b * 64 * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) qs[e >> 6][e & 63] = Qb[e];
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+        int i = e >> 4, j = e & 15;
+        rs[i][j] = (i < rows && j < m) ? W[(r0 + i) * m + j] : 0.0;
+    }
+    __syncthreads();
+    // T = Q^T R, scaled row-wise by 1/g(lambda_i - mu_j)
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+        int i = e >> 4, j = e & 15;
+        double s = 0.0;
+        if (j < m) {
+            for (int k = 0; k < 64; k++) s = fma(qs[k][i], rs[k][j], s);
+            s = s / guard_den(lam[b * 64 + i] - mu[j], delta);
+        }
+        ts[i][j] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+        int i = e >> 4, j = e & 15;
+        if (i < rows && j < m) {
+            double s = 0.0;
+            for (int k = 0; k < 64; k++) s = fma(qs[i][k], ts[k][j], s);
+            W[(r0 + i) * m + j] = s;
+        }
+    }
+}
+
+void precond_apply(hsym_matrix *H, int kind, double *W, const double *mu, double delta, int m, hipStream_t s) {
+    const int64_t n = H->n;
+    if (kind == HSYM_PRECOND_JACOBI) {
+        unsigned grid = (unsigned)((n * m + 255) / 256);
+        hipLaunchKernelGGL(k_precond_jacobi, dim3(grid), dim3(256), 0, s, W, H->diag64, mu, delta, n, m);
+    } else if (kind == HSYM_PRECOND_BLOCK64) {
+        hipLaunchKernelGGL(k_precond_block64, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, W, H->pre_q,
+                           H->pre_lam, mu, delta, n, m);
+    }
+    HIPCHK(hipGetLastError());
+}
+
+// fp64 -> fp32 copy of a block (mixed-precision SpMM input)
+__global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, int64_t cnt) {
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < cnt) y[e] = (float)x[e];
+}
+
+// --- counter-based Gaussian generator (same definition as the input generator) ---
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ double unif(uint64_t key, uint64_t a, uint64_t b) {
+    const uint64_t G = 0x9E3779B97F4A7C15ULL;
+    uint64_t ctr = (a << 32) | (b & 0xffffffffULL);
+    return (double)(mix64(key + (ctr + 1ULL) * G) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+__global__ void k_gauss(double *__restrict__ V, int64_t n, int m, int64_t ld, uint64_t key, int mask) {
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * m) return;
+    int64_t i = e / m;
+    int j = (int)(e - i * m);
+    if (!((mask >> j) & 1)) return;
+    double u1 = unif(key, (uint64_t)i, 2 * (uint64_t)j), u2 = unif(key, (uint64_t)i, 2 * (uint64_t)j + 1);
+    V[i * ld + j] = sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586476925286766559 * u2);
+}
+
+void gauss_fill(double *V, int64_t n, int m, int64_t ld, uint64_t seed, uint64_t purpose, int mask,
+                hipStream_t s) {
+    const uint64_t G = 0x9E3779B97F4A7C15ULL;
+    auto hmix = [](uint64_t z) {
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        return z ^ (z >> 31);
+    };
+    uint64_t key = hmix(hmix(seed + G) ^ (purpose * G));
+    hipLaunchKernelGGL(k_gauss, dim3((unsigned)((n * m + 255) / 256)), dim3(256), 0, s, V, n, m, ld, key, mask);
+    HIPCHK(hipGetLastError());
+}
+
+// --- sign convention of returned eigenvectors ---
+struct AbsMax { double a; double v; int64_t r; };
+
+__global__ __launch_bounds__(256) void k_absmax_part(const double *__restrict__ X, int m, int nev, int64_t n,
+                                                     int64_t rows_per, AbsMax *__restrict__ part) {
+    __shared__ AbsMax red[256];
+    for (int j = 0; j < nev; j++) {
+        AbsMax best = {-1.0, 0.0, 0};
+        int64_t r0 = (int64_t)blockIdx.x * rows_per, r1 = r0 + rows_per < n ? r0 + rows_per : n;
+        for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+            double v = X[r * m + j], a = fabs(v);
+            if (a > best.a) { best.a = a; best.v = v; best.r = r; }
+        }
+        red[threadIdx.x] = best;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (threadIdx.x < off) {
+                AbsMax o = red[threadIdx.x + off], c = red[threadIdx.x];
+                if (o.a > c.a || (o.a == c.a && o.r < c.r)) red[threadIdx.x] = o;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nev + j] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sign_copy(const double *__restrict__ X, int m, int nev, int64_t n,
+                                                   const AbsMax *__restrict__ part, int nparts,
+                                                   double *__restrict__ out) {
+    __shared__ double sg[16];
+    if (threadIdx.x < nev) {
+        AbsMax b = {-1.0, 0.0, 0};
+        for (int p = 0; p < nparts; p++) {
+            AbsMax o = part[(int64_t)p * nev + threadIdx.x];
+            if (o.a > b.a || (o.a == b.a && o.r < b.r)) b = o;
+        }
+        sg[threadIdx.x] = b.v < 0 ? -1.0 : 1.0;
+    }
+    __syncthreads();
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * nev) return;
+    int64_t r = e / nev;
+    int j = (int)(e - r * nev);
+    out[e] = sg[j] * X[r * m + j];
+}
+
+static int absmax_parts(int64_t n) {
+    int64_t p = (n + 4095) / 4096;
+    return (int)(p > 1024 ? 1024 : (p < 1 ? 1 : p));
+}
+
+size_t sign_fix_scratch_bytes(int64_t n, int m) { return (size_t)absmax_parts(n) * m * sizeof(AbsMax); }
+
+void sign_fix_copy(const double *X, int m, int nev, int64_t n, double *evecs, double *scratch, hipStream_t s) {
+    int parts = absmax_parts(n);
+    int64_t rows_per = (n + parts - 1) / parts;
+    hipLaunchKernelGGL(k_absmax_part, dim3(parts), dim3(256), 0, s, X, m, nev, n, rows_per, (AbsMax *)scratch);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_sign_copy, dim3((unsigned)((n * nev + 255) / 256)), dim3(256), 0, s, X, m, nev, n,
+                       (const AbsMax *)scratch, parts, evecs);
+    HIPCHK(hipGetLastError());
+}
+
+void to_f32(const double *x, float *y, int64_t cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, x, y, cnt);
+    HIPCHK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos helpers: V is k x n (one basis vector per row, contiguous).
+// h = V^T w (one workgroup per basis vector), then w -= V^T h.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_dots(const double *__restrict__ V, int64_t ldv, const double *__restrict__ w,
+                                              int64_t n, double *__restrict__ h) {
+    __shared__ double red[4];
+    const double *v = V + (int64_t)blockIdx.x * ldv;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s = fma(v[i], w[i], s);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) h[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_sub_vh(const double *__restrict__ V, int64_t ldv, const double *__restrict__ h,
+                                                int k, double *__restrict__ w, int64_t n) {
+    __shared__ double hs[1024];
+    for (int i = threadIdx.x; i < k && i < 1024; i += 256) hs[i] = h[i];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int j = 0; j < k; j++) s = fma(hs[j], V[(int64_t)j * ldv + i], s);
+    w[i] -= s;
+}
+
+void dots(const double *V, int64_t ldv, int k, const double *w, int64_t n, double *h, hipStream_t s) {
+    hipLaunchKernelGGL(k_dots, dim3(k), dim3(256), 0, s, V, ldv, w, n, h);
+    HIPCHK(hipGetLastError());
+}
+
+void sub_vh(const double *V, int64_t ldv, const double *h, int k, double *w, int64_t n, hipStream_t s) {
+    for (int j0 = 0; j0 < k; j0 += 1024) {
+        int kk = k - j0 < 1024 ? k - j0 : 1024;
+        hipLaunchKernelGGL(k_sub_vh, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, V + (int64_t)j0 * ldv, ldv,
+                           h + j0, kk, w, n);
+        HIPCHK(hipGetLastError());
+    }
+}
+
+// w = (w - a*v1 - b*v0) ; used by the three-term recurrence
+__global__ void k_axpby2(double *__restrict__ w, const double *__restrict__ v1, const double *__restrict__ ab,
+                         const double *__restrict__ v0, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double r = w[i] - ab[0] * v1[i];
+    if (v0) r -= ab[1] * v0[i];
+    w[i] = r;
+}
+
+void axpby2(double *w, const double *v1, const double *ab, const double *v0, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, v1, ab, v0, n);
+    HIPCHK(hipGetLastError());
+}
+
+__global__ void k_scale_to(const double *__restrict__ w, const double *__restrict__ nrm2, double *__restrict__ v,
+                           int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    v[i] = w[i] / sqrt(nrm2[0]);
+}
+
+void scale_to(const double *w, const double *nrm2, double *v, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_to, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, nrm2, v, n);
+    HIPCHK(hipGetLastError());
+}
+
+}  // namespace hsym

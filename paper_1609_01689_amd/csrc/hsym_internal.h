@@ -1,0 +1,138 @@
+// Internal declarations shared by the host code and the HIP kernels of libhsym.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../include/hsym.h"
+
+namespace hsym {
+
+// ---------------------------------------------------------------------------
+// Errors: every entry point converts failures into a status and a message.
+// ---------------------------------------------------------------------------
+struct Error {
+    int status;
+    std::string msg;
+};
+void set_error(const std::string &msg);
+[[noreturn]] void fail(int status, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+#define HIPCHK(x) ::hsym::check_hip((x), #x)
+
+// ---------------------------------------------------------------------------
+// Tile format of the stored upper triangle (compressed sparse blocks,
+// Section 4.2).  Rows are cut into panels of R rows and columns into chunks of
+// C columns (R a multiple of C).  The strictly-upper entries of one panel that
+// fall into one chunk form a tile.  Inside a tile the rows that own entries are
+// sorted by their entry count (descending) and cut into slices of up to 64
+// rows; slice entries are stored lane-interleaved: entry e of slice row l sits
+// at base + e*nrows + l, short rows padded with zero values.  A tile is "own"
+// when its chunk lies inside the panel (its transposed half lands in the
+// panel's own rows) and "external" otherwise; every external tile owns one
+// partial-sum slot of C rows.
+// ---------------------------------------------------------------------------
+struct TileDesc {
+    int64_t slice_begin;   // first slice (global index)
+    int32_t nslices;
+    int32_t chunk;         // global chunk index g: columns [g*C, g*C+C)
+    int32_t slot;          // partial slot, -1 for an own tile
+    int32_t pad;
+};
+
+struct SliceDesc {
+    int64_t base;          // first entry (global index)
+    int32_t len;           // entries per row after padding
+    int32_t nrows;         // rows in the slice (<= 64): lane stride of the entries
+};
+
+struct TileFormat {
+    int R = 0, C = 0;
+    int64_t n = 0, npanels = 0, nchunks = 0;
+    int64_t ntiles = 0, nslices = 0, nentries = 0, nslots = 0;
+    // host copies (freed after upload unless kept for tests)
+    std::vector<int64_t> panel_tile_ptr;     // npanels+1
+    std::vector<TileDesc> tiles;
+    std::vector<SliceDesc> slices;
+    std::vector<uint16_t> slice_rows;        // nslices*64, panel-local rows
+    std::vector<uint32_t> cols;              // chunk-local column of every entry
+    std::vector<double> vals64;
+    std::vector<float> vals32;
+    std::vector<int64_t> red_ptr;            // per output chunk: contributing slots
+    std::vector<int32_t> red_slot;
+    std::vector<int32_t> red_chunks;         // chunks with at least one contribution
+};
+
+struct DeviceTiles {
+    int R = 0, C = 0, SR = 64;   // SR: rows per slice
+    int64_t npanels = 0, nchunks = 0, ntiles = 0, nslices = 0, nentries = 0, nslots = 0;
+    int64_t nred_chunks = 0;
+    int64_t *panel_tile_ptr = nullptr;
+    TileDesc *tiles = nullptr;
+    SliceDesc *slices = nullptr;
+    uint16_t *slice_rows = nullptr;
+    uint32_t *cols = nullptr;
+    void *vals = nullptr;
+    int64_t *red_ptr = nullptr;
+    int32_t *red_slot = nullptr;
+    int32_t *red_chunks = nullptr;
+    int64_t bytes = 0;
+};
+
+}  // namespace hsym
+
+struct hsym_matrix {
+    int64_t n = 0;
+    int64_t nnz = 0;              // stored entries incl. diagonal
+    int storage = HSYM_FP64;
+    double norm1 = 0.0;
+    int device = 0;
+    // diagonal in both precisions
+    double *diag64 = nullptr;
+    float *diag32 = nullptr;
+    // tile format of the strictly-upper part (one panel geometry per handle)
+    hsym::DeviceTiles tiles;
+    int geom_m = 16;              // block width the geometry is sized for
+    std::vector<double> d_host;   // diagonal, fp64, host copy
+    std::vector<double> colsum;   // absolute column sums (streaming create)
+    // block-64 preconditioner: per 64-row chunk Q (64x64, row-major) and lambda
+    double *pre_q = nullptr;
+    double *pre_lam = nullptr;
+    int64_t pre_nchunks = 0;
+    int64_t bytes = 0;
+    // streaming create
+    int64_t stream_rows = 0;
+    int flags = 0;
+    bool ready = false;
+    hipStream_t stream = nullptr;
+};
+
+namespace hsym {
+
+// geometry: (R, C) for a block width and storage precision
+void geometry_for(int storage, int m, int *R, int *C, int *SR);
+size_t spmm_lds_bytes(int storage, int m, int R, int C);
+void free_tiles(DeviceTiles *dt);
+
+// device scratch (per call)
+struct Scratch {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~Scratch();
+    void *get(size_t b);
+};
+
+// SpMM launch: X (n x m, ld ldx) -> Y; XIN/YOUT precision flags
+enum { T_F64 = 0, T_F32 = 1 };
+void spmm_launch(hsym_matrix *H, int m, const void *X, int xprec, int64_t ldx, void *Y, int yprec,
+                 int64_t ldy, void *partials, hipStream_t s);
+size_t spmm_partial_bytes(hsym_matrix *H, int m);
+
+// small parallel-for on host threads
+void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)> &fn);
+int host_threads();
+
+}  // namespace hsym

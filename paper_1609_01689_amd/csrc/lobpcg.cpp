@@ -1,0 +1,488 @@
+// LOBPCG driver (Algorithm 1 with the preconditioning of Section 3.2 and the
+// rules of Section 4.3).  Host code enqueues the kernels on one stream and
+// reads back one small status block per iteration (residual norms, Ritz
+// values) to run the convergence test and the shift rules.
+//
+// Basis handling: S = [X W P] is kept orthonormal.  W is orthonormalised
+// against [X P] and itself by Cholesky-QR passes driven by Gram matrices;
+// after Rayleigh-Ritz the new P is built in coefficient space as an
+// orthonormal basis of the W,P-components of the new X made orthogonal to the
+// new X, so span{X_new, P_new} equals span{X_new, (I - X X^T) X_new} of step 10
+// and no full-size pass is needed to orthogonalise P.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "dense.h"
+
+namespace hsym {
+
+struct Status {
+    double norms[HSYM_MAX_BLOCK];     // squared column norms of R
+    double theta[HSYM_MAX_BLOCK];
+    double evals_all[48];
+    int flags[8];                     // 0: orth deficiency mask, 1: rr sweeps
+};
+
+// Orthonormalise V (n x m) against the kb orthonormal blocks B and itself
+// (Cholesky-QR with column scaling, then a second Cholesky-QR pass).  Columns
+// that turn out numerically inside span(B, V) are replaced with seeded
+// Gaussian columns and the procedure is repeated.  Returns the number of
+// replaced columns.  Synchronises the stream once per attempt.
+int orthonormalize_block(int64_t n, int m, double *V, const double *const *B, int kb, uint64_t seed,
+                         OrthWork &w, hipStream_t s) {
+    int replaced = 0;
+    for (int attempt = 0;; attempt++) {
+        HIPCHK(hipMemsetAsync(w.flag_d, 0, sizeof(int), s));
+        GramArgs g{};
+        for (int i = 0; i < kb; i++) g.a[i] = B[i];
+        g.a[kb] = V; g.b[0] = V; g.na = kb + 1; g.nb = 1; g.m = m; g.n = n;
+        gram(g, w.gbuf, w.gram_scr, s);
+        OrthArgs oa{w.gbuf, w.coef, w.flag_d, kb, m, 0};
+        small_orth(&oa, 1, s);
+        LincombArgs l{};
+        for (int i = 0; i < kb; i++) l.in[i] = B[i];
+        l.in[kb] = V; l.out[0] = V; l.coef = w.coef; l.ldc = m; l.nin = kb + 1; l.nout = 1; l.nsets = 1;
+        l.m = m; l.n = n;
+        lincomb(l, s);
+        gram(g, w.gbuf, w.gram_scr, s);
+        oa.stage = 1;
+        small_orth(&oa, 1, s);
+        HIPCHK(hipMemcpyAsync(w.flag_h, w.flag_d, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int flag = *w.flag_h;
+        if (flag) {
+            if (attempt >= 3) fail(HSYM_E_BREAKDOWN, "block stays rank deficient after 3 random repairs");
+            int mask = flag & ((1 << m) - 1);
+            replaced += __builtin_popcount((unsigned)mask);
+            gauss_fill(V, n, m, m, seed + (uint64_t)attempt, 10, mask, s);
+            continue;
+        }
+        lincomb(l, s);
+        GramArgs g2{};
+        g2.a[0] = V; g2.b[0] = V; g2.na = g2.nb = 1; g2.m = m; g2.n = n;
+        gram(g2, w.gbuf, w.gram_scr, s);
+        OrthArgs o2{w.gbuf, w.coef, w.flag_d, 0, m, 2};
+        small_orth(&o2, 1, s);
+        LincombArgs l2{};
+        l2.in[0] = V; l2.out[0] = V; l2.coef = w.coef; l2.ldc = m; l2.nin = 1; l2.nout = 1; l2.nsets = 1;
+        l2.m = m; l2.n = n;
+        lincomb(l2, s);
+        return replaced;
+    }
+}
+
+struct Lobpcg {
+    hsym_matrix *H = nullptr;
+    hipStream_t s = nullptr;
+    int64_t n = 0;
+    int m = 0, nev = 0, precond = HSYM_PRECOND_NONE;
+    double tol = 0.0;
+    lobpcg_opts o{};
+    // device blocks
+    double *X = nullptr, *AX = nullptr, *W = nullptr, *AW = nullptr, *P = nullptr, *AP = nullptr;
+    double *spmm_part = nullptr, *gram_scr = nullptr, *gbuf = nullptr, *coef = nullptr, *rrcoef = nullptr;
+    double *mu = nullptr, *norm_part = nullptr;
+    Status *st_d = nullptr;
+    Status *st_h = nullptr;      // pinned
+    double *mu_h = nullptr;      // pinned
+    int64_t bytes = 0;
+    // iteration state
+    int it = 0;
+    bool have_p = false;
+    bool done = false;
+    int status = HSYM_NOT_CONVERGED;
+    lobpcg_report rep{};
+    std::chrono::steady_clock::time_point t0;
+    std::vector<void *> allocs;
+
+    template <class T>
+    T *dalloc(size_t count) {
+        void *p = nullptr;
+        size_t b = std::max<size_t>(count * sizeof(T), 256);
+        if (hipMalloc(&p, b) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(HSYM_E_OUT_OF_MEMORY, "solver allocation of " + std::to_string(b) + " bytes");
+        }
+        allocs.push_back(p);
+        bytes += (int64_t)b;
+        return (T *)p;
+    }
+
+    ~Lobpcg() {
+        for (void *p : allocs) (void)hipFree(p);
+        if (st_h) (void)hipHostFree(st_h);
+        if (mu_h) (void)hipHostFree(mu_h);
+    }
+
+    void setup(hsym_matrix *H_, int nev_, int m_, double tol_, const double *X0, int pc, const lobpcg_opts *opts,
+               hipStream_t s_) {
+        H = H_; s = s_; n = H->n; m = m_; nev = nev_; tol = tol_; precond = pc;
+        lobpcg_opts_default(&o);
+        if (opts) o = *opts;
+        if (o.maxit < 1) o.maxit = 1000;
+        if (o.check_every < 1) o.check_every = 1;
+        if (pc == HSYM_PRECOND_BLOCK64 && !H->pre_q)
+            fail(HSYM_E_INVALID_ARG, "block64 preconditioner needs a handle created with HSYM_BUILD_BLOCK64");
+        size_t nm = (size_t)n * m;
+        X = dalloc<double>(nm); AX = dalloc<double>(nm); W = dalloc<double>(nm);
+        AW = dalloc<double>(nm); P = dalloc<double>(nm); AP = dalloc<double>(nm);
+        spmm_part = (double *)dalloc<char>(spmm_partial_bytes(H, m));
+        gram_scr = (double *)dalloc<char>(std::max(gram_scratch_bytes(n, 3 * m, 3 * m),
+                                                   sign_fix_scratch_bytes(n, m)));
+        gbuf = dalloc<double>(48 * 48);
+        coef = dalloc<double>(48 * 32);
+        rrcoef = dalloc<double>(48 * 32);
+        mu = dalloc<double>(HSYM_MAX_BLOCK);
+        norm_part = dalloc<double>((size_t)lincomb_norm_parts(n) * m);
+        st_d = dalloc<Status>(1);
+        HIPCHK(hipHostMalloc((void **)&st_h, sizeof(Status), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&mu_h, sizeof(double) * HSYM_MAX_BLOCK, hipHostMallocDefault));
+        memset(&rep, 0, sizeof(rep));
+        t0 = std::chrono::steady_clock::now();
+        // start block: X0 or a seeded Gaussian block
+        if (X0) HIPCHK(hipMemcpyAsync(X, X0, sizeof(double) * nm, hipMemcpyDeviceToDevice, s));
+        else gauss_fill(X, n, m, m, o.seed, 8, -1, s);
+        // step 1: orthonormalise X0, Rayleigh quotient, Ritz vectors of span(X0)
+        OrthWork ow{gbuf, coef, gram_scr, &st_d->flags[0], &st_h->flags[0]};
+        rep.w_replaced += orthonormalize_block(n, m, X, nullptr, 0, o.seed * 1000003ULL + 5ULL, ow, s);
+        spmm(X, AX);
+        GramArgs g{};
+        g.a[0] = X; g.b[0] = AX; g.na = g.nb = 1; g.m = m; g.n = n;
+        gram(g, gbuf, gram_scr, s);
+        rayleigh_ritz(1);
+        LincombArgs u{};
+        u.in[0] = X; u.in[3] = AX; u.out[0] = X; u.out[2] = AX;
+        u.coef = rrcoef; u.ldc = 2 * m; u.nin = 1; u.nout = 1; u.nsets = 2; u.m = m; u.n = n;
+        u.theta = st_d->theta; u.res = W; u.norm_part = norm_part;
+        lincomb(u, s);
+        colsum_final(norm_part, lincomb_norm_parts(n), m, st_d->norms, s);
+        have_p = false;
+        it = 0;
+    }
+
+    void spmm(const double *V, double *AV) {
+        spmm_launch(H, m, V, T_F64, m, AV, T_F64, m, spmm_part, s);
+        rep.spmm_calls++;
+    }
+
+    void rayleigh_ritz(int nblk) {
+        RRArgs r{};
+        r.gram = gbuf; r.coef = rrcoef; r.theta = st_d->theta; r.evals_all = st_d->evals_all;
+        r.flag = &st_d->flags[1]; r.nblk = nblk; r.m = m;
+        small_rr(&r, 1, s);
+    }
+
+    // ---- phases of one iteration (the two host synchronisation points) ----
+    // post_status: enqueue the copy of the status block (norms, Ritz values)
+    void post_status() { HIPCHK(hipMemcpyAsync(st_h, st_d, sizeof(Status), hipMemcpyDeviceToHost, s)); }
+
+    // Section 4.3 rules 1-4 on the host; returns false when W = R
+    bool shifts(const double *rho, const double *rnorm, const double *theta) {
+        if (precond == HSYM_PRECOND_NONE || it <= o.no_precond_iters || rho[0] > o.near) return false;
+        bool far = false;
+        for (int j = 0; j < m; j++) {
+            if (!far && rho[j] > o.near) far = true;
+            mu_h[j] = far ? mu_h[j - 1] : theta[j] - 2.0 * rnorm[j];
+        }
+        return true;
+    }
+
+    // evaluate (status copy complete): convergence test of step 5; true when done
+    double rho_[HSYM_MAX_BLOCK], rnorm_[HSYM_MAX_BLOCK];
+    int evaluated = -1;
+    bool evaluate() {
+        if (done) return true;
+        if (evaluated == it) return false;
+        evaluated = it;
+        const double normH = H->norm1;
+        double mx = 0.0;
+        for (int j = 0; j < m; j++) {
+            double v = st_h->norms[j];
+            if (!std::isfinite(v) || !std::isfinite(st_h->theta[j])) fail(HSYM_E_NUMERIC, "NaN/Inf in residual");
+            rnorm_[j] = std::sqrt(v);
+            rho_[j] = rnorm_[j] / normH;
+            if (j < nev) mx = std::max(mx, rho_[j]);
+        }
+        if (st_h->flags[1] < 0) fail(HSYM_E_NUMERIC, "Rayleigh-Ritz eigensolver did not converge");
+        if (o.keep_history && rep.history_len < HSYM_MAX_HISTORY) rep.history[rep.history_len++] = mx;
+        for (int j = 0; j < m; j++) { rep.theta[j] = st_h->theta[j]; rep.resnorm[j] = rho_[j]; }
+        rep.iters = it;
+        if (mx <= tol) { status = HSYM_OK; rep.converged = 1; done = true; }
+        else if (it >= o.maxit) { status = HSYM_NOT_CONVERGED; done = true; }
+        return done;
+    }
+
+    // advance_a: step 6 (W = T^-1 R) and the first Cholesky-QR stage of step 7,
+    // ending with the copy of the rank-deficiency flag
+    void orth_part1() {
+        const double *B[2] = {X, P};
+        const int kb = have_p ? 2 : 1;
+        HIPCHK(hipMemsetAsync(&st_d->flags[0], 0, sizeof(int), s));
+        GramArgs g{};
+        for (int i = 0; i < kb; i++) g.a[i] = B[i];
+        g.a[kb] = W; g.b[0] = W; g.na = kb + 1; g.nb = 1; g.m = m; g.n = n;
+        gram(g, gbuf, gram_scr, s);
+        OrthArgs oa{gbuf, coef, &st_d->flags[0], kb, m, 0};
+        small_orth(&oa, 1, s);
+        orth_lc = LincombArgs{};
+        for (int i = 0; i < kb; i++) orth_lc.in[i] = B[i];
+        orth_lc.in[kb] = W; orth_lc.out[0] = W; orth_lc.coef = coef; orth_lc.ldc = m; orth_lc.nin = kb + 1;
+        orth_lc.nout = 1; orth_lc.nsets = 1; orth_lc.m = m; orth_lc.n = n;
+        lincomb(orth_lc, s);
+        gram(g, gbuf, gram_scr, s);
+        oa.stage = 1;
+        small_orth(&oa, 1, s);
+        HIPCHK(hipMemcpyAsync(&st_h->flags[0], &st_d->flags[0], sizeof(int), hipMemcpyDeviceToHost, s));
+    }
+    LincombArgs orth_lc{};
+    int orth_attempt = 0;
+
+    void advance_a() {
+        it++;
+        if (shifts(rho_, rnorm_, st_h->theta)) {
+            HIPCHK(hipMemcpyAsync(mu, mu_h, sizeof(double) * m, hipMemcpyHostToDevice, s));
+            precond_apply(H, precond, W, mu, o.guard * H->norm1, m, s);
+        }
+        orth_attempt = 0;
+        orth_part1();
+    }
+
+    // advance_b (flag copy complete): repair a deficient W, or finish step 7,
+    // apply H (the one SpMM of the iteration), Rayleigh-Ritz (steps 7-9), the
+    // update of X, P, AX, AP (step 10) fused with the next residual, and post
+    // the status copy.  Returns false when the flag copy must be awaited again.
+    bool advance_b() {
+        int flag = st_h->flags[0];
+        if (flag) {
+            if (orth_attempt >= 3) fail(HSYM_E_BREAKDOWN, "block stays rank deficient after 3 random repairs");
+            int mask = flag & ((1 << m) - 1);
+            rep.w_replaced += __builtin_popcount((unsigned)mask);
+            gauss_fill(W, n, m, m, o.seed * 1000003ULL + (uint64_t)it * 101ULL + 7ULL + (uint64_t)orth_attempt, 10,
+                       mask, s);
+            orth_attempt++;
+            orth_part1();
+            return false;
+        }
+        lincomb(orth_lc, s);
+        GramArgs g2{};
+        g2.a[0] = W; g2.b[0] = W; g2.na = g2.nb = 1; g2.m = m; g2.n = n;
+        gram(g2, gbuf, gram_scr, s);
+        OrthArgs o2{gbuf, coef, &st_d->flags[0], 0, m, 2};
+        small_orth(&o2, 1, s);
+        LincombArgs l2{};
+        l2.in[0] = W; l2.out[0] = W; l2.coef = coef; l2.ldc = m; l2.nin = 1; l2.nout = 1; l2.nsets = 1;
+        l2.m = m; l2.n = n;
+        lincomb(l2, s);
+        spmm(W, AW);
+        const int nblk = have_p ? 3 : 2;
+        GramArgs g{};
+        g.a[0] = X; g.a[1] = W; g.a[2] = P; g.b[0] = AX; g.b[1] = AW; g.b[2] = AP;
+        g.na = g.nb = nblk; g.m = m; g.n = n;
+        gram(g, gbuf, gram_scr, s);
+        rayleigh_ritz(nblk);
+        LincombArgs u{};
+        u.in[0] = X; u.in[1] = W; u.in[2] = P; u.in[3] = AX; u.in[4] = AW; u.in[5] = AP;
+        u.out[0] = X; u.out[1] = P; u.out[2] = AX; u.out[3] = AP;
+        u.coef = rrcoef; u.ldc = 2 * m; u.nin = nblk; u.nout = 2; u.nsets = 2; u.m = m; u.n = n;
+        u.theta = st_d->theta; u.res = W; u.norm_part = norm_part;
+        lincomb(u, s);
+        colsum_final(norm_part, lincomb_norm_parts(n), m, st_d->norms, s);
+        have_p = true;
+        post_status();
+        return true;
+    }
+
+    void sync() { HIPCHK(hipStreamSynchronize(s)); }
+
+    // whole solve on one stream
+    void run() {
+        post_status();
+        for (;;) {
+            sync();
+            if (evaluate()) return;
+            advance_a();
+            do { sync(); } while (!advance_b());
+        }
+    }
+
+    void finish(double *evals, double *evecs) {
+        for (int j = 0; j < nev; j++) evals[j] = st_h->theta[j];
+        if (evecs) sign_fix_copy(X, m, nev, n, evecs, gram_scr, s);
+        HIPCHK(hipStreamSynchronize(s));
+        rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+}  // namespace hsym
+
+using namespace hsym;
+
+extern "C" {
+
+void lobpcg_opts_default(lobpcg_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->maxit = 1000;
+    o->seed = 0;
+    o->check_every = 1;
+    o->no_precond_iters = 3;
+    o->near = 0.1;
+    o->guard = 1e-4;
+    o->keep_history = 1;
+}
+
+static void check_solve_args(hsym_t H, int nev, int m, double tol) {
+    if (!H || !H->ready) fail(HSYM_E_INVALID_ARG, "invalid handle");
+    if (nev < 1 || m < nev || m > HSYM_MAX_BLOCK) fail(HSYM_E_INVALID_ARG, "need 1 <= nev <= block_width <= 16");
+    if (3 * (int64_t)m > H->n) fail(HSYM_E_INVALID_ARG, "need 3*block_width <= n");
+    if (!(tol > 0.0)) fail(HSYM_E_INVALID_ARG, "tol must be > 0");
+}
+
+int lobpcg_solve(hsym_t H, int nev, int block_width, double tol, const double *X0, int precond,
+                 const lobpcg_opts *opts, double *evals, double *evecs, lobpcg_report *rep, void *stream) {
+    try {
+        check_solve_args(H, nev, block_width, tol);
+        if (!evals) fail(HSYM_E_INVALID_ARG, "NULL evals");
+        if (precond < HSYM_PRECOND_NONE || precond > HSYM_PRECOND_BLOCK64) fail(HSYM_E_INVALID_ARG, "bad precond");
+        Lobpcg L;
+        L.setup(H, nev, block_width, tol, X0, precond, opts, (hipStream_t)stream);
+        L.run();
+        L.finish(evals, evecs);
+        if (rep) *rep = L.rep;
+        set_error("");
+        return L.status;
+    } catch (Error &e) {
+        set_error(e.msg);
+        return e.status;
+    } catch (std::bad_alloc &) {
+        set_error("host allocation failed");
+        return HSYM_E_OUT_OF_MEMORY;
+    }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// context/step API
+// ---------------------------------------------------------------------------
+struct lobpcg_ctx {
+    hsym::Lobpcg L;
+    hipStream_t own = nullptr;
+};
+
+template <class F>
+static int ctx_guard(F &&f) {
+    try {
+        int st = f();
+        set_error("");
+        return st;
+    } catch (Error &e) {
+        set_error(e.msg);
+        return e.status;
+    } catch (std::bad_alloc &) {
+        set_error("host allocation failed");
+        return HSYM_E_OUT_OF_MEMORY;
+    }
+}
+
+extern "C" {
+
+int lobpcg_ctx_create(lobpcg_ctx_t *out, hsym_t H, int nev, int block_width, double tol, const double *X0,
+                      int precond, const lobpcg_opts *opts, void *stream) {
+    if (out) *out = nullptr;
+    return ctx_guard([&] {
+        if (!out) fail(HSYM_E_INVALID_ARG, "NULL context pointer");
+        check_solve_args(H, nev, block_width, tol);
+        if (precond < HSYM_PRECOND_NONE || precond > HSYM_PRECOND_BLOCK64) fail(HSYM_E_INVALID_ARG, "bad precond");
+        lobpcg_ctx *c = new lobpcg_ctx();
+        try {
+            hipStream_t s = (hipStream_t)stream;
+            if (!s) {
+                HIPCHK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+                s = c->own;
+            }
+            c->L.setup(H, nev, block_width, tol, X0, precond, opts, s);
+            c->L.post_status();
+        } catch (...) {
+            if (c->own) (void)hipStreamDestroy(c->own);
+            delete c;
+            throw;
+        }
+        *out = c;
+        return (int)HSYM_OK;
+    });
+}
+
+// Advance every context by up to `iters` iterations.  Contexts on different
+// streams overlap on the device: each phase is enqueued for all contexts
+// before any of them is waited on.
+int lobpcg_ctx_step(lobpcg_ctx_t *ctxs, int count, int iters) {
+    return ctx_guard([&] {
+        if ((!ctxs && count) || count < 0 || iters < 0) fail(HSYM_E_INVALID_ARG, "bad step arguments");
+        for (int i = 0; i < count; i++) if (!ctxs[i]) fail(HSYM_E_INVALID_ARG, "NULL context");
+        std::vector<Lobpcg *> act, pend;
+        for (int k = 0; k < iters; k++) {
+            act.clear();
+            for (int i = 0; i < count; i++) {
+                Lobpcg &L = ctxs[i]->L;
+                if (L.done) continue;
+                L.sync();
+                if (!L.evaluate()) act.push_back(&L);
+            }
+            if (act.empty()) break;
+            for (Lobpcg *L : act) L->advance_a();
+            pend = act;
+            while (!pend.empty()) {
+                std::vector<Lobpcg *> next;
+                for (Lobpcg *L : pend) {
+                    L->sync();
+                    if (!L->advance_b()) next.push_back(L);
+                }
+                pend.swap(next);
+            }
+        }
+        return (int)HSYM_OK;
+    });
+}
+
+int lobpcg_ctx_status(lobpcg_ctx_t c, int *done, double *evals, lobpcg_report *rep) {
+    return ctx_guard([&] {
+        if (!c) fail(HSYM_E_INVALID_ARG, "NULL context");
+        Lobpcg &L = c->L;
+        L.sync();
+        bool d = L.evaluate();
+        if (done) *done = d ? 1 : 0;
+        if (evals) for (int j = 0; j < L.nev; j++) evals[j] = L.st_h->theta[j];
+        if (rep) {
+            L.rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - L.t0).count();
+            *rep = L.rep;
+        }
+        return d ? L.status : (int)HSYM_NOT_CONVERGED;
+    });
+}
+
+int lobpcg_ctx_evecs(lobpcg_ctx_t c, double *evecs) {
+    return ctx_guard([&] {
+        if (!c || !evecs) fail(HSYM_E_INVALID_ARG, "NULL argument");
+        Lobpcg &L = c->L;
+        sign_fix_copy(L.X, L.m, L.nev, L.n, evecs, L.gram_scr, L.s);
+        L.sync();
+        return (int)HSYM_OK;
+    });
+}
+
+int64_t lobpcg_ctx_device_bytes(lobpcg_ctx_t c) { return c ? c->L.bytes : 0; }
+
+int lobpcg_ctx_destroy(lobpcg_ctx_t c) {
+    return ctx_guard([&] {
+        if (!c) fail(HSYM_E_INVALID_ARG, "NULL context");
+        (void)hipStreamSynchronize(c->L.s);
+        hipStream_t own = c->own;
+        delete c;
+        if (own) (void)hipStreamDestroy(own);
+        return (int)HSYM_OK;
+    });
+}
+
+}  // extern "C"

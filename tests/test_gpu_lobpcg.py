@@ -1,0 +1,146 @@
+"""GPU parity of lobpcg_solve (through the C ABI) against the CPU oracle,
+LAPACK and closed-form spectra."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import hsymgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1609_01689_amd as hs  # noqa: E402
+
+
+def dense_of(A):
+    U = sp.csr_matrix((A.values.astype(np.float64), A.colind, A.rowptr), shape=(A.n, A.n))
+    return (U + U.T - sp.diags(U.diagonal())).toarray()
+
+
+def solve(A, nev, m, tol, precond="jacobi", storage=hs.HSYM_FP64, X0=None, seed=0, maxit=1000):
+    dev = torch.device("cuda:0")
+    M = hs.Matrix(A, storage=storage, block64=(precond == "block64"), geom_m=m)
+    X0d = None if X0 is None else torch.from_numpy(np.ascontiguousarray(X0)).to(dev)
+    ev = torch.zeros((A.n, nev), dtype=torch.float64, device=dev)
+    opts = hs.default_lobpcg_opts(seed=seed, maxit=maxit)
+    st, evals, rep = hs.lobpcg_solve(M.h, nev, m, tol, X0=X0d, precond=precond, opts=opts, evecs=ev)
+    torch.cuda.synchronize()
+    vecs = ev.cpu().numpy()
+    norm1 = M.info["norm1"]
+    M.close()
+    print("n=%d m=%d nev=%d %s storage=%d: status %d iters %d spmm %d time %.3fs" %
+          (A.n, m, nev, precond, storage, st, rep.iters, rep.spmm_calls, rep.seconds), flush=True)
+    return st, evals, vecs, rep, norm1
+
+
+def certify(A, evals, vecs, tol_rel):
+    """fp64 residuals of the returned pairs with the oracle's SpMM."""
+    H = oracle.SymMatrix.from_csr(A)
+    R = H.spmm(vecs) - vecs * evals[None, :]
+    rho = np.linalg.norm(R, axis=0) / H.norm1()
+    nrm = np.linalg.norm(vecs, axis=0)
+    assert np.allclose(nrm, 1.0, atol=1e-10)
+    # sign convention: largest-magnitude entry positive
+    idx = np.argmax(np.abs(vecs), axis=0)
+    assert np.all(vecs[idx, np.arange(vecs.shape[1])] > 0)
+    assert np.max(rho) <= tol_rel, rho
+    return rho
+
+
+@pytest.fixture(scope="module")
+def c1():
+    A = hsymgen.config("C1")
+    return A, np.linalg.eigvalsh(dense_of(A))
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi", "block64"])
+def test_lobpcg_c1_fp64(c1, precond):
+    A, lam = c1
+    X0 = hsymgen.gauss_block(1, A.n, 8)
+    st, evals, vecs, rep, _ = solve(A, 5, 8, 1e-8, precond=precond, X0=X0)
+    assert st == hs.HSYM_OK and rep.converged
+    assert np.max(np.abs(evals - lam[:5]) / np.abs(lam[:5])) <= 1e-8
+    certify(A, evals, vecs, 1.5e-8)
+    # iteration count of the oracle on the same start block, same algorithm
+    ref = oracle.lobpcg(oracle.SymMatrix.from_csr(A), 5, 8, 1e-8, X0=X0, precond=precond)
+    print("oracle iters", ref.iters, "gpu iters", rep.iters)
+    assert abs(rep.iters - ref.iters) <= max(3, 0.2 * ref.iters)
+
+
+def test_lobpcg_c1_seeded_start(c1):
+    A, lam = c1
+    st, evals, vecs, rep, _ = solve(A, 5, 8, 1e-8, seed=17)
+    assert st == hs.HSYM_OK
+    assert np.max(np.abs(evals - lam[:5]) / np.abs(lam[:5])) <= 1e-8
+
+
+def test_lobpcg_c1_mixed(c1):
+    A, lam = c1
+    st, evals, vecs, rep, _ = solve(A, 5, 8, 1e-6, storage=hs.HSYM_FP32, X0=hsymgen.gauss_block(1, A.n, 8))
+    assert st == hs.HSYM_OK
+    err = np.abs(evals - lam[:5]) / np.abs(lam[:5])
+    print("mixed C1 eigenvalue errors", err)
+    assert np.max(err) <= 1e-6
+
+
+def test_lobpcg_blockdiag_union():
+    g = hsymgen.Generator(6000, 40, 21, variant="blockdiag")
+    A = g.matrix()
+    st_, _ = g.blocks()
+    D = dense_of(A)
+    spec = np.sort(np.concatenate([np.linalg.eigvalsh(D[a:b, a:b]) for a, b in zip(st_[:-1], st_[1:])]))
+    st, evals, vecs, rep, _ = solve(A, 4, 8, 1e-9)
+    assert st == hs.HSYM_OK
+    assert np.max(np.abs(evals - spec[:4]) / np.abs(spec[:4])) < 1e-8
+
+
+def test_lobpcg_laplacian():
+    n = 400
+    A = hsymgen.laplacian_1d(n)
+    st, evals, vecs, rep, _ = solve(A, 3, 6, 1e-9, precond="none", X0=hsymgen.gauss_block(2, n, 6), maxit=3000)
+    lam = 2 - 2 * np.cos(np.arange(1, 4) * np.pi / (n + 1))
+    assert st == hs.HSYM_OK
+    assert np.max(np.abs(evals - lam) / lam) < 1e-8
+
+
+@pytest.mark.parametrize("m,nev", [(16, 10), (12, 8), (5, 3)])
+def test_lobpcg_block_widths(m, nev):
+    A = hsymgen.generate(20000, 100, 5)
+    H = oracle.SymMatrix.from_csr(A)
+    X0 = hsymgen.gauss_block(3, A.n, m)
+    st, evals, vecs, rep, _ = solve(A, nev, m, 1e-8, X0=X0)
+    assert st == hs.HSYM_OK
+    ref = oracle.lobpcg(H, nev, m, 1e-8, X0=X0, precond="jacobi")
+    assert ref.converged
+    assert np.max(np.abs(evals - ref.evals) / np.abs(ref.evals)) <= 1e-8
+    certify(A, evals, vecs, 1.5e-8)
+
+
+def test_lobpcg_not_converged_status(c1):
+    A, _ = c1
+    st, evals, vecs, rep, _ = solve(A, 5, 8, 1e-12, maxit=4, X0=hsymgen.gauss_block(1, A.n, 8))
+    assert st == hs.HSYM_NOT_CONVERGED and rep.iters == 4
+    assert np.all(np.isfinite(evals))
+
+
+def test_lobpcg_rank_deficient_start(c1):
+    """Duplicate columns in X0: the start block is repaired with random columns."""
+    A, lam = c1
+    X0 = hsymgen.gauss_block(1, A.n, 8)
+    X0[:, 5] = X0[:, 2]
+    st, evals, vecs, rep, _ = solve(A, 5, 8, 1e-8, X0=X0)
+    assert st == hs.HSYM_OK and rep.w_replaced >= 1
+    assert np.max(np.abs(evals - lam[:5]) / np.abs(lam[:5])) <= 1e-8
+
+
+def test_lobpcg_invalid_args(c1):
+    A, _ = c1
+    M = hs.Matrix(A)
+    for nev, m, tol in [(9, 8, 1e-8), (0, 8, 1e-8), (5, 17, 1e-8), (5, 8, 0.0)]:
+        with pytest.raises(hs.HsymError) as e:
+            hs.lobpcg_solve(M.h, nev, m, tol)
+        assert e.value.status == hs.HSYM_E_INVALID_ARG
+    with pytest.raises(hs.HsymError):
+        hs.lobpcg_solve(M.h, 5, 8, 1e-8, precond="block64")   # factors not built
+    M.close()
