@@ -1,0 +1,223 @@
+"""Benchmark of the LOBPCG hot path on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): seeded
+synthetic CI-shaped symmetric matrix, n = 500,000, about 300 nonzeros per full
+row (75.5M stored upper entries), fp64 values, block width m, nev = 8,
+tol = 1e-8, Jacobi preconditioner.  One step = one complete LOBPCG solve to
+tolerance (every step of the hot path: SpMM, residual, preconditioner,
+Cholesky-QR, Rayleigh-Ritz, update), with the matrix already resident in HBM.
+
+Also measured, outside the timed steps: the symmetric SpMM alone (HIP events
+on the stream it runs on; roofline against 8 TB/s), the Lanczos baseline on
+the same GPU, the mixed-precision (fp32 SpMM) solve, and the CPU oracle on a
+bounded sample (cpu_baseline).
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "LOBPCG s-to-tol + SpMM HBM GB/s (% peak), mixed vs FP64; solves/s, p99"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmm_algorithmic_bytes(nnz_stored, n, m, val_bytes, x_bytes, y_bytes):
+    """What the product must move: every stored entry once (value + int32
+    column index), X read once, Y written once."""
+    return nnz_stored * (val_bytes + 4) + n * m * x_bytes + n * m * y_bytes
+
+
+def time_spmm(hs, torch, M, m, reps, dtype):
+    n = M.n
+    X = torch.randn((n, m), dtype=dtype, device="cuda:0")
+    Y = torch.empty_like(X)
+    fn = hs.spmm_sym if dtype == torch.float64 else hs.spmm_sym_f32
+    for _ in range(3):
+        fn(M.h, X, Y)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn(M.h, X, Y, stream=s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(A, m, nev, tol, gpu_iters, budget_s):
+    """The oracle (as it stands) on the same matrix: LOBPCG iterations are run
+    for about budget_s seconds and the per-iteration time is scaled to the
+    iteration count of a full solve."""
+    import oracle
+    import hsymgen
+    H = oracle.SymMatrix.from_csr(A)
+    H.full()
+    H.norm1()
+    X0 = hsymgen.gauss_block(1, A.n, m)
+    t = time.perf_counter()
+    its = 2
+    r = oracle.lobpcg(H, nev, m, tol, X0=X0, precond="jacobi", maxit=its, keep_history=False)
+    dt = time.perf_counter() - t
+    per_it = dt / max(1, r.iters)
+    more = int(max(0, budget_s - dt) / max(per_it, 1e-9))
+    if more > 0:
+        its = min(its + more, gpu_iters)
+        t = time.perf_counter()
+        r = oracle.lobpcg(H, nev, m, tol, X0=X0, precond="jacobi", maxit=its, keep_history=False)
+        dt = time.perf_counter() - t
+        per_it = dt / max(1, r.iters)
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    solve_s = per_it * gpu_iters
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": "%d oracle LOBPCG iterations (%.1f s, %.3f s/iteration) on the same n=%d matrix, "
+                      "scaled to the %d iterations of a full solve" % (r.iters, dt, per_it, A.n, gpu_iters)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--m", type=int, default=16, help="block width (8 or 16)")
+    ap.add_argument("--spmm-reps", type=int, default=50)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the multi-GPU path is not part of this build "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import hsymgen
+    import paper_1609_01689_amd as hs
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    m, nev, tol = args.m, 8, 1e-8
+    cfg = hsymgen.CONFIGS["C2"]
+    t = time.perf_counter()
+    A = hsymgen.config("C2")
+    log("generated C2: n=%d nnz_stored=%d in %.1fs" % (A.n, A.nnz, time.perf_counter() - t))
+    t = time.perf_counter()
+    M = hs.Matrix(A, storage=hs.HSYM_FP64, geom_m=m)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t
+    info = M.info
+    log("handle built in %.2fs: %s" % (build_s, info))
+
+    # --- SpMM roofline (dominant kernel) ---
+    spmm_ms = time_spmm(hs, torch, M, m, args.spmm_reps, torch.float64)
+    alg = spmm_algorithmic_bytes(A.nnz, A.n, m, 8, 8, 8)
+    achieved = alg / (spmm_ms * 1e-3) / 1e9
+    log("spmm fp64 m=%d: %.3f ms, %.1f GB/s (%.1f%% of 8 TB/s)" % (m, spmm_ms, achieved, 100 * achieved / HBM_PEAK_GBS))
+
+    # --- timed LOBPCG solves ---
+    opts = hs.default_lobpcg_opts(seed=1, keep_history=0)
+    for _ in range(args.warmup):
+        hs.lobpcg_solve(M.h, nev, m, tol, precond="jacobi", opts=opts)
+    torch.cuda.synchronize()
+    times, iters = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        st, ev, rep = hs.lobpcg_solve(M.h, nev, m, tol, precond="jacobi", opts=opts)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        iters.append(rep.iters)
+        assert st == hs.HSYM_OK, "solve did not converge"
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ms_per_step = 1000.0 * total / args.steps
+    log("lobpcg fp64: %.1f ms/solve, iterations %s, rr sweeps max %d, evals %s" % (ms_per_step, iters, rep.rr_sweeps_max, ev))
+
+    extras = {}
+    if not args.no_extras:
+        # Lanczos baseline on the same GPU and matrix
+        t = time.perf_counter()
+        stl, evl, repl = hs.lanczos_solve(M.h, nev, tol, seed=1)
+        torch.cuda.synchronize()
+        lan_s = time.perf_counter() - t
+        extras["lanczos"] = {"s_to_tol": lan_s, "iters": repl.iters, "status": stl,
+                             "max_rel_eval_diff_vs_lobpcg": float(np.max(np.abs(evl - ev) / np.abs(ev)))}
+        # SpMV (m=1) bandwidth of the Lanczos baseline
+        M1 = hs.Matrix(A, storage=hs.HSYM_FP64, geom_m=1)
+        spmv_ms = time_spmm(hs, torch, M1, 1, args.spmm_reps, torch.float64)
+        M1.close()
+        extras["spmv_fp64"] = {"ms": spmv_ms, "GB/s": spmm_algorithmic_bytes(A.nnz, A.n, 1, 8, 8, 8) / spmv_ms / 1e6}
+        # mixed precision: fp32 storage and SpMM, fp64 everything else
+        Mf = hs.Matrix(A, storage=hs.HSYM_FP32, geom_m=m)
+        spmm32_ms = time_spmm(hs, torch, Mf, m, args.spmm_reps, torch.float32)
+        alg32 = spmm_algorithmic_bytes(A.nnz, A.n, m, 4, 4, 4)
+        for tol_m in (1e-6,):
+            t = time.perf_counter()
+            stm, evm, repm = hs.lobpcg_solve(Mf.h, nev, m, tol_m, precond="jacobi", opts=opts)
+            torch.cuda.synchronize()
+            mixed_s = time.perf_counter() - t
+            t = time.perf_counter()
+            st6, ev6, rep6 = hs.lobpcg_solve(M.h, nev, m, tol_m, precond="jacobi", opts=opts)
+            torch.cuda.synchronize()
+            fp64_s = time.perf_counter() - t
+            extras["mixed_vs_fp64_tol1e-6"] = {
+                "mixed_s_to_tol": mixed_s, "mixed_iters": repm.iters, "fp64_s_to_tol": fp64_s,
+                "fp64_iters": rep6.iters, "speedup": fp64_s / mixed_s,
+                "max_rel_eval_err_mixed_vs_fp64": float(np.max(np.abs(evm - ev6) / np.abs(ev6)))}
+        extras["spmm_fp32"] = {"ms": spmm32_ms, "GB/s": alg32 / spmm32_ms / 1e6,
+                               "frac": alg32 / spmm32_ms / 1e6 / HBM_PEAK_GBS}
+        Mf.close()
+        log("extras: %s" % json.dumps(extras))
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(A, m, nev, tol, int(np.median(iters)), args.cpu_budget)
+        log("cpu baseline: %s" % cpu)
+
+    times.sort()
+    out = {
+        "metric": METRIC,
+        "value": args.steps / total,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "GEN n=%d N=%d seed=%d (CI-shaped upper CSR, fp64), LOBPCG nev=%d m=%d "
+                               "tol=%g jacobi" % (cfg["n"], cfg["N"], cfg["seed"], nev, m, tol),
+                   "n": A.n, "nnz_stored": A.nnz, "block_width": m, "nev": nev, "tol": tol},
+        "s_to_tol": ms_per_step / 1000.0,
+        "p50_s": times[len(times) // 2],
+        "p99_s": times[min(len(times) - 1, int(0.99 * len(times)))],
+        "iters": int(np.median(iters)),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "spmm_sym fp64 m=%d (k_spmm_panel + k_spmm_reduce), %.4f ms/call" % (m, spmm_ms),
+                     "algorithmic_bytes": alg},
+        "cpu_baseline": cpu,
+        "build_s": build_s,
+        "extras": extras,
+    }
+    M.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

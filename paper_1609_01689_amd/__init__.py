@@ -19,7 +19,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhsym.so")
+LIB_PATH = os.environ.get("HSYM_LIB", os.path.join(_HERE, "libhsym.so"))
 
 HSYM_OK, HSYM_NOT_CONVERGED = 0, 1
 HSYM_E_INVALID_ARG, HSYM_E_OUT_OF_MEMORY, HSYM_E_DEVICE = -1, -2, -3
@@ -60,7 +60,8 @@ class lobpcg_report(ctypes.Structure):
                 ("p_dropped", ctypes.c_int), ("w_replaced", ctypes.c_int),
                 ("theta", ctypes.c_double * MAX_BLOCK), ("resnorm", ctypes.c_double * MAX_BLOCK),
                 ("seconds", ctypes.c_double), ("phase_ms", ctypes.c_double * 8),
-                ("history_len", ctypes.c_int), ("history", ctypes.c_double * MAX_HISTORY)]
+                ("history_len", ctypes.c_int), ("history", ctypes.c_double * MAX_HISTORY),
+                ("rr_sweeps_max", ctypes.c_int)]
 
 
 class lanczos_opts(ctypes.Structure):

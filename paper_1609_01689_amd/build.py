@@ -13,14 +13,14 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-OUT = os.path.join(HERE, "libhsym.so")
-BUILD = os.path.join(os.path.dirname(HERE), "_build")
+OUT = os.environ.get("HSYM_LIB_OUT", os.path.join(HERE, "libhsym.so"))
+BUILD = os.environ.get("HSYM_BUILD_DIR", os.path.join(os.path.dirname(HERE), "_build"))
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-I" + CSRC]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics"]
+          "-munsafe-fp-atomics"] + os.environ.get("HSYM_EXTRA_DEVICE_FLAGS", "").split()
 
 
 def _compile(src: str) -> str:

@@ -53,35 +53,32 @@ void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, in
     if (errst) fail(errst, err);
 }
 
-void geometry_for(int storage, int m, int *R, int *C, int *SR) {
-    // Panel rows R and chunk columns C: the largest R for which the panel
-    // accumulator plus the staged X chunk and the transposed accumulator of one
-    // chunk fit the 160 KB LDS of a gfx950 CU at this block width.
-    const int budget = 160 * 1024;
-    int c = 256;
-    int r = 4096;
-    while (r > c && spmm_lds_bytes(storage, m, r, c) > (size_t)budget) r /= 2;
-    if (spmm_lds_bytes(storage, m, r, c) > (size_t)budget) { c = 128; r = 128; }
+void geometry_for(int storage, int m, int64_t n, int *R, int *C, int *G) {
+    // Panel rows R and chunk columns C = R/4: the largest power-of-two R for
+    // which the panel accumulator, the panel's X rows, the staged X chunk and
+    // the chunk's transposed accumulator fit the 160 KB LDS of a gfx950 CU.
+    const size_t budget = 160 * 1024;
+    int r = 65536;
+    while (r > 64 && spmm_lds_bytes(storage, m, r, r / 4) > budget) r /= 2;
+    // keep at least one panel per CU (256 CUs) when n allows
+    while (r > 256 && (int64_t)r * 256 > n) r /= 2;
+    int c = r / 4;
     const char *er = getenv("HSYM_PANEL_ROWS");
     const char *ec = getenv("HSYM_CHUNK_COLS");
     if (er) r = atoi(er);
     if (ec) c = atoi(ec);
     *R = r;
     *C = c;
-    // wide blocks split a slice row over two lanes, so a slice holds 32 rows
-    *SR = (m > 8) ? 32 : 64;
-    const char *es = getenv("HSYM_SLICE_ROWS");
-    if (es) *SR = atoi(es);
+    // one segment per lane group of the 1024-thread workgroup at this width
+    *G = 1024 / spmm_lanes_per_entry(storage, m);
 }
 
 // ---------------------------------------------------------------------------
 // one panel
 // ---------------------------------------------------------------------------
 struct PanelOut {
-    std::vector<TileDesc> tiles;      // slice_begin relative to the panel
-    std::vector<SliceDesc> slices;    // base relative to the panel
-    std::vector<uint16_t> rows;       // 64 per slice
-    std::vector<uint32_t> cols;
+    std::vector<TileDesc> tiles;      // base relative to the panel
+    std::vector<uint32_t> idx;
     std::vector<double> v64;
     std::vector<float> v32;
     std::vector<int32_t> ext_chunks;  // chunk of every external tile, in order
@@ -121,7 +118,7 @@ static void block64_factor(int64_t c0, int sz, int64_t slab_row0, const int64_t 
 
 // Rows [r0, r1) of the matrix; rp/ci/v index the caller's slab whose first row
 // is slab_row0.  dg receives the diagonal of the panel rows.
-static void build_panel(int64_t n, int64_t r0, int64_t r1, int R, int C, int SR, int storage, bool b64,
+static void build_panel(int64_t n, int64_t r0, int64_t r1, int R, int C, int G, int storage, bool b64,
                         int64_t slab_row0, const int64_t *rp, const int32_t *ci,
                         const double *vin64, const float *vin32, double *dg, PanelOut &out) {
     const int nr = (int)(r1 - r0);
@@ -166,51 +163,43 @@ static void build_panel(int64_t n, int64_t r0, int64_t r1, int R, int C, int SR,
             block64_factor(c0, (int)std::min<int64_t>(64, r1 - c0), slab_row0, rp, ci, vin64, vin32, out);
 
     const int64_t gmin = r0 / C, gmax = maxcol / C;
-    std::vector<int> cnt(nr), order(nr);
+    std::vector<int> cnt(nr);
     for (int64_t g = gmin; g <= gmax; g++) {
         const int64_t cend = (g + 1) * (int64_t)C;
-        int nact = 0;
+        int64_t nnz = 0;
+        int last = -1;
         for (int i = 0; i < nr; i++) {
             int64_t p = cur[i];
             while (p < end[i] && ci[p] < cend) p++;
             cnt[i] = (int)(p - cur[i]);
-            if (cnt[i]) order[nact++] = i;
+            nnz += cnt[i];
+            if (cnt[i]) last = i;
         }
-        if (!nact) continue;
-        std::stable_sort(order.begin(), order.begin() + nact,
-                         [&](int a, int b) { return cnt[a] > cnt[b]; });
+        if (!nnz) continue;
         TileDesc td;
-        td.slice_begin = (int64_t)out.slices.size();
-        td.nslices = (nact + SR - 1) / SR;
+        td.base = (int64_t)out.idx.size();
+        td.len = (int32_t)((nnz + G - 1) / G);
         td.chunk = (int32_t)g;
         bool ext = g * (int64_t)C >= r0 + R;
         td.slot = ext ? (int32_t)out.ext_chunks.size() : -1;
         td.pad = 0;
         if (ext) out.ext_chunks.push_back((int32_t)g);
         out.tiles.push_back(td);
-        for (int s = 0; s < td.nslices; s++) {
-            int f = s * SR, nrs = std::min(SR, nact - f);
-            SliceDesc sd;
-            sd.base = (int64_t)out.cols.size();
-            sd.len = cnt[order[f]];
-            sd.nrows = nrs;
-            out.slices.push_back(sd);
-            size_t sz = (size_t)sd.len * nrs;
-            out.cols.resize(out.cols.size() + sz, 0u);
-            if (storage == HSYM_FP64) out.v64.resize(out.v64.size() + sz, 0.0);
-            else out.v32.resize(out.v32.size() + sz, 0.0f);
-            size_t rbase = out.rows.size();
-            out.rows.resize(rbase + 64, (uint16_t)0xFFFF);
-            for (int l = 0; l < nrs; l++) {
-                int i = order[f + l];
-                out.rows[rbase + l] = (uint16_t)i;
-                for (int e = 0; e < cnt[i]; e++) {
-                    int64_t p = cur[i] + e;
-                    size_t pos = (size_t)sd.base + (size_t)e * nrs + l;
-                    out.cols[pos] = (uint32_t)(ci[p] - g * (int64_t)C);
-                    if (storage == HSYM_FP64) out.v64[pos] = vin64 ? vin64[p] : (double)vin32[p];
-                    else out.v32[pos] = vin64 ? (float)vin64[p] : vin32[p];
-                }
+        const size_t sz = (size_t)td.len * G;
+        const size_t b0 = out.idx.size();
+        // padding: zero values on the last row (keeps a segment's row run unbroken)
+        out.idx.resize(b0 + sz, (uint32_t)last << 16);
+        if (storage == HSYM_FP64) out.v64.resize(b0 + sz, 0.0);
+        else out.v32.resize(b0 + sz, 0.0f);
+        int64_t logical = 0;
+        for (int i = 0; i < nr; i++) {
+            for (int e = 0; e < cnt[i]; e++, logical++) {
+                int64_t p = cur[i] + e;
+                const int64_t seg = logical / td.len, pos = logical - seg * td.len;
+                const size_t at = b0 + (size_t)pos * G + (size_t)seg;
+                out.idx[at] = ((uint32_t)i << 16) | (uint32_t)(ci[p] - g * (int64_t)C);
+                if (storage == HSYM_FP64) out.v64[at] = vin64 ? vin64[p] : (double)vin32[p];
+                else out.v32[at] = vin64 ? (float)vin64[p] : vin32[p];
             }
         }
         for (int i = 0; i < nr; i++) cur[i] += cnt[i];
@@ -246,7 +235,7 @@ struct DevVec {
 };
 
 struct Builder {
-    int R = 0, C = 0, SR = 64;
+    int R = 0, C = 0, G = 256;
     int storage = HSYM_FP64;
     bool b64 = false;
     DevVec<double> preq, prelam;
@@ -261,9 +250,7 @@ struct Builder {
     std::vector<float> carry_v32;
     // device arrays
     DevVec<TileDesc> tiles;
-    DevVec<SliceDesc> slices;
-    DevVec<uint16_t> rows;
-    DevVec<uint32_t> cols;
+    DevVec<uint32_t> idx;
     DevVec<double> v64;
     DevVec<float> v32;
     std::vector<int64_t> panel_tile_ptr{0};
@@ -271,10 +258,10 @@ struct Builder {
     std::vector<double> diag;          // n
     std::vector<double> abssum;        // n: row+column absolute sums
     double norm1 = 0.0;
-    int64_t nslices = 0, nentries = 0, ntiles = 0;
+    int64_t nentries = 0, ntiles = 0;
 
     void release() {
-        tiles.release(); slices.release(); rows.release(); cols.release(); v64.release(); v32.release();
+        tiles.release(); idx.release(); v64.release(); v32.release();
         preq.release(); prelam.release();
     }
 
@@ -289,14 +276,12 @@ struct Builder {
                 for (int64_t k = a; k < b; k++) {
                     int64_t p = b0 + k;
                     int64_t r0 = p * R, r1 = std::min(n, r0 + R);
-                    build_panel(n, r0, r1, R, C, SR, storage, b64, slab_row0, rp, ci, vin64, vin32,
+                    build_panel(n, r0, r1, R, C, G, storage, b64, slab_row0, rp, ci, vin64, vin32,
                                 diag.data() + r0, outs[(size_t)k]);
                 }
             });
             // concatenate in panel order
             std::vector<TileDesc> t;
-            std::vector<SliceDesc> s;
-            std::vector<uint16_t> r;
             std::vector<uint32_t> c;
             std::vector<double> d64;
             std::vector<float> d32;
@@ -304,17 +289,14 @@ struct Builder {
             for (int64_t k = 0; k < b1 - b0; k++) {
                 PanelOut &o = outs[(size_t)k];
                 int64_t r0 = (b0 + k) * R;
-                int64_t slice_off = nslices + (int64_t)s.size();
                 int64_t entry_off = nentries + (int64_t)c.size();
                 int32_t slot_off = (int32_t)slot_chunk.size();
                 for (auto td : o.tiles) {
-                    td.slice_begin += slice_off;
+                    td.base += entry_off;
                     if (td.slot >= 0) td.slot += slot_off;
                     t.push_back(td);
                 }
-                for (auto sd : o.slices) { sd.base += entry_off; s.push_back(sd); }
-                r.insert(r.end(), o.rows.begin(), o.rows.end());
-                c.insert(c.end(), o.cols.begin(), o.cols.end());
+                c.insert(c.end(), o.idx.begin(), o.idx.end());
                 d64.insert(d64.end(), o.v64.begin(), o.v64.end());
                 d32.insert(d32.end(), o.v32.begin(), o.v32.end());
                 for (int32_t g : o.ext_chunks) slot_chunk.push_back(g);
@@ -326,14 +308,11 @@ struct Builder {
                 PanelOut().tiles.swap(o.tiles);
             }
             tiles.append(t.data(), (int64_t)t.size());
-            slices.append(s.data(), (int64_t)s.size());
-            rows.append(r.data(), (int64_t)r.size());
-            cols.append(c.data(), (int64_t)c.size());
+            idx.append(c.data(), (int64_t)c.size());
             if (storage == HSYM_FP64) v64.append(d64.data(), (int64_t)d64.size());
             else v32.append(d32.data(), (int64_t)d32.size());
             if (b64) { preq.append(pq.data(), (int64_t)pq.size()); prelam.append(pl.data(), (int64_t)pl.size()); }
             ntiles += (int64_t)t.size();
-            nslices += (int64_t)s.size();
             nentries += (int64_t)c.size();
             npanels_done = b1;
         }
@@ -416,15 +395,15 @@ void builder_begin(hsym_matrix *H, int64_t nnz_hint) {
     b->n = H->n;
     b->storage = H->storage;
     b->b64 = (H->flags & HSYM_BUILD_BLOCK64) != 0;
-    geometry_for(H->storage, H->geom_m, &b->R, &b->C, &b->SR);
-    if (b->SR < 1 || b->SR > 64) fail(HSYM_E_INVALID_ARG, "slice rows must be in [1, 64]");
+    geometry_for(H->storage, H->geom_m, H->n, &b->R, &b->C, &b->G);
+    if (b->G < 1) fail(HSYM_E_INVALID_ARG, "bad segment count");
     if (b->R % b->C != 0 || b->C > 65536 || b->R > 65535)
         fail(HSYM_E_INVALID_ARG, "panel rows must be a multiple of chunk columns (<= 65535)");
     b->diag.assign((size_t)H->n, 0.0);
     b->abssum.assign((size_t)H->n, 0.0);
     if (nnz_hint > 0) {
         int64_t est = nnz_hint + nnz_hint / 8 + 4096;
-        b->cols.reserve(est);
+        b->idx.reserve(est);
         if (H->storage == HSYM_FP64) b->v64.reserve(est); else b->v32.reserve(est);
     }
     std::lock_guard<std::mutex> g(g_builders_mu);
@@ -455,18 +434,18 @@ void builder_finish(hsym_matrix *H) {
     if (b->next_row != H->n || b->carry_rp.size() != 1)
         fail(HSYM_E_INVALID_ARG, "streaming create finished before all n rows were appended");
     DeviceTiles &dt = H->tiles;
-    dt.R = b->R; dt.C = b->C; dt.SR = b->SR;
+    dt.R = b->R; dt.C = b->C; dt.G = b->G;
     dt.npanels = (H->n + b->R - 1) / b->R;
     dt.nchunks = (H->n + b->C - 1) / b->C;
-    dt.ntiles = b->ntiles; dt.nslices = b->nslices; dt.nentries = b->nentries;
+    dt.ntiles = b->ntiles; dt.nentries = b->nentries;
     dt.nslots = (int64_t)b->slot_chunk.size();
-    dt.tiles = b->tiles.p; dt.slices = b->slices.p; dt.slice_rows = b->rows.p; dt.cols = b->cols.p;
+    dt.tiles = b->tiles.p; dt.idx = b->idx.p;
     dt.vals = H->storage == HSYM_FP64 ? (void *)b->v64.p : (void *)b->v32.p;
-    b->tiles.p = nullptr; b->slices.p = nullptr; b->rows.p = nullptr; b->cols.p = nullptr;
+    b->tiles.p = nullptr; b->idx.p = nullptr;
     b->v64.p = nullptr; b->v32.p = nullptr;
     int vs = H->storage == HSYM_FP64 ? 8 : 4;
-    dt.bytes = b->tiles.cap * (int64_t)sizeof(TileDesc) + b->slices.cap * (int64_t)sizeof(SliceDesc) +
-               b->rows.cap * 2 + b->cols.cap * 4 + (H->storage == HSYM_FP64 ? b->v64.cap : b->v32.cap) * vs;
+    dt.bytes = b->tiles.cap * (int64_t)sizeof(TileDesc) + b->idx.cap * 4 +
+               (H->storage == HSYM_FP64 ? b->v64.cap : b->v32.cap) * vs;
     // panel pointers
     HIPCHK(hipMalloc(&dt.panel_tile_ptr, sizeof(int64_t) * b->panel_tile_ptr.size()));
     HIPCHK(hipMemcpy(dt.panel_tile_ptr, b->panel_tile_ptr.data(), sizeof(int64_t) * b->panel_tile_ptr.size(),
@@ -513,7 +492,7 @@ void builder_finish(hsym_matrix *H) {
 }
 
 void free_tiles(DeviceTiles *dt) {
-    void *ptrs[] = {dt->panel_tile_ptr, dt->tiles, dt->slices, dt->slice_rows, dt->cols, dt->vals,
+    void *ptrs[] = {dt->panel_tile_ptr, dt->tiles, dt->idx, dt->vals,
                     dt->red_ptr, dt->red_slot, dt->red_chunks};
     for (void *p : ptrs) if (p) (void)hipFree(p);
     *dt = DeviceTiles();

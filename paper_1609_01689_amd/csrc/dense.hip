@@ -81,13 +81,25 @@ __global__ __launch_bounds__(256) void k_gram_partial(GramArgs g, double *__rest
     }
 }
 
+// sum of the partial Gram matrices: 64 elements x 4 part-slices per
+// workgroup, combined in a fixed order (bitwise reproducible)
 __global__ __launch_bounds__(256) void k_gram_final(const double *__restrict__ part, int nparts, int kk,
                                                     double *__restrict__ out) {
-    for (int e = blockIdx.x * 256 + threadIdx.x; e < kk; e += gridDim.x * 256) {
-        double s = 0.0;
-        for (int p = 0; p < nparts; p++) s += part[(int64_t)p * kk + e];
-        out[e] = s;
+    __shared__ double red[4][64];
+    const int el = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + el;
+    double s0 = 0.0, s1 = 0.0;
+    if (e < kk) {
+        int p = sl;
+        for (; p + 4 < nparts; p += 8) {
+            s0 += part[(int64_t)p * kk + e];
+            s1 += part[(int64_t)(p + 4) * kk + e];
+        }
+        if (p < nparts) s0 += part[(int64_t)p * kk + e];
     }
+    red[sl][el] = s0 + s1;
+    __syncthreads();
+    if (sl == 0 && e < kk) out[e] = (red[0][el] + red[1][el]) + (red[2][el] + red[3][el]);
 }
 
 int gram_parts(int64_t n) {
@@ -116,7 +128,7 @@ void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s) {
 #undef GL
     HIPCHK(hipGetLastError());
     const int kk = K1 * K2;
-    hipLaunchKernelGGL(k_gram_final, dim3((kk + 255) / 256), dim3(256), 0, s, scratch, parts, kk, out);
+    hipLaunchKernelGGL(k_gram_final, dim3((kk + 63) / 64), dim3(256), 0, s, scratch, parts, kk, out);
     HIPCHK(hipGetLastError());
 }
 
@@ -130,108 +142,113 @@ void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s) {
 // and its product AX (set 1, output 0), writes it to `res` and accumulates the
 // squared column norms of R per workgroup.
 // ---------------------------------------------------------------------------
-template <int M>
+// One workgroup (4 waves) per tile of 64 rows.  The coefficient matrix and
+// the input rows of one set are staged in LDS (rows padded to 17 doubles so
+// the 16 rows an MFMA operand reads fall in distinct banks); each wave forms
+// 16 output rows x 16 columns per v_mfma_f64_16x16x4f64 chain.
 __global__ __launch_bounds__(256) void k_lincomb(LincombArgs a) {
-    __shared__ double cs[48 * 32];
-    __shared__ double nred[256 / 64][M];
+    __shared__ double cs[48][33];
+    __shared__ double ins[3][64][17];
+    __shared__ double nred[4][4][16];
     const int m = a.m, nin = a.nin, nout = a.nout;
     const int kin = nin * m, kout = nout * m;
-    for (int e = threadIdx.x; e < kin * kout; e += 256) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int rows = (int)((a.n - r0) < 64 ? (a.n - r0) : 64);
+    for (int e = tid; e < kin * kout; e += 256) {
         const int i = e / kout, j = e - (e / kout) * kout;
-        cs[e] = a.coef[i * a.ldc + j];
+        cs[i][j] = a.coef[i * a.ldc + j];
     }
-    __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double rn[M];
-#pragma unroll
-    for (int k = 0; k < M; k++) rn[k] = 0.0;
-    if (r < a.n) {
-        double xo[M];   // first output of set 0 (kept for the residual)
-        for (int set = 0; set < a.nsets; set++) {
-            double o[2][M];
-#pragma unroll
-            for (int q = 0; q < 2; q++)
-#pragma unroll
-                for (int k = 0; k < M; k++) o[q][k] = 0.0;
+    double4_t xkeep = (double4_t){0.0, 0.0, 0.0, 0.0};
+    double nrm = 0.0;
+    for (int set = 0; set < a.nsets; set++) {
+        __syncthreads();
+        for (int i = 0; i < nin; i++) {
+            const double *src = a.in[set * 3 + i] + r0 * m;
+            for (int e = tid; e < 64 * 16; e += 256) {
+                const int r = e >> 4, k = e & 15;
+                ins[i][r][k] = (r < rows && k < m) ? src[r * m + k] : 0.0;
+            }
+        }
+        __syncthreads();
+        for (int q = 0; q < nout; q++) {
+            double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
             for (int i = 0; i < nin; i++) {
-                const double *src = a.in[set * 3 + i] + r * m;
-                double v[M];
-#pragma unroll
-                for (int k = 0; k < M; k++) v[k] = k < m ? src[k] : 0.0;
-#pragma unroll
-                for (int k = 0; k < M; k++) {
-                    if (k >= m) break;
-                    const double *crow = cs + (i * m + k) * kout;
-#pragma unroll
-                    for (int q = 0; q < 2; q++) {
-                        if (q >= nout) break;
-#pragma unroll
-                        for (int j = 0; j < M; j++) o[q][j] = fma(v[k], crow[q * m + j], o[q][j]);
-                    }
+                for (int k0 = 0; k0 < m; k0 += 4) {
+                    const int kk = k0 + lk;
+                    const double av = ins[i][16 * wave + li][kk];
+                    const double bv = (kk < m && li < m) ? cs[i * m + kk][q * m + li] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
                 }
             }
-            for (int q = 0; q < nout; q++) {
-                double *dst = a.out[set * 2 + q] + r * m;
+            // accumulator register v holds row lk + 4v, column li of this wave's 16 rows
+            double *dst = a.out[set * 2 + q];
 #pragma unroll
-                for (int j = 0; j < M; j++)
-                    if (j < m) dst[j] = o[q][j];
+            for (int v = 0; v < 4; v++) {
+                const int r = 16 * wave + lk + 4 * v;
+                if (r < rows && li < m) dst[(r0 + r) * m + li] = acc[v];
             }
-            if (set == 0) {
+            if (q == 0 && a.theta) {
+                if (set == 0) {
+                    xkeep = acc;
+                } else {
+                    const double th = li < m ? a.theta[li] : 0.0;
 #pragma unroll
-                for (int j = 0; j < M; j++) xo[j] = o[0][j];
-            } else if (a.theta) {
-                double *rr = a.res + r * m;
-#pragma unroll
-                for (int j = 0; j < M; j++) {
-                    if (j < m) {
-                        double v = o[0][j] - xo[j] * a.theta[j];
-                        rr[j] = v;
-                        rn[j] = v * v;
+                    for (int v = 0; v < 4; v++) {
+                        const int r = 16 * wave + lk + 4 * v;
+                        if (r < rows && li < m) {
+                            const double rv = acc[v] - xkeep[v] * th;
+                            a.res[(r0 + r) * m + li] = rv;
+                            nrm += rv * rv;
+                        }
                     }
                 }
             }
         }
     }
     if (a.theta) {
-        // deterministic workgroup reduction of the squared norms
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-        for (int j = 0; j < M; j++) {
-            double v = rn[j];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-            if (lane == 0) nred[wave][j] = v;
-        }
+        // squared column norms of R for this tile, combined in a fixed order
+        nred[wave][lk][li] = nrm;
         __syncthreads();
-        if (threadIdx.x < m) {
+        if (tid < m) {
             double s = 0.0;
-            for (int w = 0; w < 4; w++) s += nred[w][threadIdx.x];
-            a.norm_part[(int64_t)blockIdx.x * m + threadIdx.x] = s;
+            for (int w = 0; w < 4; w++)
+                for (int g = 0; g < 4; g++) s += nred[w][g][tid];
+            a.norm_part[(int64_t)blockIdx.x * m + tid] = s;
         }
     }
 }
 
 void lincomb(const LincombArgs &a, hipStream_t s) {
-    if (a.nin * a.m > 48 || a.nout * a.m > 32 || a.nout > 2 || a.nin > 3)
+    if (a.nin * a.m > 48 || a.nout * a.m > 32 || a.nout > 2 || a.nin > 3 || a.m > 16)
         fail(HSYM_E_UNSUPPORTED, "lincomb shape");
-    unsigned grid = (unsigned)((a.n + 255) / 256);
-    if (a.m <= 8) hipLaunchKernelGGL(k_lincomb<8>, dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_lincomb<16>, dim3(grid), dim3(256), 0, s, a);
+    unsigned grid = (unsigned)((a.n + 63) / 64);
+    hipLaunchKernelGGL(k_lincomb, dim3(grid), dim3(256), 0, s, a);
     HIPCHK(hipGetLastError());
 }
 
-int64_t lincomb_norm_parts(int64_t n) { return (n + 255) / 256; }
+int64_t lincomb_norm_parts(int64_t n) { return (n + 63) / 64; }
 
-// sum of per-workgroup partial column sums (fixed order)
-__global__ void k_colsum_final(const double *__restrict__ part, int64_t nparts, int m, double *__restrict__ out) {
-    const int j = threadIdx.x;
-    if (j >= m) return;
+// sum of per-workgroup partial column sums: one workgroup per column,
+// strided partial sums combined by a fixed tree (bitwise reproducible)
+__global__ __launch_bounds__(256) void k_colsum_final(const double *__restrict__ part, int64_t nparts, int m,
+                                                      double *__restrict__ out) {
+    __shared__ double red[256];
+    const int j = blockIdx.x;
     double s = 0.0;
-    for (int64_t p = 0; p < nparts; p++) s += part[p * m + j];
-    out[j] = s;
+    for (int64_t p = threadIdx.x; p < nparts; p += 256) s += part[p * m + j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = red[0];
 }
 
 void colsum_final(const double *part, int64_t nparts, int m, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, part, nparts, m, out);
+    hipLaunchKernelGGL(k_colsum_final, dim3(m), dim3(256), 0, s, part, nparts, m, out);
     HIPCHK(hipGetLastError());
 }
 
@@ -289,11 +306,11 @@ __device__ __forceinline__ double guard_den(double d, double delta) {
 __global__ __launch_bounds__(256) void k_precond_jacobi(double *__restrict__ W, const double *__restrict__ diag,
                                                         const double *__restrict__ mu, double delta, int64_t n,
                                                         int m) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= n * m) return;
-    const int64_t r = e / m;
-    const int j = (int)(e - r * m);
-    W[e] = W[e] / guard_den(diag[r] - mu[j], delta);
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    const double d = diag[r];
+    double *w = W + r * m;
+    for (int j = 0; j < m; j++) w[j] = w[j] / guard_den(d - mu[j], delta);
 }
 
 // One workgroup per 64-row chunk: W_b = Q diag(1/g(lambda - mu_j)) Q^T R_b.
@@ -338,7 +355,7 @@ __global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W,
 void precond_apply(hsym_matrix *H, int kind, double *W, const double *mu, double delta, int m, hipStream_t s) {
     const int64_t n = H->n;
     if (kind == HSYM_PRECOND_JACOBI) {
-        unsigned grid = (unsigned)((n * m + 255) / 256);
+        unsigned grid = (unsigned)((n + 255) / 256);
         hipLaunchKernelGGL(k_precond_jacobi, dim3(grid), dim3(256), 0, s, W, H->diag64, mu, delta, n, m);
     } else if (kind == HSYM_PRECOND_BLOCK64) {
         hipLaunchKernelGGL(k_precond_block64, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, W, H->pre_q,

@@ -25,56 +25,33 @@ void check_hip(hipError_t e, const char *what);
 
 // ---------------------------------------------------------------------------
 // Tile format of the stored upper triangle (compressed sparse blocks,
-// Section 4.2).  Rows are cut into panels of R rows and columns into chunks of
-// C columns (R a multiple of C).  The strictly-upper entries of one panel that
-// fall into one chunk form a tile.  Inside a tile the rows that own entries are
-// sorted by their entry count (descending) and cut into slices of up to 64
-// rows; slice entries are stored lane-interleaved: entry e of slice row l sits
-// at base + e*nrows + l, short rows padded with zero values.  A tile is "own"
-// when its chunk lies inside the panel (its transposed half lands in the
-// panel's own rows) and "external" otherwise; every external tile owns one
-// partial-sum slot of C rows.
+// Section 4.2: independently addressable blocks, each holding its entries in
+// coordinate form with 16-bit local row and column offsets).  Rows are cut
+// into panels of R rows and columns into chunks of C columns (R a multiple of
+// C).  The strictly-upper entries of one panel that fall into one chunk form a
+// tile, stored row-major as 32-bit words (local row << 16 | local column) plus
+// values.  A tile's entries are cut into G equal segments (the last one padded
+// with zero values) stored interleaved: entry e of segment s sits at
+// base + e*G + s, so G lane groups stream a tile with coalesced loads and equal
+// work.  A tile is "own" when its chunk lies inside the panel (its transposed
+// half lands in the panel's rows) and "external" otherwise; every external tile
+// owns one partial-sum slot of C rows.
 // ---------------------------------------------------------------------------
 struct TileDesc {
-    int64_t slice_begin;   // first slice (global index)
-    int32_t nslices;
+    int64_t base;          // first stored entry
+    int32_t len;           // entries per segment (after padding)
     int32_t chunk;         // global chunk index g: columns [g*C, g*C+C)
     int32_t slot;          // partial slot, -1 for an own tile
     int32_t pad;
 };
 
-struct SliceDesc {
-    int64_t base;          // first entry (global index)
-    int32_t len;           // entries per row after padding
-    int32_t nrows;         // rows in the slice (<= 64): lane stride of the entries
-};
-
-struct TileFormat {
-    int R = 0, C = 0;
-    int64_t n = 0, npanels = 0, nchunks = 0;
-    int64_t ntiles = 0, nslices = 0, nentries = 0, nslots = 0;
-    // host copies (freed after upload unless kept for tests)
-    std::vector<int64_t> panel_tile_ptr;     // npanels+1
-    std::vector<TileDesc> tiles;
-    std::vector<SliceDesc> slices;
-    std::vector<uint16_t> slice_rows;        // nslices*64, panel-local rows
-    std::vector<uint32_t> cols;              // chunk-local column of every entry
-    std::vector<double> vals64;
-    std::vector<float> vals32;
-    std::vector<int64_t> red_ptr;            // per output chunk: contributing slots
-    std::vector<int32_t> red_slot;
-    std::vector<int32_t> red_chunks;         // chunks with at least one contribution
-};
-
 struct DeviceTiles {
-    int R = 0, C = 0, SR = 64;   // SR: rows per slice
-    int64_t npanels = 0, nchunks = 0, ntiles = 0, nslices = 0, nentries = 0, nslots = 0;
+    int R = 0, C = 0, G = 0;
+    int64_t npanels = 0, nchunks = 0, ntiles = 0, nentries = 0, nslots = 0;
     int64_t nred_chunks = 0;
     int64_t *panel_tile_ptr = nullptr;
     TileDesc *tiles = nullptr;
-    SliceDesc *slices = nullptr;
-    uint16_t *slice_rows = nullptr;
-    uint32_t *cols = nullptr;
+    uint32_t *idx = nullptr;
     void *vals = nullptr;
     int64_t *red_ptr = nullptr;
     int32_t *red_slot = nullptr;
@@ -113,7 +90,8 @@ struct hsym_matrix {
 namespace hsym {
 
 // geometry: (R, C) for a block width and storage precision
-void geometry_for(int storage, int m, int *R, int *C, int *SR);
+void geometry_for(int storage, int m, int64_t n, int *R, int *C, int *G);
+int spmm_lanes_per_entry(int storage, int m);
 size_t spmm_lds_bytes(int storage, int m, int R, int C);
 void free_tiles(DeviceTiles *dt);
 

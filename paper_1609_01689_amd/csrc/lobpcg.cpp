@@ -205,6 +205,7 @@ struct Lobpcg {
             if (j < nev) mx = std::max(mx, rho_[j]);
         }
         if (st_h->flags[1] < 0) fail(HSYM_E_NUMERIC, "Rayleigh-Ritz eigensolver did not converge");
+        rep.rr_sweeps_max = std::max(rep.rr_sweeps_max, st_h->flags[1] - 1);
         if (o.keep_history && rep.history_len < HSYM_MAX_HISTORY) rep.history[rep.history_len++] = mx;
         for (int j = 0; j < m; j++) { rep.theta[j] = st_h->theta[j]; rep.resnorm[j] = rho_[j]; }
         rep.iters = it;

@@ -88,20 +88,47 @@ __global__ __launch_bounds__(256) void k_small_orth(Batch<OrthArgs> b) {
         for (int k = 0; k < KB; k++) v -= G[k * m + i] * G[k * m + j];
         S[i][j] = v;
     }
+    if (tid == 0) bad = -1;
     __syncthreads();
-    if (tid == 0) {
-        int f = chol_lower(&S[0][0], 17, m);
-        bad = f;
-        if (f >= 0) {
-            int mask = 0;
-            for (int j = f; j < m; j++) mask |= 1 << j;
-            atomicOr(a.flag, mask);
-        } else {
-            tri_inv_lower(&S[0][0], 17, &Li[0][0], 17, m);
+    // right-looking Cholesky S = L L^T, in place in the lower triangle
+    double dmax = 0.0;
+    for (int j = 0; j < m; j++) dmax = fmax(dmax, fabs(S[j][j]));
+    for (int j = 0; j < m; j++) {
+        const double d = S[j][j];
+        if (!(d > 1e-14 * dmax) || !isfinite(d)) {
+            if (tid == 0) {
+                bad = j;
+                int mask = 0;
+                for (int jj = j; jj < m; jj++) mask |= 1 << jj;
+                atomicOr(a.flag, mask);
+            }
+            break;
         }
+        const double sd = sqrt(d);
+        __syncthreads();
+        if (tid < m && tid > j) S[tid][j] /= sd;
+        if (tid == 0) S[j][j] = sd;
+        __syncthreads();
+        for (int e = tid; e < m * m; e += 256) {
+            const int i = e / m, l = e - (e / m) * m;
+            if (l > j && i >= l) S[i][l] -= S[i][j] * S[l][j];
+        }
+        __syncthreads();
     }
     __syncthreads();
     if (bad >= 0) return;
+    // Li = L^{-1}: column c by forward substitution, one thread per column
+    if (tid < m) {
+        const int c = tid;
+        for (int i = 0; i < c; i++) Li[i][c] = 0.0;
+        Li[c][c] = 1.0 / S[c][c];
+        for (int i = c + 1; i < m; i++) {
+            double v = 0.0;
+            for (int l = c; l < i; l++) v += S[i][l] * Li[l][c];
+            Li[i][c] = -v / S[i][i];
+        }
+    }
+    __syncthreads();
     // coef rows: i < KB: -(G_B L^-T)[i][j] = -sum_k G[i][k] Li[j][k];  else L^-T[i-KB][j] = Li[j][i-KB]
     for (int e = tid; e < (KB + m) * m; e += 256) {
         int i = e / m, j = e - (e / m) * m;
@@ -130,110 +157,144 @@ void small_orth(const OrthArgs *a, int count, hipStream_t s) {
 // Rayleigh-Ritz: parallel cyclic Jacobi on k x k (k <= 48)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
-    __shared__ double A[KMAX][KMAX + 1], A2[KMAX][KMAX + 1];
-    __shared__ double V[KMAX][KMAX + 1], V2[KMAX][KMAX + 1];
-    __shared__ double rc[KMAX / 2], rs[KMAX / 2];
-    __shared__ int partner[KMAX + 1], pidx[KMAX + 1], isp[KMAX + 1];
-    __shared__ double offs, fro;
+    __shared__ double A[2][KMAX][KMAX + 1];
+    __shared__ double V[2][KMAX][KMAX + 1];
+    __shared__ double cj[KMAX + 1], sj[KMAX + 1];   // rotation of the pair index x belongs to
+    __shared__ double fro;
+    __shared__ int nrot;
     __shared__ int perm[KMAX];
     __shared__ double ev[KMAX];
     __shared__ double Z[KMAX][17];
+    __shared__ double dq[16];
     const RRArgs a = b.a[blockIdx.x];
     const int m = a.m, k = a.nblk * m;
     const int kp = (k + 1) & ~1;          // even number of players (one dummy if k is odd)
+    const int km = kp - 1;
     const int tid = threadIdx.x;
     for (int e = tid; e < k * k; e += 256) {
         int i = e / k, j = e - (e / k) * k;
-        A[i][j] = 0.5 * (a.gram[i * k + j] + a.gram[j * k + i]);
-        V[i][j] = (i == j) ? 1.0 : 0.0;
+        A[0][i][j] = 0.5 * (a.gram[i * k + j] + a.gram[j * k + i]);
+        V[0][i][j] = (i == j) ? 1.0 : 0.0;
     }
+    if (tid == 0) fro = 0.0;
     __syncthreads();
-    if (tid == 0) {
+    if (tid < 64) {
         double f = 0.0;
-        for (int i = 0; i < k; i++)
-            for (int j = 0; j < k; j++) f += A[i][j] * A[i][j];
-        fro = f;
+        for (int e = tid; e < k * k; e += 64) f += A[0][e / k][e % k] * A[0][e / k][e % k];
+        for (int off = 32; off > 0; off >>= 1) f += __shfl_down(f, off, 64);
+        if (tid == 0) fro = f;
     }
     __syncthreads();
-    int sweeps = 0;
+    // a rotation is applied when the off-diagonal entry is above this level
+    // (above the rounding floor of the rotations themselves, about k u ||A||);
+    // a sweep that applies none ends the iteration
+    const double tiny = 1e-14 * sqrt(fro) + 1e-300;
+    int cur = 0, sweeps = 0;
     for (; sweeps < 40; sweeps++) {
-        if (tid == 0) {
-            double o = 0.0;
-            for (int i = 0; i < k; i++)
-                for (int j = 0; j < k; j++)
-                    if (i != j) o += A[i][j] * A[i][j];
-            offs = o;
-        }
+        if (tid == 0) nrot = 0;
         __syncthreads();
-        if (offs <= 1e-30 * fro || offs == 0.0) break;
-        for (int r = 0; r < kp - 1; r++) {
-            // circle-method pairing of round r
+        for (int r = 0; r < km; r++) {
+            // circle-method pairing of round r: the fixed player km meets r, every
+            // other x meets (2r - x) mod km
             if (tid < kp / 2) {
                 int p, q;
-                if (tid == 0) { p = kp - 1; q = r; }
-                else { p = (r + tid) % (kp - 1); q = (r - tid + (kp - 1)) % (kp - 1); }
+                if (tid == 0) { p = km; q = r; }
+                else { p = (r + tid) % km; q = (r - tid + km) % km; }
                 if (p > q) { int t = p; p = q; q = t; }
-                partner[p] = q; partner[q] = p;
-                pidx[p] = tid; pidx[q] = tid;
-                isp[p] = 1; isp[q] = 0;
-                double c = 1.0, s = 0.0;
+                double c = 1.0, sn = 0.0;
                 if (q < k) {
-                    double apq = A[p][q];
-                    if (apq != 0.0) {
-                        double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+                    double apq = A[cur][p][q];
+                    if (fabs(apq) > tiny) {
+                        double tau = (A[cur][q][q] - A[cur][p][p]) / (2.0 * apq);
                         double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + t * t);
-                        s = t * c;
+                        sn = t * c;
+                        atomicAdd(&nrot, 1);
                     }
                 }
-                rc[tid] = c; rs[tid] = s;
+                // column p of J is (c at p, -s at q); column q is (s at p, c at q)
+                cj[p] = c; sj[p] = -sn;
+                cj[q] = c; sj[q] = sn;
             }
             __syncthreads();
-            // A' = J^T A J and V' = V J for all disjoint rotations at once.  Only the
-            // upper triangle of A' is computed and mirrored, so A stays exactly
-            // symmetric (rotations cannot remove an antisymmetric rounding part).
-            for (int e = tid; e < k * k; e += 256) {
-                int x = e / k, y = e - (e / k) * k;
-                int yb = partner[y];
-                double cy = rc[pidx[y]], sy = isp[y] ? -rs[pidx[y]] : rs[pidx[y]];
-                double w = cy * V[x][y];
-                if (yb < k) w += sy * V[x][yb];
-                V2[x][y] = w;
-                if (x > y) continue;
-                int xb = partner[x];
-                double cx = rc[pidx[x]], sx = isp[x] ? -rs[pidx[x]] : rs[pidx[x]];
-                double v = cx * cy * A[x][y];
-                if (yb < k) v += cx * sy * A[x][yb];
-                if (xb < k) v += sx * cy * A[xb][y];
-                if (xb < k && yb < k) v += sx * sy * A[xb][yb];
-                A2[x][y] = v;
-                A2[y][x] = v;
+            const int nx = cur ^ 1;
+            // lanes own columns y, the four waves split the rows x: no integer
+            // division in the loop (partner(y) = 2r - y wrapped into [0, km))
+            const int y = tid & 63, xg = tid >> 6;
+            if (y < k) {
+                int yb = (y == km) ? r : (y == r ? km : 2 * r - y);
+                if (yb < 0) yb += km;
+                else if (yb >= km && y != r) yb -= km;
+                const bool ybk = yb < k;
+                const double cy = cj[y], sy = sj[y];
+                // V' = V J: rows x = xg + 4 it, loads issued before the stores
+                double v0[KMAX / 4], v1[KMAX / 4];
+#pragma unroll
+                for (int it = 0; it < KMAX / 4; it++) {
+                    const int x = xg + 4 * it;
+                    v0[it] = (x < k) ? V[cur][x][y] : 0.0;
+                    v1[it] = (x < k && ybk) ? V[cur][x][yb] : 0.0;
+                }
+#pragma unroll
+                for (int it = 0; it < KMAX / 4; it++) {
+                    const int x = xg + 4 * it;
+                    if (x < k) V[nx][x][y] = cy * v0[it] + sy * v1[it];
+                }
+                // A' = J^T A J on the upper triangle (x <= y), mirrored: A stays exactly
+                // symmetric (rotations cannot remove an antisymmetric rounding part)
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    double a0[KMAX / 8], a1[KMAX / 8], a2[KMAX / 8], a3[KMAX / 8], cx[KMAX / 8], sx[KMAX / 8];
+#pragma unroll
+                    for (int it = 0; it < KMAX / 8; it++) {
+                        const int x = xg + 4 * (it + h * (KMAX / 8));
+                        int xb = (x == km) ? r : (x == r ? km : 2 * r - x);
+                        if (xb < 0) xb += km;
+                        else if (xb >= km && x != r) xb -= km;
+                        const bool ok = x <= y, xbk = ok && xb < k;
+                        a0[it] = ok ? A[cur][x][y] : 0.0;
+                        a1[it] = (ok && ybk) ? A[cur][x][yb] : 0.0;
+                        a2[it] = xbk ? A[cur][xb][y] : 0.0;
+                        a3[it] = (xbk && ybk) ? A[cur][xb][yb] : 0.0;
+                        cx[it] = ok ? cj[x] : 0.0;
+                        sx[it] = ok ? sj[x] : 0.0;
+                    }
+#pragma unroll
+                    for (int it = 0; it < KMAX / 8; it++) {
+                        const int x = xg + 4 * (it + h * (KMAX / 8));
+                        if (x <= y) {
+                            const double v = cx[it] * cy * a0[it] + cx[it] * sy * a1[it] + sx[it] * cy * a2[it] +
+                                             sx[it] * sy * a3[it];
+                            A[nx][x][y] = v;
+                            A[nx][y][x] = v;
+                        }
+                    }
+                }
             }
-            __syncthreads();
-            for (int e = tid; e < k * k; e += 256) {
-                int x = e / k, y = e - (e / k) * k;
-                A[x][y] = A2[x][y];
-                V[x][y] = V2[x][y];
-            }
+            cur = nx;
             __syncthreads();
         }
+        const int none = (nrot == 0);
+        __syncthreads();      // every thread has read nrot before it is reset
+        if (none) break;
     }
-    if (tid == 0) {
-        for (int i = 0; i < k; i++) { perm[i] = i; ev[i] = A[i][i]; }
-        for (int i = 0; i < k; i++) {          // selection sort, ascending
-            int b2 = i;
-            for (int j = i + 1; j < k; j++) if (ev[perm[j]] < ev[perm[b2]]) b2 = j;
-            int t = perm[i]; perm[i] = perm[b2]; perm[b2] = t;
-        }
-        a.flag[0] = (sweeps < 40 || offs <= 1e-24 * fro) ? sweeps + 1 : -1;
+    // ascending order by rank (ties by index)
+    if (tid < k) ev[tid] = A[cur][tid][tid];
+    __syncthreads();
+    if (tid < k) {
+        int rank = 0;
+        double v = ev[tid];
+        for (int j = 0; j < k; j++) rank += (ev[j] < v) || (ev[j] == v && j < tid);
+        perm[rank] = tid;
     }
+    if (tid == 0) a.flag[0] = sweeps < 40 ? sweeps + 1 : -1;
     __syncthreads();
     if (tid < k) a.evals_all[tid] = ev[perm[tid]];
     if (tid < m) a.theta[tid] = ev[perm[tid]];
     // C_X = first m sorted eigenvectors
     for (int e = tid; e < k * m; e += 256) {
         int i = e / m, j = e - (e / m) * m;
-        a.coef[i * 2 * m + j] = V[i][perm[j]];
+        a.coef[i * 2 * m + j] = V[cur][i][perm[j]];
     }
     // Z = C_rest^T Y, Y = C_X with its X rows zeroed; (k-m) x m
     const int kr = k - m;
@@ -247,43 +308,58 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
     for (int e = tid; e < kr * m; e += 256) {
         int i = e / m, j = e - (e / m) * m;
         double s = 0.0;
-        for (int t = m; t < k; t++) s += V[t][perm[m + i]] * V[t][perm[j]];
+        for (int t = m; t < k; t++) s += V[cur][t][perm[m + i]] * V[cur][t][perm[j]];
         Z[i][j] = s;
     }
     __syncthreads();
-    if (tid == 0) {
-        // modified Gram-Schmidt, two passes; a vanishing column is replaced by a unit vector
-        int next_unit = 0;
-        for (int j = 0; j < m; j++) {
-            double n0 = 0.0;
+    // modified Gram-Schmidt on the columns of Z, two passes; a vanishing column
+    // is replaced by a unit vector
+    int next_unit = 0;
+    for (int j = 0; j < m; j++) {
+        double n0 = 0.0;
+        if (tid == 0) {
             for (int i = 0; i < kr; i++) n0 += Z[i][j] * Z[i][j];
-            n0 = sqrt(n0);
-            for (int attempt = 0; attempt < 4; attempt++) {
-                for (int pass = 0; pass < 2; pass++)
-                    for (int q = 0; q < j; q++) {
-                        double d = 0.0;
-                        for (int i = 0; i < kr; i++) d += Z[i][q] * Z[i][j];
-                        for (int i = 0; i < kr; i++) Z[i][j] -= d * Z[i][q];
-                    }
+            dq[0] = sqrt(n0);
+        }
+        __syncthreads();
+        n0 = dq[0];
+        __syncthreads();
+        for (int attempt = 0; attempt < 4; attempt++) {
+            for (int pass = 0; pass < 2; pass++) {
+                if (tid < j) {
+                    double d = 0.0;
+                    for (int i = 0; i < kr; i++) d += Z[i][tid] * Z[i][j];
+                    dq[tid] = d;
+                }
+                __syncthreads();
+                if (tid < kr) {
+                    double v = Z[tid][j];
+                    for (int q = 0; q < j; q++) v -= dq[q] * Z[tid][q];
+                    Z[tid][j] = v;
+                }
+                __syncthreads();
+            }
+            __shared__ double nn_s;
+            if (tid == 0) {
                 double nn = 0.0;
                 for (int i = 0; i < kr; i++) nn += Z[i][j] * Z[i][j];
-                nn = sqrt(nn);
-                if (nn > 1e-12 * n0 && nn > 1e-300) {
-                    for (int i = 0; i < kr; i++) Z[i][j] /= nn;
-                    break;
-                }
-                for (int i = 0; i < kr; i++) Z[i][j] = (i == (next_unit % kr)) ? 1.0 : 0.0;
-                next_unit++;
-                n0 = 1.0;
+                nn_s = sqrt(nn);
             }
+            __syncthreads();
+            double nn = nn_s;
+            bool ok = nn > 1e-12 * n0 && nn > 1e-300;
+            if (tid < kr) Z[tid][j] = ok ? Z[tid][j] / nn : ((tid == (next_unit % kr)) ? 1.0 : 0.0);
+            __syncthreads();
+            if (ok) break;
+            next_unit++;
+            n0 = 1.0;
         }
     }
-    __syncthreads();
     // C_P = C_rest Z
     for (int e = tid; e < k * m; e += 256) {
         int i = e / m, j = e - (e / m) * m;
         double s = 0.0;
-        for (int t = 0; t < kr; t++) s += V[i][perm[m + t]] * Z[t][j];
+        for (int t = 0; t < kr; t++) s += V[cur][i][perm[m + t]] * Z[t][j];
         a.coef[i * 2 * m + m + j] = s;
     }
 }

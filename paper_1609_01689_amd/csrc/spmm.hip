@@ -1,47 +1,52 @@
 // Symmetric SpMM from one stored triangle: Y = D X + U X + U^T X.
 //
 // Each stored off-diagonal entry is used twice, once as itself (row half,
-// U X) and once transposed (U^T X), the two local products per stored block
-// of Section 4.1; the diagonal D is applied separately so it is counted once.
+// U X) and once transposed (U^T X): the two local products per stored block of
+// Section 4.1.  The diagonal D is applied separately so it is counted once.
 //
-// One workgroup owns one row panel of R rows and walks its tiles (chunks of
-// C columns) in column order, as the CSB traversal of Section 4.4 does:
-//   - the X rows of the chunk are staged in LDS;
-//   - lanes own slice rows: the row half is accumulated in registers and
-//     added once per tile to the panel accumulator in LDS;
-//   - the transposed half is accumulated with LDS atomics into the panel
-//     accumulator (own tiles) or into a chunk accumulator that is written out
-//     as a partial sum (external tiles, whose columns lie below the panel);
+// One 1024-thread workgroup owns one row panel of R rows and walks its tiles
+// in column order, as the CSB traversal of Section 4.4 does.  In LDS it keeps
+// the panel's accumulator and X rows, plus the X rows and the transposed
+// accumulator of the current external chunk.  A tile's entries are split in
+// equal segments, one per group of LPE lanes; each lane of a group handles
+// MW = M/LPE columns:
+//   - row half: a register accumulator for the current row, added to the
+//     panel accumulator with LDS atomics when the row changes;
+//   - transposed half: LDS atomics into the panel accumulator (own tiles) or
+//     into the chunk accumulator, written out as a partial sum (external
+//     tiles, whose columns lie below the panel);
 //   - a second kernel adds the partial sums of every output chunk in a fixed
 //     order.  No global atomics are used.
+// LDS rows are swizzled (the column offset rotates with the row index) so the
+// lane groups of one wave, which touch different rows, spread over the banks.
 #include "hsym_internal.h"
 
 namespace hsym {
-
-template <typename T, int M>
-struct LdsStride {
-    // one 16-byte pad per row spreads consecutive rows over the LDS banks
-    static constexpr int MP = (M == 1) ? 1 : (M + 16 / (int)sizeof(T));
-};
 
 static inline int round_m(int m) {
     if (m <= 1) return 1;
     if (m <= 2) return 2;
     if (m <= 4) return 4;
     if (m <= 8) return 8;
-    if (m <= 12) return 12;
     return 16;
 }
 
+// values per lane: one 16-byte LDS access per lane and step
 template <typename T>
-static int stride_of(int M) {
-    return (M == 1) ? 1 : (M + 16 / (int)sizeof(T));
+__host__ __device__ constexpr int mw_of(int M) {
+    return M == 1 ? 1 : (sizeof(T) == 8 ? 2 : (M < 4 ? M : 4));
+}
+
+int spmm_lanes_per_entry(int storage, int m) {
+    (void)storage;
+    int M = round_m(m);
+    return M / mw_of<double>(M);
 }
 
 size_t spmm_lds_bytes(int storage, int m, int R, int C) {
     int M = round_m(m);
-    if (storage == HSYM_FP64) return (size_t)(R + 2 * C) * stride_of<double>(M) * sizeof(double);
-    return (size_t)(R + 2 * C) * stride_of<float>(M) * sizeof(float);
+    size_t es = storage == HSYM_FP64 ? 8 : 4;
+    return (size_t)(R + C) * M * (8 + es);
 }
 
 __device__ __forceinline__ int64_t xcd_panel(int64_t b, int64_t P) {
@@ -59,83 +64,122 @@ __device__ __forceinline__ void lds_add(float *p, float v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// LPR lanes share one slice row, each handling MW = M/LPR columns.
-template <int M, int LPR, typename T, typename XIN, typename YT, int NT>
-__global__ __launch_bounds__(NT) void k_spmm_panel(
-    const int64_t *__restrict__ ptp, const TileDesc *__restrict__ tiles,
-    const SliceDesc *__restrict__ slices, const uint16_t *__restrict__ srows,
-    const uint32_t *__restrict__ cols, const T *__restrict__ vals, const T *__restrict__ diag,
-    const XIN *__restrict__ X, int64_t ldx, YT *__restrict__ Y, int64_t ldy,
-    T *__restrict__ partials, int64_t n, int R, int C, int64_t npanels, int m) {
-    constexpr int MP = LdsStride<T, M>::MP;
-    constexpr int NW = NT / 64;
-    constexpr int MW = M / LPR;
+template <int M, typename T>
+struct Lay {
+    static constexpr int MW = mw_of<T>(M);
+    static constexpr int LPE = M / MW;
+    static constexpr int ROWB = M * (int)sizeof(T);
+    static constexpr int RPB = ROWB >= 128 ? 1 : 128 / ROWB;   // rows per 128-byte bank line
+    // physical column of (row c, column k)
+    __device__ static __forceinline__ int sw(int c, int k) {
+        return (MW == 1) ? k : ((k + LPE * ((c / RPB) & (MW - 1))) & (M - 1));
+    }
+};
+
+// T: stored values and staged X; A: products and sums (fp64 for both
+// storage precisions: a product of two fp32 numbers is exact in fp64, and the
+// LDS fp64 atomic add is several times cheaper than the fp32 one on gfx950)
+template <int M, typename T, typename XIN, typename YT>
+__global__ __launch_bounds__(1024) void k_spmm_panel(
+    const int64_t *__restrict__ ptp, const TileDesc *__restrict__ tiles, const uint32_t *__restrict__ idx,
+    const T *__restrict__ vals, const T *__restrict__ diag, const XIN *__restrict__ X, int64_t ldx,
+    YT *__restrict__ Y, int64_t ldy, double *__restrict__ partials, int64_t n, int R, int C, int G,
+    int64_t npanels, int m) {
+    using A = double;
+    using L = Lay<M, double>;
+    constexpr int NT = 1024, MW = L::MW, LPE = L::LPE, GK = NT / LPE;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *acc = reinterpret_cast<T *>(smem_raw);
-    T *xs = acc + (size_t)R * MP;
-    T *ts = xs + (size_t)C * MP;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int l = lane / LPR, h = lane % LPR;
+    A *acc = reinterpret_cast<A *>(smem_raw);
+    A *ts = acc + (size_t)R * M;
+    T *xp = reinterpret_cast<T *>(ts + (size_t)C * M);
+    T *xs = xp + (size_t)R * M;
+    const int tid = threadIdx.x, g = tid / LPE, q = tid % LPE;
     const int64_t p = xcd_panel(blockIdx.x, npanels);
     const int64_t row0 = p * (int64_t)R;
     const int nrow = (int)((n - row0) < R ? (n - row0) : R);
 
-    for (int i = tid; i < R * MP; i += NT) acc[i] = T(0);
+    for (int i = tid; i < R * M; i += NT) {
+        const int r = i / M, k = i - r * M;
+        T v = T(0);
+        if (r < nrow && k < m) v = (T)X[(row0 + r) * ldx + k];
+        xp[r * M + L::sw(r, k)] = v;
+        acc[i] = A(0);
+    }
     const int64_t t0 = ptp[p], t1 = ptp[p + 1];
+    constexpr int B = 4;   // entries loaded ahead of use
     for (int64_t t = t0; t < t1; t++) {
         const TileDesc td = tiles[t];
         const int64_t col0 = (int64_t)td.chunk * C;
-        const int ncol = (int)((n - col0) < C ? (n - col0) : C);
-        for (int i = tid; i < C * M; i += NT) {
-            const int r = i / M, k = i - r * M;
-            T v = T(0);
-            if (r < ncol && k < m) v = (T)X[(col0 + r) * ldx + k];
-            xs[r * MP + k] = v;
-        }
         const bool ext = td.slot >= 0;
-        if (ext)
-            for (int i = tid; i < C * MP; i += NT) ts[i] = T(0);
+        if (ext) {
+            const int ncol = (int)((n - col0) < C ? (n - col0) : C);
+            for (int i = tid; i < C * M; i += NT) {
+                const int r = i / M, k = i - r * M;
+                T v = T(0);
+                if (r < ncol && k < m) v = (T)X[(col0 + r) * ldx + k];
+                xs[r * M + L::sw(r, k)] = v;
+                ts[i] = A(0);
+            }
+        }
         __syncthreads();
-        T *tgt = ext ? ts : acc + (col0 - row0) * MP;
-        for (int s = wave; s < td.nslices; s += NW) {
-            const SliceDesc sd = slices[td.slice_begin + s];
-            const int nr = sd.nrows;
-            // a slice holds up to 64 rows; 64/LPR of them are processed per pass
-            for (int lb = 0; lb < nr; lb += 64 / LPR) {
-                const int lr = lb + l;
-                if (lr >= nr) break;
-                const int r = srows[(td.slice_begin + s) * 64 + lr];
-                const XIN *xrow = X + (row0 + r) * ldx + h * MW;
-                T xr[MW], ra[MW];
+        // own tiles read and update the panel's rows directly; col0 - row0 is a
+        // multiple of C, so the swizzle of a chunk row equals that of its panel row
+        const T *xsrc = ext ? xs : xp + (col0 - row0) * M;
+        A *tgt = ext ? ts : acc + (col0 - row0) * M;
+        const int len = td.len;
+        for (int seg = g; seg < G; seg += GK) {
+            const uint32_t *ip = idx + td.base + seg;
+            const T *vp = vals + td.base + seg;
+            int cur = -1;
+            A ra[MW], xr[MW];
 #pragma unroll
-                for (int k = 0; k < MW; k++) {
-                    xr[k] = (h * MW + k < m) ? (T)xrow[k] : T(0);
-                    ra[k] = T(0);
+            for (int j = 0; j < MW; j++) { ra[j] = A(0); xr[j] = A(0); }
+            for (int e0 = 0; e0 < len; e0 += B) {
+                uint32_t w[B];
+                T a[B];
+                const int cnt = (len - e0) < B ? (len - e0) : B;
+#pragma unroll
+                for (int u = 0; u < B; u++) {
+                    const int off = (e0 + (u < cnt ? u : 0)) * G;
+                    w[u] = ip[off];
+                    a[u] = vp[off];
                 }
-                const uint32_t *cp = cols + sd.base + lr;
-                const T *vp = vals + sd.base + lr;
-                const int len = sd.len;
-                for (int e = 0; e < len; e++) {
-                    const uint32_t c = cp[(int64_t)e * nr];
-                    const T a = vp[(int64_t)e * nr];
-                    const T *xc = xs + c * MP + h * MW;
-                    T *tc = tgt + c * MP + h * MW;
 #pragma unroll
-                    for (int k = 0; k < MW; k++) ra[k] = fma(a, xc[k], ra[k]);
+                for (int u = 0; u < B; u++) {
+                    if (u >= cnt) break;
+                    const int r = (int)(w[u] >> 16), c = (int)(w[u] & 0xffffu);
+                    if (r != cur) {
+                        if (cur >= 0) {
 #pragma unroll
-                    for (int k = 0; k < MW; k++) lds_add(tc + k, a * xr[k]);
+                            for (int j = 0; j < MW; j++) {
+                                lds_add(acc + cur * M + L::sw(cur, q + LPE * j), ra[j]);
+                                ra[j] = A(0);
+                            }
+                        }
+                        cur = r;
+#pragma unroll
+                        for (int j = 0; j < MW; j++) xr[j] = (A)xp[r * M + L::sw(r, q + LPE * j)];
+                    }
+#pragma unroll
+                    for (int j = 0; j < MW; j++) {
+                        const int pk = c * M + L::sw(c, q + LPE * j);
+                        const A av = (A)a[u];
+                        ra[j] = fma(av, (A)xsrc[pk], ra[j]);
+                        lds_add(tgt + pk, av * xr[j]);
+                    }
                 }
-                T *ar = acc + r * MP + h * MW;
+            }
+            if (cur >= 0) {
 #pragma unroll
-                for (int k = 0; k < MW; k++) lds_add(ar + k, ra[k]);
+                for (int j = 0; j < MW; j++) lds_add(acc + cur * M + L::sw(cur, q + LPE * j), ra[j]);
             }
         }
         __syncthreads();
         if (ext) {
-            T *dst = partials + (int64_t)td.slot * C * M;
+            A *dst = partials + (int64_t)td.slot * C * M;
             for (int i = tid; i < C * M; i += NT) {
                 const int r = i / M, k = i - r * M;
-                dst[i] = ts[r * MP + k];
+                dst[i] = ts[r * M + L::sw(r, k)];
             }
             __syncthreads();
         }
@@ -144,18 +188,18 @@ __global__ __launch_bounds__(NT) void k_spmm_panel(
         const int r = i / M, k = i - r * M;
         if (k < m) {
             const int64_t row = row0 + r;
-            const T x = (T)X[row * ldx + k];
-            Y[row * ldy + k] = (YT)(acc[r * MP + k] + diag[row] * x);
+            const int pk = r * M + L::sw(r, k);
+            Y[row * ldy + k] = (YT)(acc[pk] + (A)diag[row] * (A)xp[pk]);
         }
     }
 }
 
 // Y[chunk rows] += sum of the partial slots of that chunk, in slot order.
-template <int M, typename T, typename YT, int NT>
+template <int M, typename YT, int NT>
 __global__ __launch_bounds__(NT) void k_spmm_reduce(const int32_t *__restrict__ red_chunks,
                                                     const int64_t *__restrict__ red_ptr,
                                                     const int32_t *__restrict__ red_slot,
-                                                    const T *__restrict__ partials, YT *__restrict__ Y,
+                                                    const double *__restrict__ partials, YT *__restrict__ Y,
                                                     int64_t ldy, int64_t n, int C, int m) {
     const int64_t g = red_chunks[blockIdx.x];
     const int64_t col0 = g * C;
@@ -164,34 +208,33 @@ __global__ __launch_bounds__(NT) void k_spmm_reduce(const int32_t *__restrict__ 
     for (int i = threadIdx.x; i < ncol * M; i += NT) {
         const int r = i / M, k = i - r * M;
         if (k >= m) continue;
-        T s = T(0);
+        double s = 0.0;
         for (int64_t q = q0; q < q1; q++) s += partials[(int64_t)red_slot[q] * C * M + i];
         YT *y = Y + (col0 + r) * ldy + k;
-        *y = *y + (YT)s;
+        *y = (YT)((double)*y + s);
     }
 }
 
-template <int M, int LPR, typename T, typename XIN, typename YT>
+template <int M, typename T, typename XIN, typename YT>
 static void launch_typed(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y, int64_t ldy,
                          void *partials, hipStream_t s) {
     const DeviceTiles &dt = H->tiles;
-    constexpr int NT = (M >= 8) ? 1024 : 512;
-    size_t lds = (size_t)(dt.R + 2 * dt.C) * LdsStride<T, M>::MP * sizeof(T);
-    auto kp = k_spmm_panel<M, LPR, T, XIN, YT, NT>;
+    size_t lds = (size_t)(dt.R + dt.C) * M * (sizeof(double) + sizeof(T));
+    auto kp = k_spmm_panel<M, T, XIN, YT>;
     static bool attr_set = false;
     if (!attr_set) {
         HIPCHK(hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         attr_set = true;
     }
     const T *diag = (const T *)(H->storage == HSYM_FP64 ? (const void *)H->diag64 : (const void *)H->diag32);
-    hipLaunchKernelGGL(kp, dim3((unsigned)dt.npanels), dim3(NT), lds, s, dt.panel_tile_ptr, dt.tiles,
-                       dt.slices, dt.slice_rows, dt.cols, (const T *)dt.vals, diag, (const XIN *)X, ldx,
-                       (YT *)Y, ldy, (T *)partials, H->n, dt.R, dt.C, dt.npanels, m);
+    hipLaunchKernelGGL(kp, dim3((unsigned)dt.npanels), dim3(1024), lds, s, dt.panel_tile_ptr, dt.tiles, dt.idx,
+                       (const T *)dt.vals, diag, (const XIN *)X, ldx, (YT *)Y, ldy, (double *)partials, H->n, dt.R,
+                       dt.C, dt.G, dt.npanels, m);
     HIPCHK(hipGetLastError());
     if (dt.nred_chunks > 0) {
-        hipLaunchKernelGGL((k_spmm_reduce<M, T, YT, 256>), dim3((unsigned)dt.nred_chunks), dim3(256), 0, s,
-                           dt.red_chunks, dt.red_ptr, dt.red_slot, (const T *)partials, (YT *)Y, ldy, H->n,
-                           dt.C, m);
+        hipLaunchKernelGGL((k_spmm_reduce<M, YT, 256>), dim3((unsigned)dt.nred_chunks), dim3(256), 0, s,
+                           dt.red_chunks, dt.red_ptr, dt.red_slot, (const double *)partials, (YT *)Y, ldy, H->n, dt.C,
+                           m);
         HIPCHK(hipGetLastError());
     }
 }
@@ -200,18 +243,16 @@ template <typename T, typename XIN, typename YT>
 static void launch_m(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y, int64_t ldy, void *part,
                      hipStream_t s) {
     switch (round_m(m)) {
-        case 1: launch_typed<1, 1, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
-        case 2: launch_typed<2, 1, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
-        case 4: launch_typed<4, 1, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
-        case 8: launch_typed<8, 1, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
-        case 12: launch_typed<12, 2, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
-        default: launch_typed<16, 2, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
+        case 1: launch_typed<1, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
+        case 2: launch_typed<2, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
+        case 4: launch_typed<4, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
+        case 8: launch_typed<8, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
+        default: launch_typed<16, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
     }
 }
 
 size_t spmm_partial_bytes(hsym_matrix *H, int m) {
-    size_t es = H->storage == HSYM_FP64 ? 8 : 4;
-    return (size_t)std::max<int64_t>(H->tiles.nslots, 1) * H->tiles.C * round_m(m) * es;
+    return (size_t)std::max<int64_t>(H->tiles.nslots, 1) * H->tiles.C * round_m(m) * sizeof(double);
 }
 
 void spmm_launch(hsym_matrix *H, int m, const void *X, int xprec, int64_t ldx, void *Y, int yprec,
