@@ -143,7 +143,7 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     ms_per_step = 1000.0 * total / args.steps
-    log("lobpcg fp64: %.1f ms/solve, iterations %s, rr sweeps max %d, evals %s" % (ms_per_step, iters, rep.rr_sweeps_max, ev))
+    log("lobpcg fp64: %.1f ms/solve, iterations %s, rr bisection rounds max %d, evals %s" % (ms_per_step, iters, rep.rr_rounds_max, ev))
 
     extras = {}
     if not args.no_extras:

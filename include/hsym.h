@@ -155,7 +155,7 @@ typedef struct {
     double phase_ms[8];               /* spmm, precond, orth, rr_gram, small, update, sync, other */
     int history_len;
     double history[HSYM_MAX_HISTORY]; /* max_{j<=nev} rho_j per iteration           */
-    int rr_sweeps_max;                /* most Jacobi sweeps any Rayleigh-Ritz needed  */
+    int rr_rounds_max;                /* most multisection rounds any Rayleigh-Ritz eigenvalue search took */
 } lobpcg_report;
 
 void lobpcg_opts_default(lobpcg_opts *o);

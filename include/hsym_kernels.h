@@ -34,7 +34,10 @@ int hsym_kernel_lincomb(int64_t n, int m, int nin, const double *const *In, int 
 
 /*
  * Rayleigh-Ritz of eq. 9 on an orthonormal basis of nblk (1..3) blocks:
- * A is device k x k (k = nblk*m), symmetrised on input.  Writes theta (device,
+ * A is device k x k (k = nblk*m), symmetrised on input.  Eigenvalues by
+ * bisection on Sturm counts of the Householder tridiagonal form, eigenvectors
+ * by inverse iteration (accuracy: eigenvalues and residuals within a small
+ * multiple of k * eps * ||A||).  Writes theta (device,
  * m lowest eigenvalues ascending), evals (device, all k), and coef (device
  * k x 2m): columns 0..m-1 the m lowest eigenvectors C_X, columns m..2m-1 an
  * orthonormal basis of the rows m..k-1 of C_X made orthogonal to C_X (the

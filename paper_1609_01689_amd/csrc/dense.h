@@ -76,8 +76,8 @@ struct RRArgs {
     const double *gram;   // k x k
     double *coef;         // k x 2m
     double *theta;        // m
-    double *evals_all;    // k (diagnostics)
-    int *flag;            // sweeps used (>0) or -1 on failure
+    double *evals_all;    // k (diagnostics), or null: then only the m lowest are computed
+    int *flag;            // 1 + multisection rounds used (>0), or -1 on failure
     int nblk, m;
 };
 void small_rr(const RRArgs *a, int count, hipStream_t s);

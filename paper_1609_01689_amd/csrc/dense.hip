@@ -303,14 +303,15 @@ __device__ __forceinline__ double guard_den(double d, double delta) {
     return fabs(d) >= delta ? d : (d >= 0.0 ? delta : -delta);
 }
 
+// Elementwise over the row-major n x M block (coalesced): W[r][j] /= g(d_r - mu_j).
+template <int M>
 __global__ __launch_bounds__(256) void k_precond_jacobi(double *__restrict__ W, const double *__restrict__ diag,
-                                                        const double *__restrict__ mu, double delta, int64_t n,
-                                                        int m) {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r >= n) return;
-    const double d = diag[r];
-    double *w = W + r * m;
-    for (int j = 0; j < m; j++) w[j] = w[j] / guard_den(d - mu[j], delta);
+                                                        const double *__restrict__ mu, double delta, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * M) return;
+    const int64_t r = e / M;
+    const int j = (int)(e - r * M);
+    W[e] = W[e] / guard_den(diag[r] - mu[j], delta);
 }
 
 // One workgroup per 64-row chunk: W_b = Q diag(1/g(lambda - mu_j)) Q^T R_b.
@@ -355,8 +356,14 @@ __global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W,
 void precond_apply(hsym_matrix *H, int kind, double *W, const double *mu, double delta, int m, hipStream_t s) {
     const int64_t n = H->n;
     if (kind == HSYM_PRECOND_JACOBI) {
-        unsigned grid = (unsigned)((n + 255) / 256);
-        hipLaunchKernelGGL(k_precond_jacobi, dim3(grid), dim3(256), 0, s, W, H->diag64, mu, delta, n, m);
+        const unsigned grid = (unsigned)((n * m + 255) / 256);
+        switch (m) {
+#define HSYM_JAC(MM) case MM: hipLaunchKernelGGL(k_precond_jacobi<MM>, dim3(grid), dim3(256), 0, s, W, H->diag64, mu, delta, n); break;
+            HSYM_JAC(1) HSYM_JAC(2) HSYM_JAC(3) HSYM_JAC(4) HSYM_JAC(5) HSYM_JAC(6) HSYM_JAC(7) HSYM_JAC(8)
+            HSYM_JAC(9) HSYM_JAC(10) HSYM_JAC(11) HSYM_JAC(12) HSYM_JAC(13) HSYM_JAC(14) HSYM_JAC(15) HSYM_JAC(16)
+#undef HSYM_JAC
+            default: fail(HSYM_E_INVALID_ARG, "block width must be 1..16");
+        }
     } else if (kind == HSYM_PRECOND_BLOCK64) {
         hipLaunchKernelGGL(k_precond_block64, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, W, H->pre_q,
                            H->pre_lam, mu, delta, n, m);

@@ -88,7 +88,7 @@ int hsym_kernel_rayleigh_ritz(int nblk, int m, const double *A, double *theta, d
         int f = 0;
         HIPCHK(hipMemcpyAsync(&f, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        if (f < 0) fail(HSYM_E_NUMERIC, "Jacobi eigensolver did not converge");
+        if (f < 0) fail(HSYM_E_NUMERIC, "Rayleigh-Ritz eigensolver broke down (non-finite inverse iterate)");
     });
 }
 

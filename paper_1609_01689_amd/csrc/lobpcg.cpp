@@ -20,8 +20,7 @@ namespace hsym {
 struct Status {
     double norms[HSYM_MAX_BLOCK];     // squared column norms of R
     double theta[HSYM_MAX_BLOCK];
-    double evals_all[48];
-    int flags[8];                     // 0: orth deficiency mask, 1: rr sweeps
+    int flags[8];                     // 0: orth deficiency mask, 1: rr bisection rounds
 };
 
 // Orthonormalise V (n x m) against the kb orthonormal blocks B and itself
@@ -168,7 +167,7 @@ struct Lobpcg {
 
     void rayleigh_ritz(int nblk) {
         RRArgs r{};
-        r.gram = gbuf; r.coef = rrcoef; r.theta = st_d->theta; r.evals_all = st_d->evals_all;
+        r.gram = gbuf; r.coef = rrcoef; r.theta = st_d->theta; r.evals_all = nullptr;   // only the m lowest are needed
         r.flag = &st_d->flags[1]; r.nblk = nblk; r.m = m;
         small_rr(&r, 1, s);
     }
@@ -204,8 +203,8 @@ struct Lobpcg {
             rho_[j] = rnorm_[j] / normH;
             if (j < nev) mx = std::max(mx, rho_[j]);
         }
-        if (st_h->flags[1] < 0) fail(HSYM_E_NUMERIC, "Rayleigh-Ritz eigensolver did not converge");
-        rep.rr_sweeps_max = std::max(rep.rr_sweeps_max, st_h->flags[1] - 1);
+        if (st_h->flags[1] < 0) fail(HSYM_E_NUMERIC, "Rayleigh-Ritz eigensolver broke down (non-finite inverse iterate)");
+        rep.rr_rounds_max = std::max(rep.rr_rounds_max, st_h->flags[1] - 1);
         if (o.keep_history && rep.history_len < HSYM_MAX_HISTORY) rep.history[rep.history_len++] = mx;
         for (int j = 0; j < m; j++) { rep.theta[j] = st_h->theta[j]; rep.resnorm[j] = rho_[j]; }
         rep.iters = it;

@@ -3,8 +3,9 @@
 //   - Cholesky-QR coefficient matrices for orthonormalising W (Section 3.1:
 //     orthogonalisation of the search space, step 7 of Algorithm 1);
 //   - the Rayleigh-Ritz eigenproblem of eq. 9 on an orthonormal basis, solved
-//     by cyclic Jacobi rotations with the round-robin parallel ordering
-//     (Golub and Van Loan, Matrix Computations, Sections 8.5.2 and 8.5.4).
+//     by Householder tridiagonalisation, Sturm-count bisection and inverse
+//     iteration (Golub and Van Loan, Matrix Computations, Sections 8.3.1,
+//     8.4.1 and 8.2.2).
 #include "dense.h"
 
 namespace hsym {
@@ -16,39 +17,6 @@ struct Batch {
     A a[32];
     int count;
 };
-
-// In-place Cholesky of the m x m SPD matrix s (row-major, lower factor kept),
-// single thread.  Returns -1 on success or the first failing column.
-__device__ int chol_lower(double *s, int ld, int m) {
-    double dmax = 0.0;
-    for (int j = 0; j < m; j++) dmax = fmax(dmax, fabs(s[j * ld + j]));
-    for (int j = 0; j < m; j++) {
-        double d = s[j * ld + j];
-        for (int k = 0; k < j; k++) d -= s[j * ld + k] * s[j * ld + k];
-        if (!(d > 1e-14 * dmax) || !isfinite(d)) return j;
-        d = sqrt(d);
-        s[j * ld + j] = d;
-        for (int i = j + 1; i < m; i++) {
-            double v = s[i * ld + j];
-            for (int k = 0; k < j; k++) v -= s[i * ld + k] * s[j * ld + k];
-            s[i * ld + j] = v / d;
-        }
-    }
-    return -1;
-}
-
-// Linv = L^{-1} (lower triangular), single thread
-__device__ void tri_inv_lower(const double *L, int ld, double *Li, int ldi, int m) {
-    for (int j = 0; j < m; j++) {
-        Li[j * ldi + j] = 1.0 / L[j * ld + j];
-        for (int i = j + 1; i < m; i++) {
-            double s = 0.0;
-            for (int k = j; k < i; k++) s += L[i * ld + k] * Li[k * ldi + j];
-            Li[i * ldi + j] = -s / L[i * ld + i];
-        }
-        for (int i = 0; i < j; i++) Li[i * ldi + j] = 0.0;
-    }
-}
 
 __global__ __launch_bounds__(256) void k_small_orth(Batch<OrthArgs> b) {
     __shared__ double S[16][17], Li[16][17];
@@ -154,213 +122,512 @@ void small_orth(const OrthArgs *a, int count, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Rayleigh-Ritz: parallel cyclic Jacobi on k x k (k <= 48)
+// Rayleigh-Ritz on k x k (k <= 48), one workgroup of 256 threads:
+//   1. Householder reduction to tridiagonal form T = Q^T A Q (Golub and Van
+//      Loan, Section 8.3.1), a quad of lanes per row for A22 v and the
+//      rank-2 update, reflectors kept for step 4;
+//   2. eigenvalues of T by multisection on Sturm counts (Section 8.4.1): a
+//      group of lanes per eigenvalue evaluates the count at one point each
+//      per round; the m lowest, or all k when they are asked for;
+//   3. eigenvectors of T for the m lowest eigenvalues by inverse iteration
+//      with a partially pivoted tridiagonal LU, one lane per vector; where
+//      eigenvalues cluster (gap below 1e-3 of the norm of T, the rule of
+//      LAPACK's stein) the vectors are orthogonalised by Cholesky-QR, refined
+//      by one more solve and orthogonalised again;
+//   4. back-transformation C_X = Q Y, 16 lanes per vector.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
-    __shared__ double A[2][KMAX][KMAX + 1];
-    __shared__ double V[2][KMAX][KMAX + 1];
-    __shared__ double cj[KMAX + 1], sj[KMAX + 1];   // rotation of the pair index x belongs to
-    __shared__ double fro;
-    __shared__ int nrot;
-    __shared__ int perm[KMAX];
-    __shared__ double ev[KMAX];
-    __shared__ double Z[KMAX][17];
-    __shared__ double dq[16];
-    const RRArgs a = b.a[blockIdx.x];
-    const int m = a.m, k = a.nblk * m;
-    const int kp = (k + 1) & ~1;          // even number of players (one dummy if k is odd)
-    const int km = kp - 1;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < k * k; e += 256) {
-        int i = e / k, j = e - (e / k) * k;
-        A[0][i][j] = 0.5 * (a.gram[i * k + j] + a.gram[j * k + i]);
-        V[0][i][j] = (i == j) ? 1.0 : 0.0;
-    }
-    if (tid == 0) fro = 0.0;
-    __syncthreads();
-    if (tid < 64) {
-        double f = 0.0;
-        for (int e = tid; e < k * k; e += 64) f += A[0][e / k][e % k] * A[0][e / k][e % k];
-        for (int off = 32; off > 0; off >>= 1) f += __shfl_down(f, off, 64);
-        if (tid == 0) fro = f;
-    }
-    __syncthreads();
-    // a rotation is applied when the off-diagonal entry is above this level
-    // (above the rounding floor of the rotations themselves, about k u ||A||);
-    // a sweep that applies none ends the iteration
-    const double tiny = 1e-14 * sqrt(fro) + 1e-300;
-    int cur = 0, sweeps = 0;
-    for (; sweeps < 40; sweeps++) {
-        if (tid == 0) nrot = 0;
-        __syncthreads();
-        for (int r = 0; r < km; r++) {
-            // circle-method pairing of round r: the fixed player km meets r, every
-            // other x meets (2r - x) mod km
-            if (tid < kp / 2) {
-                int p, q;
-                if (tid == 0) { p = km; q = r; }
-                else { p = (r + tid) % km; q = (r - tid + km) % km; }
-                if (p > q) { int t = p; p = q; q = t; }
-                double c = 1.0, sn = 0.0;
-                if (q < k) {
-                    double apq = A[cur][p][q];
-                    if (fabs(apq) > tiny) {
-                        double tau = (A[cur][q][q] - A[cur][p][p]) / (2.0 * apq);
-                        double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        sn = t * c;
-                        atomicAdd(&nrot, 1);
-                    }
-                }
-                // column p of J is (c at p, -s at q); column q is (s at p, c at q)
-                cj[p] = c; sj[p] = -sn;
-                cj[q] = c; sj[q] = sn;
-            }
-            __syncthreads();
-            const int nx = cur ^ 1;
-            // lanes own columns y, the four waves split the rows x: no integer
-            // division in the loop (partner(y) = 2r - y wrapped into [0, km))
-            const int y = tid & 63, xg = tid >> 6;
-            if (y < k) {
-                int yb = (y == km) ? r : (y == r ? km : 2 * r - y);
-                if (yb < 0) yb += km;
-                else if (yb >= km && y != r) yb -= km;
-                const bool ybk = yb < k;
-                const double cy = cj[y], sy = sj[y];
-                // V' = V J: rows x = xg + 4 it, loads issued before the stores
-                double v0[KMAX / 4], v1[KMAX / 4];
+// Cross-lane moves of a double through DPP (no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+// Sums over a quad / a row of 16 lanes / the wave.  Every lane receives the
+// bitwise identical sum (each butterfly step adds the same two operands, in
+// either order).  Called with the whole wave active.
+__device__ __forceinline__ double quad_sum(double v) {
+    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    return v;
+}
+__device__ __forceinline__ double row_sum(double v) {
+    v = quad_sum(v);
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+    v = row_sum(v);
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// Number of eigenvalues of the (scaled, |d|, |e| <= 1) tridiagonal T below x:
+// the number of negative pivots q_i = p_i / p_{i-1} of the LDL^T
+// factorisation of T - xI, carried division-free as the pair (p_i, p_{i-1})
+// of leading principal minors, p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2},
+// rescaled by a power of two every 4 steps.  A pivot of magnitude below PIV
+// is replaced by -PIV (the LAPACK bisection convention), which also keeps
+// every p_i nonzero and each step's growth within 2^62.
+__device__ __forceinline__ int sturm_count(const double *d, const double *e2, int k, double x) {
+    constexpr double PIV = 0x1p-60;
+    double p = d[0] - x, q = 1.0;
+    if (fabs(p) < PIV) p = -PIV;
+    int n = p < 0.0;
+    // steps 1 .. k-1 in chunks of 4; the arrays are padded past k with
+    // d = 4, e^2 = 0, steps that keep the sign (x lies in [-1.01, 1.01])
+    for (int i0 = 1; i0 < k; i0 += 4) {
+        double dd[4], ee[4];
 #pragma unroll
-                for (int it = 0; it < KMAX / 4; it++) {
-                    const int x = xg + 4 * it;
-                    v0[it] = (x < k) ? V[cur][x][y] : 0.0;
-                    v1[it] = (x < k && ybk) ? V[cur][x][yb] : 0.0;
-                }
+        for (int t = 0; t < 4; t++) { dd[t] = d[i0 + t]; ee[t] = e2[i0 + t - 1]; }
 #pragma unroll
-                for (int it = 0; it < KMAX / 4; it++) {
-                    const int x = xg + 4 * it;
-                    if (x < k) V[nx][x][y] = cy * v0[it] + sy * v1[it];
-                }
-                // A' = J^T A J on the upper triangle (x <= y), mirrored: A stays exactly
-                // symmetric (rotations cannot remove an antisymmetric rounding part)
-#pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    double a0[KMAX / 8], a1[KMAX / 8], a2[KMAX / 8], a3[KMAX / 8], cx[KMAX / 8], sx[KMAX / 8];
-#pragma unroll
-                    for (int it = 0; it < KMAX / 8; it++) {
-                        const int x = xg + 4 * (it + h * (KMAX / 8));
-                        int xb = (x == km) ? r : (x == r ? km : 2 * r - x);
-                        if (xb < 0) xb += km;
-                        else if (xb >= km && x != r) xb -= km;
-                        const bool ok = x <= y, xbk = ok && xb < k;
-                        a0[it] = ok ? A[cur][x][y] : 0.0;
-                        a1[it] = (ok && ybk) ? A[cur][x][yb] : 0.0;
-                        a2[it] = xbk ? A[cur][xb][y] : 0.0;
-                        a3[it] = (xbk && ybk) ? A[cur][xb][yb] : 0.0;
-                        cx[it] = ok ? cj[x] : 0.0;
-                        sx[it] = ok ? sj[x] : 0.0;
-                    }
-#pragma unroll
-                    for (int it = 0; it < KMAX / 8; it++) {
-                        const int x = xg + 4 * (it + h * (KMAX / 8));
-                        if (x <= y) {
-                            const double v = cx[it] * cy * a0[it] + cx[it] * sy * a1[it] + sx[it] * cy * a2[it] +
-                                             sx[it] * sy * a3[it];
-                            A[nx][x][y] = v;
-                            A[nx][y][x] = v;
-                        }
-                    }
-                }
-            }
-            cur = nx;
-            __syncthreads();
+        for (int t = 0; t < 4; t++) {
+            double tt = fma(dd[t] - x, p, -ee[t] * q);
+            if (fabs(tt) < PIV * fabs(p)) tt = -PIV * p;
+            n += (tt < 0.0) != (p < 0.0);
+            q = p;
+            p = tt;
         }
-        const int none = (nrot == 0);
-        __syncthreads();      // every thread has read nrot before it is reset
-        if (none) break;
+        const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(p), fabs(q)));
+        p = __builtin_amdgcn_ldexp(p, -ex);
+        q = __builtin_amdgcn_ldexp(q, -ex);
     }
-    // ascending order by rank (ties by index)
-    if (tid < k) ev[tid] = A[cur][tid][tid];
+    return n;
+}
+
+// nit steps of inverse iteration on column c of Y with the factors of T - lam_c I
+// (inverse pivots in Fd, multipliers in Fl, row swaps in piv), normalising
+// after each solve.
+__device__ void inv_iter(int c, int k, int nit, const double (*Fd)[17], const double (*Fu)[17],
+                         const double (*Fu2)[17], const double (*Fl)[17], const unsigned char (*piv)[17],
+                         double (*Y)[17], int *bad) {
+    for (int it = 0; it < nit; it++) {
+        double cur = Y[0][c];
+#pragma unroll 4
+        for (int i = 0; i + 1 < k; i++) {
+            double nxt = Y[i + 1][c];
+            if (piv[i][c]) { const double t = cur; cur = nxt; nxt = t; }
+            Y[i][c] = cur;
+            cur = fma(-Fl[i][c], cur, nxt);
+        }
+        double y1 = cur * Fd[k - 1][c], y2 = 0.0;
+        double nn = y1 * y1;
+        Y[k - 1][c] = y1;
+#pragma unroll 4
+        for (int i = k - 2; i >= 0; i--) {
+            const double yi = (Y[i][c] - Fu[i][c] * y1 - Fu2[i][c] * y2) * Fd[i][c];
+            Y[i][c] = yi;
+            nn = fma(yi, yi, nn);
+            y2 = y1;
+            y1 = yi;
+        }
+        if (!(nn > 0.0) || !isfinite(nn)) { *bad = 1; return; }
+        const double inv = 1.0 / sqrt(nn);
+#pragma unroll 4
+        for (int i = 0; i < k; i++) Y[i][c] *= inv;
+    }
+}
+
+// One Cholesky-QR pass on the m columns of V (k x m, V[i][c]), whole
+// workgroup: with S = diag(G)^{-1/2} and G = V^T V, factor S G S + shift I =
+// L L^T and set V <- V S L^{-T}.  Leaves the smallest pivot of the scaled
+// factorisation (the squared sine of the smallest angle between a column and
+// the span of the ones before it, plus shift) in sh[32].  sh holds >= 33
+// doubles, G >= 16 x 17.
+__device__ void wg_cholqr(double (*V)[17], int k, int m, double shift, double (*G)[17], double *sh) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    {
+        const int q = tid >> 4, c = tid & 15;
+        if (q < m && c <= q) {
+            double s = 0.0;
+#pragma unroll 8
+            for (int i = 0; i < k; i++) s = fma(V[i][q], V[i][c], s);
+            G[q][c] = s;
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        const double gd = lane < m ? G[lane][lane] : 0.0;
+        const double sc = gd > 0.0 ? 1.0 / sqrt(gd) : 0.0;
+        double g[16];
+#pragma unroll
+        for (int c = 0; c < 16; c++) {
+            const double scc = read_lane(sc, c);
+            g[c] = (lane < m && c < m && c <= lane) ? G[lane][c] * sc * scc + (c == lane ? shift : 0.0) : 0.0;
+        }
+        double minp = 1e300;
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            if (j < m) {
+                const double pj = read_lane(g[j], j);
+                minp = fmin(minp, pj);
+                const double dj = sqrt(fmax(pj, 1e-300));
+                const double rj = 1.0 / dj;
+                const double l = (lane == j) ? dj : g[j] * rj;
+                g[j] = l;
+#pragma unroll
+                for (int c = j + 1; c < 16; c++) {
+                    if (c < m) {
+                        const double lc = read_lane(l, c);
+                        if (lane >= c) g[c] = fma(-l, lc, g[c]);
+                    }
+                }
+                if (lane == j) sh[j] = rj;
+            }
+        }
+        if (lane < m) {
+#pragma unroll
+            for (int c = 0; c < 16; c++)
+                if (c <= lane) G[lane][c] = g[c];
+            sh[16 + lane] = sc;
+        }
+        if (lane == 0) sh[32] = minp;
+    }
     __syncthreads();
     if (tid < k) {
-        int rank = 0;
-        double v = ev[tid];
-        for (int j = 0; j < k; j++) rank += (ev[j] < v) || (ev[j] == v && j < tid);
-        perm[rank] = tid;
+        double x[16];
+#pragma unroll
+        for (int c = 0; c < 16; c++) {
+            if (c < m) {
+                double v = V[tid][c] * sh[16 + c];
+#pragma unroll
+                for (int q = 0; q < c; q++) v = fma(-x[q], G[c][q], v);
+                x[c] = v * sh[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 16; c++)
+            if (c < m) V[tid][c] = x[c];
     }
-    if (tid == 0) a.flag[0] = sweeps < 40 ? sweeps + 1 : -1;
     __syncthreads();
-    if (tid < k) a.evals_all[tid] = ev[perm[tid]];
-    if (tid < m) a.theta[tid] = ev[perm[tid]];
-    // C_X = first m sorted eigenvectors
-    for (int e = tid; e < k * m; e += 256) {
-        int i = e / m, j = e - (e / m) * m;
-        a.coef[i * 2 * m + j] = V[cur][i][perm[j]];
+}
+
+// Z <- Z - Y (Y^T Z) for the m columns of Y and Z (k rows), whole workgroup.
+__device__ void proj_out(double (*Z)[17], const double (*Y)[17], int k, int m, double (*G)[17]) {
+    const int tid = threadIdx.x;
+    {
+        const int q = tid >> 4, j = tid & 15;
+        if (q < m && j < m) {
+            double s = 0.0;
+#pragma unroll 8
+            for (int i = 0; i < k; i++) s = fma(Y[i][q], Z[i][j], s);
+            G[q][j] = s;
+        }
     }
-    // Z = C_rest^T Y, Y = C_X with its X rows zeroed; (k-m) x m
+    __syncthreads();
+    for (int e0 = tid; e0 < KMAX * 16; e0 += 256) {
+        const int i = e0 >> 4, j = e0 & 15;
+        if (i < k && j < m) {
+            double v = Z[i][j];
+            for (int q = 0; q < m; q++) v = fma(-Y[i][q], G[q][j], v);
+            Z[i][j] = v;
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
+    __shared__ double A[KMAX][KMAX + 1];      // lower part: reflector vectors
+    __shared__ double beta[KMAX], d[KMAX], e[KMAX], ds[KMAX + 4], e2s[KMAX + 4], lam[KMAX];
+    __shared__ double pv[64];
+    __shared__ double Y[KMAX][17];            // Y[i][c]: tridiagonal eigenvectors, then C_X
+    __shared__ double Fd[KMAX][17], Fu[KMAX][17], Fu2[KMAX][17], Fl[KMAX][17];
+    __shared__ unsigned char piv[KMAX][17];
+    __shared__ double Z[KMAX][17];
+    __shared__ double G[16][17];
+    __shared__ double sh[40];
+    __shared__ int bad, nrounds;
+    const RRArgs a = b.a[blockIdx.x];
+    const int m = a.m, k = a.nblk * m;
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int e0 = tid; e0 < k * k; e0 += 256) {
+        const int i = e0 / k, j = e0 - (e0 / k) * k;
+        A[i][j] = 0.5 * (a.gram[i * k + j] + a.gram[j * k + i]);
+    }
+    if (tid == 0) { bad = 0; nrounds = 0; }
+    __syncthreads();
+    // 1. tridiagonalisation; the arithmetic deciding each reflector is
+    // repeated identically in every wave, so no broadcast is needed
+    {
+        const int qi = tid >> 2, qp = tid & 3;
+        for (int j = 0; j + 2 < k; j++) {
+            const int len = k - j - 1;   // x = A[j+1 .. k-1][j]
+            const double xl = lane < len ? A[j + 1 + lane][j] : 0.0;
+            const double nrm2 = wave_sum(xl * xl);
+            const double x0 = A[j + 1][j];
+            double alpha = 0.0, bt = 0.0;
+            if (nrm2 > 0.0) {
+                const double nrm = sqrt(nrm2);
+                alpha = x0 >= 0 ? -nrm : nrm;
+                bt = 1.0 / (nrm2 - alpha * x0);    // 2 / v.v with v.v = 2 (nrm2 - alpha x0)
+            }
+            if (tid == 0) { beta[j] = bt; e[j] = alpha; }
+            if (bt == 0.0) continue;                // x = 0: nothing to annihilate
+            // v = x - alpha e_1 (read from column j, first entry corrected on the fly)
+            // p = beta A22 v, a quad of lanes per row
+            // rows and columns past len are clamped to len-1 so that every
+            // load is in bounds and can be issued ahead; their terms are masked
+            const int rc = qi < len ? qi : len - 1;
+            double vl[12], al[12];
+#pragma unroll
+            for (int t = 0; t < 12; t++) {
+                const int l = qp + 4 * t, lc = l < len ? l : len - 1;
+                vl[t] = l < len ? A[j + 1 + lc][j] - (l == 0 ? alpha : 0.0) : 0.0;
+                al[t] = A[j + 1 + rc][j + 1 + lc];
+            }
+            double pi = 0.0;
+#pragma unroll
+            for (int t = 0; t < 12; t++) pi = fma(al[t], vl[t], pi);
+            pi = quad_sum(pi);
+            if (qp == 0 && qi < len) pv[qi] = bt * pi;
+            __syncthreads();
+            // w = p - (beta/2)(v.p) v;  A22 -= v w^T + w v^T (exactly symmetric)
+            const double vlane = lane < len ? A[j + 1 + lane][j] - (lane == 0 ? alpha : 0.0) : 0.0;
+            const double vp = wave_sum(lane < len ? vlane * pv[lane] : 0.0);
+            const double half = 0.5 * bt * vp;
+            const double vi = A[j + 1 + rc][j] - (rc == 0 ? alpha : 0.0);
+            const double wi = fma(-half, vi, pv[rc]);
+            double wl[12];
+#pragma unroll
+            for (int t = 0; t < 12; t++) {
+                const int l = qp + 4 * t, lc = l < len ? l : len - 1;
+                wl[t] = fma(-half, vl[t], pv[lc]);
+            }
+            if (qi < len) {
+#pragma unroll
+                for (int t = 0; t < 12; t++) {
+                    const int l = qp + 4 * t;
+                    const double upd = __dadd_rn(__dmul_rn(vi, wl[t]), __dmul_rn(wi, vl[t]));
+                    if (l < len) A[j + 1 + qi][j + 1 + l] = al[t] - upd;
+                }
+            }
+            __syncthreads();
+            if (tid == 0) A[j + 1][j] = x0 - alpha;  // store v (column j is not read again until step 4)
+        }
+    }
+    __syncthreads();
+    if (tid < k) d[tid] = A[tid][tid];
+    if (tid == 0) {
+        if (k >= 2) e[k - 2] = A[k - 1][k - 2];
+        e[k - 1] = 0.0;
+        for (int j = (k >= 2 ? k - 2 : 0); j < k; j++) beta[j] = 0.0;
+    }
+    __syncthreads();
+    // Gershgorin interval and the power-of-two scale that brings T into [-1, 1]
+    double glo = d[0], ghi = d[0];
+    for (int i = 0; i < k; i++) {
+        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + fabs(e[i]);
+        glo = fmin(glo, d[i] - r);
+        ghi = fmax(ghi, d[i] + r);
+    }
+    const double tnorm = fmax(fabs(glo), fabs(ghi));
+    const int tex = __builtin_amdgcn_frexp_exp(tnorm + 1e-300);
+    if (tid < KMAX + 4) {
+        const double es = tid < k ? __builtin_amdgcn_ldexp(e[tid], -tex) : 0.0;
+        ds[tid] = tid < k ? __builtin_amdgcn_ldexp(d[tid], -tex) : 4.0;
+        e2s[tid] = es * es;
+    }
+    __syncthreads();
+    // 2. eigenvalues: NG lanes per eigenvalue, one point per lane per round
+    const int ne = a.evals_all ? k : m;
+    {
+        const int NG = ne <= 16 ? 16 : (ne <= 32 ? 8 : 4);
+        const int g = tid / NG, lg = tid - g * NG;
+        const int gbase = lane - lg;
+        const unsigned long long gmask = (1ull << NG) - 1ull;
+        double lo = __builtin_amdgcn_ldexp(glo, -tex), hi = __builtin_amdgcn_ldexp(ghi, -tex);
+        const double w0 = fmax(hi - lo, 1e-300);
+        lo -= 1e-12 * w0 + 1e-300;
+        hi += 1e-12 * w0 + 1e-300;
+        const bool act = g < ne;
+        for (int round = 0; round < 64; round++) {
+            const double h = (hi - lo) / (double)(NG + 1);
+            const double x = fma((double)(lg + 1), h, lo);
+            const int cnt = act ? sturm_count(ds, e2s, k, x) : 0;
+            const unsigned long long bal = __ballot(act && cnt > g);
+            const unsigned long long msk = (bal >> gbase) & gmask;
+            if (msk == 0ull) {
+                lo = fma((double)NG, h, lo);
+            } else {
+                const int s = __builtin_ctzll(msk);
+                const double nlo = s == 0 ? lo : fma((double)s, h, lo);
+                hi = fma((double)(s + 1), h, lo);
+                lo = nlo;
+            }
+            // stop when every bracket is at rounding level (uniform across the workgroup)
+            const int more = act && (hi - lo) > 2.2e-16 * (fabs(lo) + fabs(hi)) + 1e-17;
+            if (tid == 0) nrounds = round + 1;
+            if (__syncthreads_or(more) == 0) break;
+        }
+        if (act && lg == 0) lam[g] = __builtin_amdgcn_ldexp(0.5 * (lo + hi), tex);
+    }
+    __syncthreads();
+    bool clustered = false;
+    for (int c = 1; c < m; c++) clustered |= (lam[c] - lam[c - 1] <= 1e-3 * tnorm);
+    // 3. inverse iteration for the m lowest eigenvectors of T, one lane each
+    if (tid < m) {
+        const int c = tid;
+        const double tiny = 1e-300 + 2.2e-16 * tnorm;
+        const double sigma = lam[c];
+        double dcur = d[0] - sigma, ucur = k > 1 ? e[0] : 0.0;
+        for (int i = 0; i + 1 < k; i++) {
+            const double li = e[i];
+            const double dn = d[i + 1] - sigma;
+            const double un = (i + 2 < k) ? e[i + 1] : 0.0;
+            if (fabs(dcur) >= fabs(li)) {
+                const double r = 1.0 / (dcur == 0.0 ? tiny : dcur);
+                const double l = li * r;
+                Fd[i][c] = r; Fl[i][c] = l; Fu[i][c] = ucur; Fu2[i][c] = 0.0; piv[i][c] = 0;
+                dcur = fma(-l, ucur, dn);
+                ucur = un;
+            } else {
+                const double r = 1.0 / li;
+                const double l = dcur * r;
+                Fd[i][c] = r; Fl[i][c] = l; Fu[i][c] = dn; Fu2[i][c] = un; piv[i][c] = 1;
+                dcur = fma(-l, dn, ucur);
+                ucur = -l * un;
+            }
+        }
+        Fd[k - 1][c] = 1.0 / (dcur == 0.0 ? tiny : dcur);
+        // distinct pseudo-random start vectors (hash of index and lane)
+        for (int i = 0; i < k; i++) {
+            unsigned h = (unsigned)(i * 2654435761u) ^ (unsigned)((c + 1) * 40503u);
+            h ^= h >> 15; h *= 2246822519u; h ^= h >> 13;
+            Y[i][c] = ((double)(h & 0xffff) - 32767.5) / 32768.0;
+        }
+        inv_iter(c, k, clustered ? 2 : 3, Fd, Fu, Fu2, Fl, piv, Y, &bad);
+    }
+    __syncthreads();
+    if (clustered) {
+        // shifted Cholesky-QR first (never breaks down), then plain; the
+        // refinement solve removes what the orthogonalisation amplified
+        // outside each cluster, and a last pass restores orthogonality
+        wg_cholqr(Y, k, m, 2e-11, G, sh);
+        wg_cholqr(Y, k, m, 0.0, G, sh);
+        if (tid < m) inv_iter(tid, k, 1, Fd, Fu, Fu2, Fl, piv, Y, &bad);
+        __syncthreads();
+        wg_cholqr(Y, k, m, 0.0, G, sh);
+    }
+    // 4. back-transformation x = H_0 H_1 ... H_{k-3} y, 16 lanes per vector
+    {
+        const int c = tid >> 4, r = tid & 15;
+        const bool own = c < m;
+        double y0 = (own && r < k) ? Y[r][c] : 0.0;
+        double y1 = (own && r + 16 < k) ? Y[r + 16][c] : 0.0;
+        double y2 = (own && r + 32 < k) ? Y[r + 32][c] : 0.0;
+        for (int j = k - 3; j >= 0; j--) {
+            const double bt = beta[j];
+            if (bt == 0.0) continue;
+            const double a0 = (r > j && r < k) ? A[r][j] : 0.0;
+            const double a1 = (r + 16 > j && r + 16 < k) ? A[r + 16][j] : 0.0;
+            const double a2 = (r + 32 > j && r + 32 < k) ? A[r + 32][j] : 0.0;
+            const double s = bt * row_sum(fma(a0, y0, fma(a1, y1, a2 * y2)));
+            y0 = fma(-s, a0, y0);
+            y1 = fma(-s, a1, y1);
+            y2 = fma(-s, a2, y2);
+        }
+        __syncthreads();
+        if (own) {
+            if (r < k) Y[r][c] = y0;
+            if (r + 16 < k) Y[r + 16][c] = y1;
+            if (r + 32 < k) Y[r + 32][c] = y2;
+        }
+    }
+    if (tid < ne) {
+        if (a.evals_all) a.evals_all[tid] = lam[tid];
+        if (tid < m) a.theta[tid] = lam[tid];
+    }
+    __syncthreads();
+    if (tid == 0) a.flag[0] = bad ? -1 : 1 + nrounds;
+    for (int e0 = tid; e0 < k * m; e0 += 256) {
+        const int i = e0 / m, j = e0 - (e0 / m) * m;
+        a.coef[i * 2 * m + j] = Y[i][j];
+    }
+    // Next search direction in coefficient space: the W,P-components of C_X,
+    // made orthogonal to C_X and orthonormal (span{C_X, C_P} = span{C_X, Y}
+    // with Y = C_X with its X rows zeroed).
     const int kr = k - m;
     if (kr == 0) {          // Rayleigh-Ritz on X alone: no search direction yet
-        for (int e = tid; e < k * m; e += 256) {
-            int i = e / m, j = e - (e / m) * m;
+        for (int e0 = tid; e0 < k * m; e0 += 256) {
+            const int i = e0 / m, j = e0 - (e0 / m) * m;
             a.coef[i * 2 * m + m + j] = 0.0;
         }
         return;
     }
-    for (int e = tid; e < kr * m; e += 256) {
-        int i = e / m, j = e - (e / m) * m;
-        double s = 0.0;
-        for (int t = m; t < k; t++) s += V[cur][t][perm[m + i]] * V[cur][t][perm[j]];
-        Z[i][j] = s;
+    for (int e0 = tid; e0 < KMAX * 16; e0 += 256) {
+        const int i = e0 >> 4, j = e0 & 15;
+        if (i < k && j < m) Z[i][j] = i < m ? 0.0 : Y[i][j];
     }
     __syncthreads();
-    // modified Gram-Schmidt on the columns of Z, two passes; a vanishing column
-    // is replaced by a unit vector
-    int next_unit = 0;
-    for (int j = 0; j < m; j++) {
-        double n0 = 0.0;
-        if (tid == 0) {
-            for (int i = 0; i < kr; i++) n0 += Z[i][j] * Z[i][j];
-            dq[0] = sqrt(n0);
+    proj_out(Z, Y, k, m, G);
+    proj_out(Z, Y, k, m, G);
+    // Cholesky-QR twice (re-projected in between) unless some column is
+    // (nearly) dependent on the others: then modified Gram-Schmidt with
+    // replacement of vanishing columns
+    wg_cholqr(Z, k, m, 0.0, G, sh);
+    const bool deficient = !(sh[32] > 1e-14);
+    __syncthreads();
+    if (!deficient) {
+        proj_out(Z, Y, k, m, G);
+        wg_cholqr(Z, k, m, 0.0, G, sh);
+    } else {
+        for (int e0 = tid; e0 < KMAX * 16; e0 += 256) {
+            const int i = e0 >> 4, j = e0 & 15;
+            if (i < k && j < m) Z[i][j] = i < m ? 0.0 : Y[i][j];
         }
         __syncthreads();
-        n0 = dq[0];
-        __syncthreads();
-        for (int attempt = 0; attempt < 4; attempt++) {
-            for (int pass = 0; pass < 2; pass++) {
-                if (tid < j) {
-                    double d = 0.0;
-                    for (int i = 0; i < kr; i++) d += Z[i][tid] * Z[i][j];
-                    dq[tid] = d;
-                }
-                __syncthreads();
-                if (tid < kr) {
-                    double v = Z[tid][j];
-                    for (int q = 0; q < j; q++) v -= dq[q] * Z[tid][q];
-                    Z[tid][j] = v;
-                }
-                __syncthreads();
-            }
-            __shared__ double nn_s;
-            if (tid == 0) {
-                double nn = 0.0;
-                for (int i = 0; i < kr; i++) nn += Z[i][j] * Z[i][j];
-                nn_s = sqrt(nn);
+        proj_out(Z, Y, k, m, G);
+        proj_out(Z, Y, k, m, G);
+        int next_unit = m;
+        for (int j = 0; j < m; j++) {
+            if (tid < 64) {
+                const double z = lane < k ? Z[lane][j] : 0.0;
+                const double n0 = wave_sum(z * z);
+                if (lane == 0) sh[0] = sqrt(n0);
             }
             __syncthreads();
-            double nn = nn_s;
-            bool ok = nn > 1e-12 * n0 && nn > 1e-300;
-            if (tid < kr) Z[tid][j] = ok ? Z[tid][j] / nn : ((tid == (next_unit % kr)) ? 1.0 : 0.0);
-            __syncthreads();
-            if (ok) break;
-            next_unit++;
-            n0 = 1.0;
+            double n0 = sh[0];
+            for (int attempt = 0; attempt < 4; attempt++) {
+                for (int pass = 0; pass < 2; pass++) {
+                    if (tid < j + m) {
+                        // against the previous Z columns (tid < j) and C_X (j <= tid < j + m)
+                        double dsum = 0.0;
+                        if (tid < j) for (int i = 0; i < k; i++) dsum = fma(Z[i][tid], Z[i][j], dsum);
+                        else for (int i = 0; i < k; i++) dsum = fma(Y[i][tid - j], Z[i][j], dsum);
+                        pv[tid] = dsum;
+                    }
+                    __syncthreads();
+                    if (tid < k) {
+                        double v = Z[tid][j];
+                        for (int q = 0; q < j; q++) v -= pv[q] * Z[tid][q];
+                        for (int q = 0; q < m; q++) v -= pv[j + q] * Y[tid][q];
+                        Z[tid][j] = v;
+                    }
+                    __syncthreads();
+                }
+                if (tid < 64) {
+                    const double z = lane < k ? Z[lane][j] : 0.0;
+                    const double nn = wave_sum(z * z);
+                    if (lane == 0) sh[1] = sqrt(nn);
+                }
+                __syncthreads();
+                const double nn = sh[1];
+                const bool ok = nn > 1e-12 * n0 && nn > 1e-300;
+                if (tid < k) Z[tid][j] = ok ? Z[tid][j] / nn : ((tid == next_unit) ? 1.0 : 0.0);
+                __syncthreads();
+                if (ok) break;
+                next_unit = (next_unit + 1 < k) ? next_unit + 1 : m;
+                n0 = 1.0;
+            }
         }
     }
-    // C_P = C_rest Z
-    for (int e = tid; e < k * m; e += 256) {
-        int i = e / m, j = e - (e / m) * m;
-        double s = 0.0;
-        for (int t = 0; t < kr; t++) s += V[cur][i][perm[m + t]] * Z[t][j];
-        a.coef[i * 2 * m + m + j] = s;
+    for (int e0 = tid; e0 < k * m; e0 += 256) {
+        const int i = e0 / m, j = e0 - (e0 / m) * m;
+        a.coef[i * 2 * m + m + j] = Z[i][j];
     }
 }
 
