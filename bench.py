@@ -58,6 +58,56 @@ def time_spmm(hs, torch, M, m, reps, dtype):
     return e0.elapsed_time(e1) / reps
 
 
+def serving(hs, torch, count, seed=5):
+    """Request-loop measurement on a stream of CI-shaped requests: n
+    log-uniform in [1e3, 2e6], N = 40, nev ~ U{1..8}, m = 8, tol 1e-6, Jacobi.
+    Baseline: the same requests solved one at a time in arrival order with
+    fp64 storage (service time = build + solve + free, measured); arrivals
+    are Poisson at twice the baseline's solves/s.  The request loop serves
+    the trace with fp32 storage (mixed form) on the device."""
+    import hsymgen
+    rng = np.random.default_rng(seed)
+    ns = np.round(10 ** rng.uniform(3, np.log10(2e6), count)).astype(np.int64)
+    nevs = rng.integers(1, 9, count)
+    t = time.perf_counter()
+    mats = [hsymgen.generate(int(n), 40, 1000 + r) for r, n in enumerate(ns)]
+    log("serving: generated %d requests (%.0fM stored entries) in %.1fs" %
+        (count, sum(A.nnz for A in mats) / 1e6, time.perf_counter() - t))
+    svc = []
+    for r, A in enumerate(mats):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        M = hs.Matrix(A, storage=hs.HSYM_FP64, geom_m=8)
+        st, ev, rep = hs.lobpcg_solve(M.h, int(nevs[r]), 8, 1e-6, precond="jacobi",
+                                      opts=hs.default_lobpcg_opts(seed=1000 + r, keep_history=0))
+        M.close()
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t)
+    svc = np.array(svc)
+    rate = 2.0 * count / svc.sum()
+    arr = np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, count))
+    fin = np.zeros(count)
+    prev = 0.0
+    for r in range(count):
+        prev = max(arr[r], prev) + svc[r]
+        fin[r] = prev
+    lat_fifo = fin - arr
+    reqs = [{"csr": A, "storage": hs.HSYM_FP32, "nev": int(nevs[r]), "block_width": 8, "precond": "jacobi",
+             "tol": 1e-6, "seed": 1000 + r, "arrival_s": float(arr[r])} for r, A in enumerate(mats)]
+    res, rep = hs.hsym_serve(reqs)
+    lat = np.array([x["latency_s"] for x in res])
+    ok = sum(x["status"] == hs.HSYM_OK for x in res)
+    out = {"requests": count, "arrival_rate_per_s": rate,
+           "fifo_fp64": {"p50_s": float(np.percentile(lat_fifo, 50)), "p99_s": float(np.percentile(lat_fifo, 99)),
+                         "solves_per_s": count / (fin[-1] - arr[0]), "mean_service_s": float(svc.mean())},
+           "request_loop_mixed": {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                                  "solves_per_s": count / rep["wall_s"], "converged": ok,
+                                  "max_active": rep["max_active_seen"], "rounds": rep["rounds"],
+                                  "peak_reserved_GB": rep["peak_reserved_bytes"] / 1e9}}
+    log("serving: %s" % json.dumps(out))
+    return out
+
+
 def cpu_baseline(A, m, nev, tol, gpu_iters, budget_s):
     """The oracle (as it stands) on the same matrix: LOBPCG iterations are run
     for about budget_s seconds and the per-iteration time is scaled to the
@@ -97,6 +147,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=150,
+                    help="requests of the request-loop measurement (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the multi-GPU path is not part of this build "
@@ -179,6 +231,8 @@ def main():
         extras["spmm_fp32"] = {"ms": spmm32_ms, "GB/s": alg32 / spmm32_ms / 1e6,
                                "frac": alg32 / spmm32_ms / 1e6 / HBM_PEAK_GBS}
         Mf.close()
+        if args.serve_requests > 0:
+            extras["serving"] = serving(hs, torch, args.serve_requests)
         log("extras: %s" % json.dumps(extras))
 
     cpu = None

@@ -119,8 +119,11 @@ int hsym_info(hsym_t H, hsym_info_t *out);
  * Y = H X (async).  X, Y device fp64 n x m with leading dimensions ldx, ldy;
  * m in {1..16}.  H is applied from its stored triangle as D X + U X + U^T X
  * (U strictly upper, D the diagonal; Section 4.1: each stored block is used
- * once as itself and once transposed).  With fp32 storage X is rounded to
- * fp32 and products and sums are fp32; Y is returned in fp64.
+ * once as itself and once transposed).  With fp32 storage the values and X
+ * are held in fp32 (X rounded once as it is staged); every product is formed
+ * and summed in fp64 (the product of two fp32 numbers is exact in fp64) and
+ * Y is returned in fp64.  The transposed half is summed with workgroup-local
+ * atomics, so repeated calls agree to rounding, not bitwise.
  * X and Y must not overlap.  Errors: HSYM_E_INVALID_ARG, HSYM_E_DEVICE.
  */
 int spmm_sym(hsym_t H, int m, const double *X, int64_t ldx, double *Y, int64_t ldy,
@@ -201,10 +204,11 @@ int lanczos_solve(hsym_t H, int nev, double tol, const double *v0, const lanczos
 
 /*
  * Context/step form of lobpcg_solve for request loops: a context owns its
- * block vectors on the device; lobpcg_ctx_step advances `count` contexts by
- * up to `iters` iterations each, sharing one launch per phase among
- * contexts whose matrices are small.  A context's arithmetic does not depend
- * on which other contexts are stepped with it.
+ * block vectors on the device and runs on its own stream (created when
+ * stream is NULL); lobpcg_ctx_step advances `count` contexts by up to
+ * `iters` iterations each, issuing each phase for all of them before waiting
+ * on any, so that their kernels overlap on the device.  A context's
+ * arithmetic does not depend on which other contexts are stepped with it.
  */
 int lobpcg_ctx_create(lobpcg_ctx_t *ctx, hsym_t H, int nev, int block_width, double tol,
                       const double *X0, int precond, const lobpcg_opts *opts, void *stream);
@@ -213,6 +217,70 @@ int lobpcg_ctx_status(lobpcg_ctx_t ctx, int *done, double *evals, lobpcg_report 
 int lobpcg_ctx_evecs(lobpcg_ctx_t ctx, double *evecs);
 int64_t lobpcg_ctx_device_bytes(lobpcg_ctx_t ctx);
 int lobpcg_ctx_destroy(lobpcg_ctx_t ctx);
+
+/*
+ * Request loop (serving layer around the solver; the paper runs one solve per
+ * job).  Continuous batching at iteration granularity: requests are admitted
+ * in arrival order while their estimated device memory fits budget_bytes and
+ * fewer than max_active are in flight; a loader thread builds each request's
+ * handle and context; every scheduling round advances all active requests by
+ * iters_per_round iterations (lobpcg_ctx_step), so short requests finish
+ * while long ones run.  A request whose estimate exceeds the budget finishes
+ * at admission with HSYM_E_OUT_OF_MEMORY.
+ *
+ * hsym_request inputs: host upper CSR as for hsym_create (must stay valid
+ * until hsym_serve returns), storage precision, nev <= block_width <= 16,
+ * tol, precond, seed of the Gaussian start block, arrival_s >= 0 (seconds
+ * from the start of the call).  Outputs: status (HSYM_OK, HSYM_NOT_CONVERGED
+ * or an error), iters, evals[0..nev), admit_s and finish_s (same clock),
+ * device_bytes held while active.  Latency = finish_s - arrival_s.
+ */
+typedef struct {
+    int64_t n;
+    const int64_t *rowptr;
+    const int32_t *colind;
+    const void *values;
+    int values_prec;
+    int storage;
+    int nev;
+    int block_width;
+    int precond;
+    double tol;
+    uint64_t seed;
+    double arrival_s;
+    /* outputs */
+    int status;
+    int iters;
+    double evals[HSYM_MAX_BLOCK];
+    double admit_s;
+    double finish_s;
+    int64_t device_bytes;
+} hsym_request;
+
+typedef struct {
+    int64_t budget_bytes;   /* device memory for requests in flight; default 200 GiB */
+    int max_active;         /* requests in flight at most; default 64                */
+    int iters_per_round;    /* iterations per active request per round; default 1   */
+    int maxit;              /* per-request iteration cap; default 1000               */
+} hsym_serve_opts;
+
+typedef struct {
+    double wall_s;                  /* first arrival to last finish              */
+    int rounds;                     /* scheduling rounds that stepped requests   */
+    int max_active_seen;
+    int64_t peak_reserved_bytes;    /* largest sum of admitted estimates         */
+} hsym_serve_report;
+
+void hsym_serve_opts_default(hsym_serve_opts *o);
+/* Runs the whole trace on the current device; returns when every request has
+ * finished.  Errors of single requests are reported in their status. */
+int hsym_serve(hsym_request *reqs, int count, const hsym_serve_opts *opts, hsym_serve_report *rep);
+/* The same scheduler on a virtual clock, without a device: request r takes
+ * iters[r] iterations of iter_s[r] seconds, holds bytes[r], and loads take
+ * load_s each on one loader; a round costs the longest iteration among the
+ * requests it steps.  For checking admission and accounting on the host. */
+int hsym_serve_sim(hsym_request *reqs, int count, const hsym_serve_opts *opts, const int *iters,
+                   const double *iter_s, const int64_t *bytes, double load_s, hsym_serve_report *rep);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *hsym_last_error(void);

@@ -9,7 +9,8 @@ this package does not load the library; the first call does, and it raises
 The functions keep the names of the C ABI in ``include/hsym.h``:
 ``hsym_create``, ``hsym_create_begin/append/finish``, ``hsym_destroy``,
 ``hsym_info``, ``spmm_sym``, ``spmm_sym_f32``, ``lobpcg_solve``,
-``lanczos_solve`` and the ``lobpcg_ctx_*`` step interface.
+``lanczos_solve``, the ``lobpcg_ctx_*`` step interface and the request loop
+``hsym_serve`` / ``hsym_serve_sim``.
 """
 from __future__ import annotations
 
@@ -74,6 +75,25 @@ class lanczos_report(ctypes.Structure):
                 ("spmv_ms", ctypes.c_double), ("orth_ms", ctypes.c_double)]
 
 
+class hsym_request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p),
+                ("values", ctypes.c_void_p), ("values_prec", ctypes.c_int), ("storage", ctypes.c_int),
+                ("nev", ctypes.c_int), ("block_width", ctypes.c_int), ("precond", ctypes.c_int),
+                ("tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("arrival_s", ctypes.c_double),
+                ("status", ctypes.c_int), ("iters", ctypes.c_int), ("evals", ctypes.c_double * MAX_BLOCK),
+                ("admit_s", ctypes.c_double), ("finish_s", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+
+class hsym_serve_opts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("max_active", ctypes.c_int),
+                ("iters_per_round", ctypes.c_int), ("maxit", ctypes.c_int)]
+
+
+class hsym_serve_report(ctypes.Structure):
+    _fields_ = [("wall_s", ctypes.c_double), ("rounds", ctypes.c_int), ("max_active_seen", ctypes.c_int),
+                ("peak_reserved_bytes", ctypes.c_int64)]
+
+
 _lib = None
 _vp, _i64, _int, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
 
@@ -98,6 +118,11 @@ _SIGS = {
     "lobpcg_ctx_evecs": [_vp, _vp],
     "lobpcg_ctx_device_bytes": [_vp],
     "lobpcg_ctx_destroy": [_vp],
+    "hsym_serve_opts_default": [ctypes.POINTER(hsym_serve_opts)],
+    "hsym_serve": [ctypes.POINTER(hsym_request), _int, ctypes.POINTER(hsym_serve_opts),
+                   ctypes.POINTER(hsym_serve_report)],
+    "hsym_serve_sim": [ctypes.POINTER(hsym_request), _int, ctypes.POINTER(hsym_serve_opts), _vp, _vp, _vp, _dbl,
+                       ctypes.POINTER(hsym_serve_report)],
     "hsym_last_error": [],
     # step-level entry points (include/hsym_kernels.h)
     "hsym_kernel_gram": [_i64, _int, _int, _vp, _int, _vp, _vp, _vp],
@@ -128,6 +153,8 @@ def lib():
         L.lobpcg_opts_default.restype = None
     if hasattr(L, "lobpcg_ctx_device_bytes"):
         L.lobpcg_ctx_device_bytes.restype = _i64
+    if hasattr(L, "hsym_serve_opts_default"):
+        L.hsym_serve_opts_default.restype = None
     _lib = L
     return L
 
@@ -313,6 +340,74 @@ def hsym_kernel_orthonormalize(V, B=(), seed=0, stream=None):
     _check(lib().hsym_kernel_orthonormalize(n, m, _dptr(V), len(B), _ptr_array(list(B)) if B else None,
                                             seed, ctypes.byref(rep), _stream(stream)))
     return rep.value
+
+
+def _serve_opts(budget_bytes=0, max_active=0, iters_per_round=0, maxit=0):
+    o = hsym_serve_opts()
+    lib().hsym_serve_opts_default(ctypes.byref(o))
+    if budget_bytes:
+        o.budget_bytes = int(budget_bytes)
+    if max_active:
+        o.max_active = int(max_active)
+    if iters_per_round:
+        o.iters_per_round = int(iters_per_round)
+    if maxit:
+        o.maxit = int(maxit)
+    return o
+
+
+def _serve_results(arr, count, rep):
+    out = []
+    for i in range(count):
+        r = arr[i]
+        out.append({"status": r.status, "iters": r.iters, "evals": np.array(r.evals[:r.nev]),
+                    "arrival_s": r.arrival_s, "admit_s": r.admit_s, "finish_s": r.finish_s,
+                    "latency_s": r.finish_s - r.arrival_s, "device_bytes": r.device_bytes})
+    return out, {f: getattr(rep, f) for f, _ in hsym_serve_report._fields_}
+
+
+def hsym_serve(requests, **opts):
+    """Run a request trace through the device request loop.
+
+    requests: list of dicts with keys csr (hsymgen.UpperCSR-like: n, rowptr,
+    colind, values), storage, nev, block_width, precond, tol, seed,
+    arrival_s.  Returns (per-request result dicts, report dict)."""
+    keep = []
+    arr = (hsym_request * max(1, len(requests)))()
+    for i, q in enumerate(requests):
+        A = q["csr"]
+        rp = np.ascontiguousarray(A.rowptr, np.int64)
+        ci = np.ascontiguousarray(A.colind, np.int32)
+        va = np.ascontiguousarray(A.values)
+        keep += [rp, ci, va]
+        r = arr[i]
+        r.n, r.rowptr, r.colind, r.values = int(A.n), rp.ctypes.data, ci.ctypes.data, va.ctypes.data
+        r.values_prec = HSYM_FP32 if va.dtype == np.float32 else HSYM_FP64
+        r.storage = int(q.get("storage", HSYM_FP64))
+        r.nev, r.block_width = int(q["nev"]), int(q["block_width"])
+        r.precond = PRECOND[q.get("precond", "jacobi")]
+        r.tol, r.seed, r.arrival_s = float(q["tol"]), int(q.get("seed", 0)), float(q["arrival_s"])
+    rep = hsym_serve_report()
+    o = _serve_opts(**opts)
+    _check(lib().hsym_serve(arr, len(requests), ctypes.byref(o), ctypes.byref(rep)))
+    return _serve_results(arr, len(requests), rep)
+
+
+def hsym_serve_sim(arrival_s, iters, iter_s, nbytes, load_s, nev=1, **opts):
+    """The request loop's scheduler on a virtual clock (no device)."""
+    k = len(arrival_s)
+    arr = (hsym_request * max(1, k))()
+    for i in range(k):
+        arr[i].arrival_s = float(arrival_s[i])
+        arr[i].nev = nev
+    it = np.ascontiguousarray(iters, np.int32)
+    its = np.ascontiguousarray(iter_s, np.float64)
+    b = np.ascontiguousarray(nbytes, np.int64)
+    rep = hsym_serve_report()
+    o = _serve_opts(**opts)
+    _check(lib().hsym_serve_sim(arr, k, ctypes.byref(o), _hptr(it), _hptr(its), _hptr(b), float(load_s),
+                                ctypes.byref(rep)))
+    return _serve_results(arr, k, rep)
 
 
 class Matrix:
