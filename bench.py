@@ -28,10 +28,53 @@ import numpy as np  # noqa: E402
 
 METRIC = "LOBPCG s-to-tol + SpMM HBM GB/s (% peak), mixed vs FP64; solves/s, p99"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmm_sym_fp64_m16_n500k_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1609_01689_amd", "csrc", f) for f in ("spmm.hip", "build.cpp")]
+CALIB_BYTES = 512 << 20
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(m):
+    """HBM bytes per SpMM call from the committed counter summary (FETCH_SIZE
+    and WRITE_SIZE of k_spmm_panel + k_spmm_reduce, scaled by the factor the
+    same counters give for an elementwise kernel of known size), or None when
+    the summary is absent, for another block width, or the kernel sources
+    changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha1") != kernel_source_hash() or int(kv.get("block_width", -1)) != m:
+        return None
+    return float(kv["hbm_bytes_per_call"])
+
+
+def calibration_kernel(torch):
+    """An elementwise kernel of known traffic (reads and writes CALIB_BYTES
+    each), run so that counter runs of this script can scale FETCH_SIZE and
+    WRITE_SIZE."""
+    a = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0000001, out=b)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def spmm_algorithmic_bytes(nnz_stored, n, m, val_bytes, x_bytes, y_bytes):
@@ -178,12 +221,15 @@ def main():
     achieved = alg / (spmm_ms * 1e-3) / 1e9
     log("spmm fp64 m=%d: %.3f ms, %.1f GB/s (%.1f%% of 8 TB/s)" % (m, spmm_ms, achieved, 100 * achieved / HBM_PEAK_GBS))
 
+    calibration_kernel(torch)
+
     # --- timed LOBPCG solves ---
     opts = hs.default_lobpcg_opts(seed=1, keep_history=0)
     for _ in range(args.warmup):
         hs.lobpcg_solve(M.h, nev, m, tol, precond="jacobi", opts=opts)
     torch.cuda.synchronize()
     times, iters = [], []
+    spmm_live_ms, spmm_live_calls = 0.0, 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
@@ -191,10 +237,16 @@ def main():
         torch.cuda.synchronize()
         times.append(time.perf_counter() - ts)
         iters.append(rep.iters)
+        spmm_live_ms += rep.phase_ms[0]
+        spmm_live_calls += rep.spmm_calls
         assert st == hs.HSYM_OK, "solve did not converge"
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     ms_per_step = 1000.0 * total / args.steps
+    # SpMM launch duration inside the timed solves (HIP events on the solve stream)
+    live_ms = spmm_live_ms / max(1, spmm_live_calls)
+    achieved = alg / (live_ms * 1e-3) / 1e9
+    log("spmm inside the solves: %d calls, %.4f ms/call, %.1f GB/s" % (spmm_live_calls, live_ms, achieved))
     log("lobpcg fp64: %.1f ms/solve, iterations %s, rr bisection rounds max %d, evals %s" % (ms_per_step, iters, rep.rr_rounds_max, ev))
 
     extras = {}
@@ -262,9 +314,10 @@ def main():
         "p99_s": times[min(len(times) - 1, int(0.99 * len(times)))],
         "iters": int(np.median(iters)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "spmm_sym fp64 m=%d (k_spmm_panel + k_spmm_reduce), %.4f ms/call" % (m, spmm_ms),
-                     "algorithmic_bytes": alg},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(m),
+                     "kernel": "spmm_sym fp64 m=%d (k_spmm_panel + k_spmm_reduce)" % m,
+                     "launch_ms": live_ms, "launches_timed": spmm_live_calls, "algorithmic_bytes": alg,
+                     "microbench_ms": spmm_ms},
         "cpu_baseline": cpu,
         "build_s": build_s,
         "extras": extras,

@@ -94,6 +94,8 @@ struct Lobpcg {
     lobpcg_report rep{};
     std::chrono::steady_clock::time_point t0;
     std::vector<void *> allocs;
+    hipEvent_t ev_spmm[2] = {nullptr, nullptr};   // brackets the latest SpMM on s
+    bool spmm_pending = false;
 
     template <class T>
     T *dalloc(size_t count) {
@@ -109,6 +111,8 @@ struct Lobpcg {
     }
 
     ~Lobpcg() {
+        for (hipEvent_t e : ev_spmm)
+            if (e) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
         if (st_h) (void)hipHostFree(st_h);
         if (mu_h) (void)hipHostFree(mu_h);
@@ -138,6 +142,7 @@ struct Lobpcg {
         HIPCHK(hipHostMalloc((void **)&st_h, sizeof(Status), hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void **)&mu_h, sizeof(double) * HSYM_MAX_BLOCK, hipHostMallocDefault));
         memset(&rep, 0, sizeof(rep));
+        for (hipEvent_t &e : ev_spmm) HIPCHK(hipEventCreate(&e));
         t0 = std::chrono::steady_clock::now();
         // start block: X0 or a seeded Gaussian block
         if (X0) HIPCHK(hipMemcpyAsync(X, X0, sizeof(double) * nm, hipMemcpyDeviceToDevice, s));
@@ -160,8 +165,13 @@ struct Lobpcg {
         it = 0;
     }
 
+    // the block SpMM, bracketed by events whose elapsed time is added to
+    // phase_ms[0] at the next synchronisation
     void spmm(const double *V, double *AV) {
+        HIPCHK(hipEventRecord(ev_spmm[0], s));
         spmm_launch(H, m, V, T_F64, m, AV, T_F64, m, spmm_part, s);
+        HIPCHK(hipEventRecord(ev_spmm[1], s));
+        spmm_pending = true;
         rep.spmm_calls++;
     }
 
@@ -293,7 +303,15 @@ struct Lobpcg {
         return true;
     }
 
-    void sync() { HIPCHK(hipStreamSynchronize(s)); }
+    void sync() {
+        HIPCHK(hipStreamSynchronize(s));
+        if (spmm_pending) {
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, ev_spmm[0], ev_spmm[1]));
+            rep.phase_ms[0] += ms;
+            spmm_pending = false;
+        }
+    }
 
     // whole solve on one stream
     void run() {
