@@ -67,6 +67,10 @@ void geometry_for(int storage, int m, int64_t n, int *R, int *C, int *G) {
     const char *ec = getenv("HSYM_CHUNK_COLS");
     if (er) r = atoi(er);
     if (ec) c = atoi(ec);
+    // the SpMM relies on chunks tiling panels and on chunk rows sharing the
+    // LDS swizzle of their panel rows (a multiple of 8)
+    if (r < 64 || r > 65536 || c < 8 || c % 8 || r % c)
+        fail(HSYM_E_INVALID_ARG, "panel geometry must have 64 <= R <= 65536, C a multiple of 8 dividing R");
     *R = r;
     *C = c;
     // one segment per lane group of the 1024-thread workgroup at this width

@@ -9,7 +9,7 @@
 // the panel's accumulator and X rows, plus the X rows and the transposed
 // accumulator of the current external chunk.  A tile's entries are split in
 // equal segments, one per group of LPE lanes; each lane of a group handles
-// MW = M/LPE columns:
+// MW = M/LPE adjacent columns (2 when M >= 2):
 //   - row half: a register accumulator for the current row, added to the
 //     panel accumulator with LDS atomics when the row changes;
 //   - transposed half: LDS atomics into the panel accumulator (own tiles) or
@@ -17,8 +17,9 @@
 //     tiles, whose columns lie below the panel);
 //   - a second kernel adds the partial sums of every output chunk in a fixed
 //     order.  No global atomics are used.
-// LDS rows are swizzled (the column offset rotates with the row index) so the
-// lane groups of one wave, which touch different rows, spread over the banks.
+// LDS rows are stored in 16-byte chunks permuted by an XOR with the row index,
+// so the lane groups of one wave, which touch different rows, spread their
+// 16-byte reads and their atomics over the banks.
 #include "hsym_internal.h"
 
 namespace hsym {
@@ -31,16 +32,14 @@ static inline int round_m(int m) {
     return 16;
 }
 
-// values per lane: one 16-byte LDS access per lane and step
-template <typename T>
-__host__ __device__ constexpr int mw_of(int M) {
-    return M == 1 ? 1 : (sizeof(T) == 8 ? 2 : (M < 4 ? M : 4));
-}
+// Columns of X handled by one lane: up to 2 adjacent ones, one 16-byte LDS
+// chunk of an fp64 row.
+__host__ __device__ constexpr int mw_of(int M) { return M < 2 ? M : 2; }
 
 int spmm_lanes_per_entry(int storage, int m) {
     (void)storage;
-    int M = round_m(m);
-    return M / mw_of<double>(M);
+    const int M = round_m(m);
+    return M / mw_of(M);
 }
 
 size_t spmm_lds_bytes(int storage, int m, int R, int C) {
@@ -60,40 +59,62 @@ __device__ __forceinline__ int64_t xcd_panel(int64_t b, int64_t P) {
 __device__ __forceinline__ void lds_add(double *p, double v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ void lds_add(float *p, float v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
 
-template <int M, typename T>
-struct Lay {
-    static constexpr int MW = mw_of<T>(M);
-    static constexpr int LPE = M / MW;
-    static constexpr int ROWB = M * (int)sizeof(T);
-    static constexpr int RPB = ROWB >= 128 ? 1 : 128 / ROWB;   // rows per 128-byte bank line
-    // physical column of (row c, column k)
-    __device__ static __forceinline__ int sw(int c, int k) {
-        return (MW == 1) ? k : ((k + LPE * ((c / RPB) & (MW - 1))) & (M - 1));
+// LDS row layout: a row of M elements of type E is cut into 16-byte chunks
+// and chunk j of row r is stored at position j ^ (r mod chunks-per-row).  A
+// wave touches one row per lane group: the XOR spreads the groups' 16-byte
+// reads over the banks.  In the fp64 accumulators (FLIP) the two slots of a
+// chunk are also swapped on the next bit of r above those that place the
+// row in the 64 banks, which gives the 8-byte atomics of one instruction 4
+// or more distinct bank windows.  Rows shorter than 16 bytes are plain.
+template <int M, typename E, bool FLIP>
+struct RowLay {
+    static constexpr int EPC = 16 / (int)sizeof(E);
+    static constexpr int CPR = (M * (int)sizeof(E)) / 16;
+    static constexpr int POS = CPR >= 1 ? 64 / (CPR * 4) : 1;   // row positions across 64 banks
+    __device__ static __forceinline__ int slot_flip(int r) {
+        if constexpr (FLIP && EPC == 2 && CPR >= 1) return (r / POS) & 1;
+        else return 0;
+    }
+    __device__ static __forceinline__ int phys(int r, int k) {
+        if constexpr (CPR < 1) return k;
+        else return (((k / EPC) ^ (r & (CPR - 1))) * EPC) + ((k % EPC) ^ slot_flip(r));
     }
 };
 
-// T: stored values and staged X; A: products and sums (fp64 for both
-// storage precisions: a product of two fp32 numbers is exact in fp64, and the
-// LDS fp64 atomic add is several times cheaper than the fp32 one on gfx950)
+// A lane's MW = mw_of(M) elements k0 .. k0+MW-1 of row r (plain slots), as fp64.
+template <int M, typename T>
+__device__ __forceinline__ void read_row(const T *rowp, int r, int k0, double *o) {
+    using RL = RowLay<M, T, false>;
+    constexpr int MW = mw_of(M);
+    if constexpr (sizeof(T) == 8 && MW == 2 && RL::CPR >= 1) {
+        const double2 v = *reinterpret_cast<const double2 *>(rowp + RL::phys(r, k0));
+        o[0] = v.x;
+        o[1] = v.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < MW; i++) o[i] = (double)rowp[RL::phys(r, k0 + i)];
+    }
+}
+
+// T: stored values and staged X; products and sums are fp64 for both storage
+// precisions (a product of two fp32 numbers is exact in fp64, and the LDS fp64
+// atomic add is several times cheaper than the fp32 one on gfx950)
 template <int M, typename T, typename XIN, typename YT>
 __global__ __launch_bounds__(1024) void k_spmm_panel(
     const int64_t *__restrict__ ptp, const TileDesc *__restrict__ tiles, const uint32_t *__restrict__ idx,
     const T *__restrict__ vals, const T *__restrict__ diag, const XIN *__restrict__ X, int64_t ldx,
     YT *__restrict__ Y, int64_t ldy, double *__restrict__ partials, int64_t n, int R, int C, int G,
     int64_t npanels, int m) {
-    using A = double;
-    using L = Lay<M, double>;
-    constexpr int NT = 1024, MW = L::MW, LPE = L::LPE, GK = NT / LPE;
+    using XL = RowLay<M, T, false>;
+    using AL = RowLay<M, double, true>;
+    constexpr int NT = 1024, MW = mw_of(M), LPE = M / MW, GK = NT / LPE;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    A *acc = reinterpret_cast<A *>(smem_raw);
-    A *ts = acc + (size_t)R * M;
+    double *acc = reinterpret_cast<double *>(smem_raw);
+    double *ts = acc + (size_t)R * M;
     T *xp = reinterpret_cast<T *>(ts + (size_t)C * M);
     T *xs = xp + (size_t)R * M;
-    const int tid = threadIdx.x, g = tid / LPE, q = tid % LPE;
+    const int tid = threadIdx.x, g = tid / LPE, q = tid % LPE, k0 = q * MW;
     const int64_t p = xcd_panel(blockIdx.x, npanels);
     const int64_t row0 = p * (int64_t)R;
     const int nrow = (int)((n - row0) < R ? (n - row0) : R);
@@ -102,8 +123,8 @@ __global__ __launch_bounds__(1024) void k_spmm_panel(
         const int r = i / M, k = i - r * M;
         T v = T(0);
         if (r < nrow && k < m) v = (T)X[(row0 + r) * ldx + k];
-        xp[r * M + L::sw(r, k)] = v;
-        acc[i] = A(0);
+        xp[r * M + XL::phys(r, k)] = v;
+        acc[i] = 0.0;
     }
     const int64_t t0 = ptp[p], t1 = ptp[p + 1];
     constexpr int B = 4;   // entries loaded ahead of use
@@ -117,23 +138,24 @@ __global__ __launch_bounds__(1024) void k_spmm_panel(
                 const int r = i / M, k = i - r * M;
                 T v = T(0);
                 if (r < ncol && k < m) v = (T)X[(col0 + r) * ldx + k];
-                xs[r * M + L::sw(r, k)] = v;
-                ts[i] = A(0);
+                xs[r * M + XL::phys(r, k)] = v;
+                ts[i] = 0.0;
             }
         }
         __syncthreads();
         // own tiles read and update the panel's rows directly; col0 - row0 is a
-        // multiple of C, so the swizzle of a chunk row equals that of its panel row
+        // multiple of C (itself a multiple of 8), so a chunk row has the
+        // swizzle of its panel row
         const T *xsrc = ext ? xs : xp + (col0 - row0) * M;
-        A *tgt = ext ? ts : acc + (col0 - row0) * M;
+        double *tgt = ext ? ts : acc + (col0 - row0) * M;
         const int len = td.len;
         for (int seg = g; seg < G; seg += GK) {
             const uint32_t *ip = idx + td.base + seg;
             const T *vp = vals + td.base + seg;
             int cur = -1;
-            A ra[MW], xr[MW];
+            double ra[MW], xr[MW];
 #pragma unroll
-            for (int j = 0; j < MW; j++) { ra[j] = A(0); xr[j] = A(0); }
+            for (int j = 0; j < MW; j++) { ra[j] = 0.0; xr[j] = 0.0; }
             for (int e0 = 0; e0 < len; e0 += B) {
                 uint32_t w[B];
                 T a[B];
@@ -152,34 +174,44 @@ __global__ __launch_bounds__(1024) void k_spmm_panel(
                         if (cur >= 0) {
 #pragma unroll
                             for (int j = 0; j < MW; j++) {
-                                lds_add(acc + cur * M + L::sw(cur, q + LPE * j), ra[j]);
-                                ra[j] = A(0);
+                                lds_add(acc + cur * M + AL::phys(cur, k0 + j), ra[j]);
+                                ra[j] = 0.0;
                             }
                         }
                         cur = r;
-#pragma unroll
-                        for (int j = 0; j < MW; j++) xr[j] = (A)xp[r * M + L::sw(r, q + LPE * j)];
+                        read_row<M, T>(xp + r * M, r, k0, xr);
                     }
+                    double xc[MW];
+                    read_row<M, T>(xsrc + c * M, c, k0, xc);
+                    const double av = (double)a[u];
+                    double *trow = tgt + c * M;
+                    if constexpr (MW == 2 && AL::CPR >= 1) {
+                        // both slots of the lane's chunk; the flip only swaps them
+                        const int cb = AL::phys(c, k0) & ~1, f = AL::slot_flip(c);
+                        ra[0] = fma(av, xc[0], ra[0]);
+                        ra[1] = fma(av, xc[1], ra[1]);
+                        lds_add(trow + cb + f, av * xr[0]);
+                        lds_add(trow + cb + (f ^ 1), av * xr[1]);
+                    } else {
 #pragma unroll
-                    for (int j = 0; j < MW; j++) {
-                        const int pk = c * M + L::sw(c, q + LPE * j);
-                        const A av = (A)a[u];
-                        ra[j] = fma(av, (A)xsrc[pk], ra[j]);
-                        lds_add(tgt + pk, av * xr[j]);
+                        for (int j = 0; j < MW; j++) {
+                            ra[j] = fma(av, xc[j], ra[j]);
+                            lds_add(trow + AL::phys(c, k0 + j), av * xr[j]);
+                        }
                     }
                 }
             }
             if (cur >= 0) {
 #pragma unroll
-                for (int j = 0; j < MW; j++) lds_add(acc + cur * M + L::sw(cur, q + LPE * j), ra[j]);
+                for (int j = 0; j < MW; j++) lds_add(acc + cur * M + AL::phys(cur, k0 + j), ra[j]);
             }
         }
         __syncthreads();
         if (ext) {
-            A *dst = partials + (int64_t)td.slot * C * M;
+            double *dst = partials + (int64_t)td.slot * C * M;
             for (int i = tid; i < C * M; i += NT) {
                 const int r = i / M, k = i - r * M;
-                dst[i] = ts[r * M + L::sw(r, k)];
+                dst[i] = ts[r * M + AL::phys(r, k)];
             }
             __syncthreads();
         }
@@ -188,8 +220,7 @@ __global__ __launch_bounds__(1024) void k_spmm_panel(
         const int r = i / M, k = i - r * M;
         if (k < m) {
             const int64_t row = row0 + r;
-            const int pk = r * M + L::sw(r, k);
-            Y[row * ldy + k] = (YT)(acc[pk] + (A)diag[row] * (A)xp[pk]);
+            Y[row * ldy + k] = (YT)(acc[r * M + AL::phys(r, k)] + (double)diag[row] * (double)xp[r * M + XL::phys(r, k)]);
         }
     }
 }
