@@ -81,25 +81,29 @@ __global__ __launch_bounds__(256) void k_gram_partial(GramArgs g, double *__rest
     }
 }
 
-// sum of the partial Gram matrices: 64 elements x 4 part-slices per
-// workgroup, combined in a fixed order (bitwise reproducible)
-__global__ __launch_bounds__(256) void k_gram_final(const double *__restrict__ part, int nparts, int kk,
-                                                    double *__restrict__ out) {
-    __shared__ double red[4][64];
+// sum of the partial Gram matrices: 64 elements x 16 part-slices per
+// 1024-thread workgroup, slices combined by a fixed tree (bitwise reproducible)
+__global__ __launch_bounds__(1024) void k_gram_final(const double *__restrict__ part, int nparts, int kk,
+                                                     double *__restrict__ out) {
+    __shared__ double red[16][64];
     const int el = threadIdx.x & 63, sl = threadIdx.x >> 6;
     const int e = blockIdx.x * 64 + el;
     double s0 = 0.0, s1 = 0.0;
     if (e < kk) {
         int p = sl;
-        for (; p + 4 < nparts; p += 8) {
+        for (; p + 16 < nparts; p += 32) {
             s0 += part[(int64_t)p * kk + e];
-            s1 += part[(int64_t)(p + 4) * kk + e];
+            s1 += part[(int64_t)(p + 16) * kk + e];
         }
         if (p < nparts) s0 += part[(int64_t)p * kk + e];
     }
     red[sl][el] = s0 + s1;
     __syncthreads();
-    if (sl == 0 && e < kk) out[e] = (red[0][el] + red[1][el]) + (red[2][el] + red[3][el]);
+    for (int h = 8; h > 0; h >>= 1) {
+        if (sl < h) red[sl][el] += red[sl + h][el];
+        __syncthreads();
+    }
+    if (sl == 0 && e < kk) out[e] = red[0][el];
 }
 
 int gram_parts(int64_t n) {
@@ -128,7 +132,7 @@ void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s) {
 #undef GL
     HIPCHK(hipGetLastError());
     const int kk = K1 * K2;
-    hipLaunchKernelGGL(k_gram_final, dim3((kk + 63) / 64), dim3(256), 0, s, scratch, parts, kk, out);
+    hipLaunchKernelGGL(k_gram_final, dim3((kk + 63) / 64), dim3(1024), 0, s, scratch, parts, kk, out);
     HIPCHK(hipGetLastError());
 }
 
@@ -146,48 +150,50 @@ void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s) {
 // the input rows of one set are staged in LDS (rows padded to 17 doubles so
 // the 16 rows an MFMA operand reads fall in distinct banks); each wave forms
 // 16 output rows x 16 columns per v_mfma_f64_16x16x4f64 chain.
+// Each wave computes 16 rows: the MFMA A operands (lane: row li, columns
+// lk, lk+4, ...) are loaded straight from the input blocks and the B operands
+// (coefficients, a few KB read by every wave, cache resident) straight from
+// the coefficient matrix, so the kernel streams with no LDS staging and no
+// barrier until the fixed-order reduction of the residual norms.
 __global__ __launch_bounds__(256) void k_lincomb(LincombArgs a) {
-    __shared__ double cs[48][33];
-    __shared__ double ins[3][64][17];
     __shared__ double nred[4][4][16];
     const int m = a.m, nin = a.nin, nout = a.nout;
-    const int kin = nin * m, kout = nout * m;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int64_t r0 = (int64_t)blockIdx.x * 64;
-    const int rows = (int)((a.n - r0) < 64 ? (a.n - r0) : 64);
-    for (int e = tid; e < kin * kout; e += 256) {
-        const int i = e / kout, j = e - (e / kout) * kout;
-        cs[i][j] = a.coef[i * a.ldc + j];
-    }
+    const int64_t w0 = (int64_t)blockIdx.x * 64 + 16 * wave;   // this wave's 16 rows
+    const int64_t ra = w0 + li;                                   // row of this lane's A values
+    const bool rok = ra < a.n;
     double4_t xkeep = (double4_t){0.0, 0.0, 0.0, 0.0};
     double nrm = 0.0;
     for (int set = 0; set < a.nsets; set++) {
-        __syncthreads();
-        for (int i = 0; i < nin; i++) {
-            const double *src = a.in[set * 3 + i] + r0 * m;
-            for (int e = tid; e < 64 * 16; e += 256) {
-                const int r = e >> 4, k = e & 15;
-                ins[i][r][k] = (r < rows && k < m) ? src[r * m + k] : 0.0;
+        double av[3][4];
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; s4++) {
+                const int kk = 4 * s4 + lk;
+                av[i][s4] = (i < nin && rok && kk < m) ? a.in[set * 3 + i][ra * m + kk] : 0.0;
             }
         }
-        __syncthreads();
         for (int q = 0; q < nout; q++) {
             double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-            for (int i = 0; i < nin; i++) {
-                for (int k0 = 0; k0 < m; k0 += 4) {
-                    const int kk = k0 + lk;
-                    const double av = ins[i][16 * wave + li][kk];
-                    const double bv = (kk < m && li < m) ? cs[i * m + kk][q * m + li] : 0.0;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                if (i >= nin) break;
+#pragma unroll
+                for (int s4 = 0; s4 < 4; s4++) {
+                    if (4 * s4 >= m) break;
+                    const int kk = 4 * s4 + lk;
+                    const double bv = (kk < m && li < m) ? a.coef[(i * m + kk) * a.ldc + q * m + li] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s4], bv, acc, 0, 0, 0);
                 }
             }
             // accumulator register v holds row lk + 4v, column li of this wave's 16 rows
             double *dst = a.out[set * 2 + q];
 #pragma unroll
             for (int v = 0; v < 4; v++) {
-                const int r = 16 * wave + lk + 4 * v;
-                if (r < rows && li < m) dst[(r0 + r) * m + li] = acc[v];
+                const int64_t r = w0 + lk + 4 * v;
+                if (r < a.n && li < m) dst[r * m + li] = acc[v];
             }
             if (q == 0 && a.theta) {
                 if (set == 0) {
@@ -196,10 +202,10 @@ __global__ __launch_bounds__(256) void k_lincomb(LincombArgs a) {
                     const double th = li < m ? a.theta[li] : 0.0;
 #pragma unroll
                     for (int v = 0; v < 4; v++) {
-                        const int r = 16 * wave + lk + 4 * v;
-                        if (r < rows && li < m) {
+                        const int64_t r = w0 + lk + 4 * v;
+                        if (r < a.n && li < m) {
                             const double rv = acc[v] - xkeep[v] * th;
-                            a.res[(r0 + r) * m + li] = rv;
+                            a.res[r * m + li] = rv;
                             nrm += rv * rv;
                         }
                     }
@@ -208,7 +214,7 @@ __global__ __launch_bounds__(256) void k_lincomb(LincombArgs a) {
         }
     }
     if (a.theta) {
-        // squared column norms of R for this tile, combined in a fixed order
+        // squared column norms of R for this workgroup's 64 rows, combined in a fixed order
         nred[wave][lk][li] = nrm;
         __syncthreads();
         if (tid < m) {
@@ -230,17 +236,22 @@ void lincomb(const LincombArgs &a, hipStream_t s) {
 
 int64_t lincomb_norm_parts(int64_t n) { return (n + 63) / 64; }
 
-// sum of per-workgroup partial column sums: one workgroup per column,
-// strided partial sums combined by a fixed tree (bitwise reproducible)
-__global__ __launch_bounds__(256) void k_colsum_final(const double *__restrict__ part, int64_t nparts, int m,
-                                                      double *__restrict__ out) {
-    __shared__ double red[256];
+// sum of per-workgroup partial column sums: one 1024-thread workgroup per
+// column, strided partial sums combined by a fixed tree (bitwise reproducible)
+__global__ __launch_bounds__(1024) void k_colsum_final(const double *__restrict__ part, int64_t nparts, int m,
+                                                       double *__restrict__ out) {
+    __shared__ double red[1024];
     const int j = blockIdx.x;
-    double s = 0.0;
-    for (int64_t p = threadIdx.x; p < nparts; p += 256) s += part[p * m + j];
-    red[threadIdx.x] = s;
+    double s0 = 0.0, s1 = 0.0;
+    int64_t p = threadIdx.x;
+    for (; p + 1024 < nparts; p += 2048) {
+        s0 += part[p * m + j];
+        s1 += part[(p + 1024) * m + j];
+    }
+    if (p < nparts) s0 += part[p * m + j];
+    red[threadIdx.x] = s0 + s1;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
+    for (int off = 512; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
@@ -248,7 +259,7 @@ __global__ __launch_bounds__(256) void k_colsum_final(const double *__restrict__
 }
 
 void colsum_final(const double *part, int64_t nparts, int m, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_colsum_final, dim3(m), dim3(256), 0, s, part, nparts, m, out);
+    hipLaunchKernelGGL(k_colsum_final, dim3(m), dim3(1024), 0, s, part, nparts, m, out);
     HIPCHK(hipGetLastError());
 }
 
