@@ -151,6 +151,98 @@ def serving(hs, torch, count, seed=5):
     return out
 
 
+def stream_create(hs, g, storage, dtype, flags, slab=250_000):
+    h = hs.hsym_create_begin(g.n, storage, flags)
+    t = time.perf_counter()
+    for r0 in range(0, g.n, slab):
+        rp, ci, v = g.rows(r0, min(g.n, r0 + slab), dtype)
+        hs.hsym_create_append(h, rp, ci, v)
+        if (r0 // slab) % 20 == 19:
+            log("  create: %d of %d rows, %.0fs" % (r0 + slab, g.n, time.perf_counter() - t))
+    hs.hsym_create_finish(h)
+    return h
+
+
+def scale_workload(args, name):
+    """The large configurations (C3: n = 5M, N = 400; C4: n = 30M, N = 500):
+    nev = 10, m = 16, tol 1e-6, Jacobi (C3) or block-64 (C4) preconditioner,
+    the mixed form (fp32 storage) against the fp64 form.  Each handle is
+    built by streaming create from generator slabs and freed before the
+    next.  One step = one solve of the mixed form."""
+    import torch
+    import hsymgen
+    import paper_1609_01689_amd as hs
+    cfg = hsymgen.CONFIGS[name]
+    nev, m, tol = 10, 16, 1e-6
+    precond = "block64" if name == "C4" else "jacobi"
+    flags = hs.HSYM_GEOM_M(m) | (hs.HSYM_BUILD_BLOCK64 if precond == "block64" else 0)
+    g = hsymgen.Generator(cfg["n"], cfg["N"], cfg["seed"])
+    dev = torch.device("cuda:0")
+    res = {}
+    for label, storage, dtype in (("mixed", hs.HSYM_FP32, np.float32), ("fp64", hs.HSYM_FP64, np.float64)):
+        t = time.perf_counter()
+        h = stream_create(hs, g, storage, dtype, flags)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t
+        info = hs.hsym_info(h)
+        log("%s %s: built in %.1fs: %s" % (name, label, build_s, info))
+        X = torch.randn((g.n, m), dtype=torch.float64, device=dev)
+        Y = torch.empty_like(X)
+        hs.spmm_sym(h, X, Y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st_ = torch.cuda.current_stream()
+        e0.record(st_)
+        for _ in range(3):
+            hs.spmm_sym(h, X, Y, stream=st_)
+        e1.record(st_)
+        torch.cuda.synchronize()
+        spmm_ms = e0.elapsed_time(e1) / 3
+        del X, Y
+        vb = 4 if storage == hs.HSYM_FP32 else 8
+        alg = info["nnz_stored"] * (vb + 4) + g.n * m * 16
+        opts = hs.default_lobpcg_opts(seed=1, keep_history=0)
+        times = []
+        for k in range(args.warmup + args.steps):
+            t = time.perf_counter()
+            stt, ev, rep = hs.lobpcg_solve(h, nev, m, tol, precond=precond, opts=opts)
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                times.append(time.perf_counter() - t)
+            log("%s %s: solve %d: status %d, %d iterations, %.2fs" % (name, label, k, stt, rep.iters,
+                                                                     time.perf_counter() - t))
+        live = rep.phase_ms[0] / max(1, rep.spmm_calls)
+        res[label] = {"build_s": build_s, "s_to_tol": float(np.mean(times)), "iters": rep.iters, "status": stt,
+                      "evals": ev.tolist(), "resnorm_max": float(max(rep.resnorm[:nev])),
+                      "spmm_ms": spmm_ms, "spmm_ms_in_solve": live,
+                      "spmm_GBs_algorithmic": alg / (live * 1e-3) / 1e9, "device_bytes": info["device_bytes"]}
+        hs.hsym_destroy(h)
+        torch.cuda.synchronize()
+    ev32, ev64 = np.array(res["mixed"]["evals"]), np.array(res["fp64"]["evals"])
+    out = {
+        "metric": METRIC,
+        "value": 1.0 / res["mixed"]["s_to_tol"],
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * res["mixed"]["s_to_tol"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-storage/f64", "data": "synthetic",
+        "config": {"workload": "GEN n=%d N=%d seed=%d (CI-shaped upper CSR), LOBPCG nev=%d m=%d tol=%g %s, "
+                               "mixed (fp32 storage) vs fp64" % (cfg["n"], cfg["N"], cfg["seed"], nev, m, tol,
+                                                                 precond)},
+        "roofline": {"bound": "hbm", "achieved": res["mixed"]["spmm_GBs_algorithmic"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": res["mixed"]["spmm_GBs_algorithmic"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "spmm_sym fp32 storage m=16 (k_spmm_panel + k_spmm_reduce)",
+                     "launch_ms": res["mixed"]["spmm_ms_in_solve"]},
+        "cpu_baseline": None,
+        "mixed_vs_fp64_speedup": res["fp64"]["s_to_tol"] / res["mixed"]["s_to_tol"],
+        "max_rel_eval_diff_mixed_vs_fp64": float(np.max(np.abs(ev32 - ev64) / np.abs(ev64))),
+        "per_pair_rel_diff": (np.abs(ev32 - ev64) / np.abs(ev64)).tolist(),
+        "forms": res,
+    }
+    print(json.dumps(out))
+
+
 def cpu_baseline(A, m, nev, tol, gpu_iters, budget_s):
     """The oracle (as it stands) on the same matrix: LOBPCG iterations are run
     for about budget_s seconds and the per-iteration time is scaled to the
@@ -190,6 +282,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4"],
+                    help="C2 (default bench line) or the large configurations C3 / C4")
     ap.add_argument("--serve-requests", type=int, default=150,
                     help="requests of the request-loop measurement (0: skip)")
     args = ap.parse_args()
@@ -203,6 +297,9 @@ def main():
     import paper_1609_01689_amd as hs
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    if args.workload != "C2":
+        scale_workload(args, args.workload)
+        return
     m, nev, tol = args.m, 8, 1e-8
     cfg = hsymgen.CONFIGS["C2"]
     t = time.perf_counter()

@@ -141,6 +141,15 @@ typedef struct {
     double near;            /* Section 4.3 rules 2-4 threshold, default 0.1          */
     double guard;           /* shifted denominators kept >= guard*||H||_1, 1e-4       */
     int keep_history;       /* record per-iteration residual norms                   */
+    int graph;              /* 1: record the launches of each steady-state iteration
+                               phase once in a HIP graph and replay it (fewer launch
+                               calls for small n; the SpMM is then not timed in
+                               lobpcg_report.phase_ms); default 0. While a context
+                               records (its first steady-state iterations) the HIP
+                               runtime refuses stream synchronisation in other
+                               threads of the process: step graph contexts from the
+                               thread that creates them, or use hsym_serve, which
+                               orders its loader against recording              */
 } lobpcg_opts;
 
 #define HSYM_MAX_BLOCK 16
@@ -234,7 +243,8 @@ int lobpcg_ctx_destroy(lobpcg_ctx_t ctx);
  * tol, precond, seed of the Gaussian start block, arrival_s >= 0 (seconds
  * from the start of the call).  Outputs: status (HSYM_OK, HSYM_NOT_CONVERGED
  * or an error), iters, evals[0..nev), admit_s and finish_s (same clock),
- * device_bytes held while active.  Latency = finish_s - arrival_s.
+ * device_bytes held while active, error (message when status < 0).
+ * Latency = finish_s - arrival_s.
  */
 typedef struct {
     int64_t n;
@@ -256,6 +266,7 @@ typedef struct {
     double admit_s;
     double finish_s;
     int64_t device_bytes;
+    char error[128];        /* message of a failed request, "" otherwise */
 } hsym_request;
 
 typedef struct {

@@ -172,6 +172,35 @@ class SymMatrix:
 # preconditioner (Section 3.2 eq. 11; rules of Section 4.3)
 # --------------------------------------------------------------------------
 
+def spmm_rows(row0, rowptr, colind, values, X, rows):
+    """Rows `rows` of Y = H X from a slab of the stored upper triangle
+    (Section 4.1: each stored entry (r, c, a) gives Y_r += a X_c and, when
+    r != c, Y_c += a X_r).
+
+    The slab holds rows [row0, row0 + len(rowptr) - 1) in CSR form with
+    global column indices; it must contain every row of the matrix that
+    holds an entry in a column listed in `rows` (for the synthetic CI
+    matrices: all rows within the coupling window before them) as well as
+    the rows themselves.  X is the full n x m block.  Plain definition,
+    fp64, one requested row at a time."""
+    rowptr = np.asarray(rowptr, np.int64)
+    colind = np.asarray(colind, np.int64)
+    values = np.asarray(values, np.float64)
+    X = np.asarray(X, np.float64)
+    rows = np.asarray(rows, np.int64)
+    nr = len(rowptr) - 1
+    r_of = np.repeat(np.arange(row0, row0 + nr, dtype=np.int64), np.diff(rowptr))
+    out = np.zeros((len(rows), X.shape[1]))
+    for k, i in enumerate(rows):
+        # U X and the diagonal: entries stored in row i
+        a, b = rowptr[i - row0], rowptr[i - row0 + 1]
+        out[k] += values[a:b] @ X[colind[a:b]]
+        # U^T X: entries (r, i) with r < i
+        sel = (colind == i) & (r_of != i)
+        out[k] += values[sel] @ X[r_of[sel]]
+    return out
+
+
 def shifts(theta, rnorm, rho):
     """Per-column shifts mu_j (Section 4.3, rules 3 and 4).
 

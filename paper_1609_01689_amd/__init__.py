@@ -53,7 +53,7 @@ class hsym_info_t(ctypes.Structure):
 class lobpcg_opts(ctypes.Structure):
     _fields_ = [("maxit", ctypes.c_int), ("seed", ctypes.c_uint64), ("check_every", ctypes.c_int),
                 ("no_precond_iters", ctypes.c_int), ("near", ctypes.c_double), ("guard", ctypes.c_double),
-                ("keep_history", ctypes.c_int)]
+                ("keep_history", ctypes.c_int), ("graph", ctypes.c_int)]
 
 
 class lobpcg_report(ctypes.Structure):
@@ -81,7 +81,8 @@ class hsym_request(ctypes.Structure):
                 ("nev", ctypes.c_int), ("block_width", ctypes.c_int), ("precond", ctypes.c_int),
                 ("tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("arrival_s", ctypes.c_double),
                 ("status", ctypes.c_int), ("iters", ctypes.c_int), ("evals", ctypes.c_double * MAX_BLOCK),
-                ("admit_s", ctypes.c_double), ("finish_s", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+                ("admit_s", ctypes.c_double), ("finish_s", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+                ("error", ctypes.c_char * 128)]
 
 
 class hsym_serve_opts(ctypes.Structure):
@@ -362,7 +363,8 @@ def _serve_results(arr, count, rep):
         r = arr[i]
         out.append({"status": r.status, "iters": r.iters, "evals": np.array(r.evals[:r.nev]),
                     "arrival_s": r.arrival_s, "admit_s": r.admit_s, "finish_s": r.finish_s,
-                    "latency_s": r.finish_s - r.arrival_s, "device_bytes": r.device_bytes})
+                    "latency_s": r.finish_s - r.arrival_s, "device_bytes": r.device_bytes,
+                    "error": r.error.decode(errors="replace")})
     return out, {f: getattr(rep, f) for f, _ in hsym_serve_report._fields_}
 
 

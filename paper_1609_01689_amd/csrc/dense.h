@@ -81,6 +81,7 @@ struct RRArgs {
     int nblk, m;
 };
 void small_rr(const RRArgs *a, int count, hipStream_t s);
+void set_int(int *p, int v, hipStream_t s);
 
 struct OrthWork {
     double *gbuf;       // >= 48*16 doubles, device

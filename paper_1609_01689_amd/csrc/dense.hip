@@ -258,6 +258,14 @@ __global__ __launch_bounds__(1024) void k_colsum_final(const double *__restrict_
     if (threadIdx.x == 0) out[j] = red[0];
 }
 
+// *p = v as a kernel (a memset cannot be recorded in a captured graph)
+__global__ void k_set_int(int *p, int v) { *p = v; }
+
+void set_int(int *p, int v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v);
+    HIPCHK(hipGetLastError());
+}
+
 void colsum_final(const double *part, int64_t nparts, int m, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_colsum_final, dim3(m), dim3(1024), 0, s, part, nparts, m, out);
     HIPCHK(hipGetLastError());

@@ -96,6 +96,10 @@ struct Lobpcg {
     std::vector<void *> allocs;
     hipEvent_t ev_spmm[2] = {nullptr, nullptr};   // brackets the latest SpMM on s
     bool spmm_pending = false;
+    // graphs of the steady-state iteration (opts.graph): phase A without and
+    // with the preconditioner, phase B
+    hipGraphExec_t graph_a[2] = {nullptr, nullptr}, graph_b = nullptr;
+    bool capturing = false;
 
     template <class T>
     T *dalloc(size_t count) {
@@ -111,6 +115,8 @@ struct Lobpcg {
     }
 
     ~Lobpcg() {
+        for (hipGraphExec_t ge : {graph_a[0], graph_a[1], graph_b})
+            if (ge) (void)hipGraphExecDestroy(ge);
         for (hipEvent_t e : ev_spmm)
             if (e) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
@@ -151,6 +157,7 @@ struct Lobpcg {
         OrthWork ow{gbuf, coef, gram_scr, &st_d->flags[0], &st_h->flags[0]};
         rep.w_replaced += orthonormalize_block(n, m, X, nullptr, 0, o.seed * 1000003ULL + 5ULL, ow, s);
         spmm(X, AX);
+        rep.spmm_calls++;
         GramArgs g{};
         g.a[0] = X; g.b[0] = AX; g.na = g.nb = 1; g.m = m; g.n = n;
         gram(g, gbuf, gram_scr, s);
@@ -168,11 +175,45 @@ struct Lobpcg {
     // the block SpMM, bracketed by events whose elapsed time is added to
     // phase_ms[0] at the next synchronisation
     void spmm(const double *V, double *AV) {
-        HIPCHK(hipEventRecord(ev_spmm[0], s));
+        if (!capturing) HIPCHK(hipEventRecord(ev_spmm[0], s));
         spmm_launch(H, m, V, T_F64, m, AV, T_F64, m, spmm_part, s);
-        HIPCHK(hipEventRecord(ev_spmm[1], s));
-        spmm_pending = true;
-        rep.spmm_calls++;
+        if (!capturing) {
+            HIPCHK(hipEventRecord(ev_spmm[1], s));
+            spmm_pending = true;
+        }
+    }
+
+    // Run f's launches on s; with opts.graph, record them once into ge (a
+    // graph of the stream's work) and replay ge from then on.  The launches
+    // of a steady-state phase take the same arguments every iteration: the
+    // block pointers are fixed and the values that change (shifts, flags,
+    // Ritz values) travel through device or pinned memory.
+    template <class F>
+    void graphed(hipGraphExec_t &ge, F &&f) {
+        if (!ge) {
+            // The recorded phase makes no allocating or synchronising call.
+            // While a capture is open the runtime refuses stream
+            // synchronisation in other threads as well: threads that build
+            // matrices or contexts meanwhile hold capture_mutex().
+            std::lock_guard<std::mutex> cg(capture_mutex());
+            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+            capturing = true;
+            hipGraph_t gr = nullptr;
+            try {
+                f();
+            } catch (...) {
+                capturing = false;
+                (void)hipStreamEndCapture(s, &gr);
+                if (gr) (void)hipGraphDestroy(gr);
+                throw;
+            }
+            capturing = false;
+            HIPCHK(hipStreamEndCapture(s, &gr));
+            const hipError_t e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            HIPCHK(e);
+        }
+        HIPCHK(hipGraphLaunch(ge, s));
     }
 
     void rayleigh_ritz(int nblk) {
@@ -228,7 +269,7 @@ struct Lobpcg {
     void orth_part1() {
         const double *B[2] = {X, P};
         const int kb = have_p ? 2 : 1;
-        HIPCHK(hipMemsetAsync(&st_d->flags[0], 0, sizeof(int), s));
+        set_int(&st_d->flags[0], 0, s);
         GramArgs g{};
         for (int i = 0; i < kb; i++) g.a[i] = B[i];
         g.a[kb] = W; g.b[0] = W; g.na = kb + 1; g.nb = 1; g.m = m; g.n = n;
@@ -250,12 +291,17 @@ struct Lobpcg {
 
     void advance_a() {
         it++;
-        if (shifts(rho_, rnorm_, st_h->theta)) {
-            HIPCHK(hipMemcpyAsync(mu, mu_h, sizeof(double) * m, hipMemcpyHostToDevice, s));
-            precond_apply(H, precond, W, mu, o.guard * H->norm1, m, s);
-        }
+        const bool pre = shifts(rho_, rnorm_, st_h->theta);
         orth_attempt = 0;
-        orth_part1();
+        auto body = [&] {
+            if (pre) {
+                HIPCHK(hipMemcpyAsync(mu, mu_h, sizeof(double) * m, hipMemcpyHostToDevice, s));
+                precond_apply(H, precond, W, mu, o.guard * H->norm1, m, s);
+            }
+            orth_part1();
+        };
+        if (o.graph && have_p) graphed(graph_a[pre ? 1 : 0], body);
+        else body();
     }
 
     // advance_b (flag copy complete): repair a deficient W, or finish step 7,
@@ -274,32 +320,37 @@ struct Lobpcg {
             orth_part1();
             return false;
         }
-        lincomb(orth_lc, s);
-        GramArgs g2{};
-        g2.a[0] = W; g2.b[0] = W; g2.na = g2.nb = 1; g2.m = m; g2.n = n;
-        gram(g2, gbuf, gram_scr, s);
-        OrthArgs o2{gbuf, coef, &st_d->flags[0], 0, m, 2};
-        small_orth(&o2, 1, s);
-        LincombArgs l2{};
-        l2.in[0] = W; l2.out[0] = W; l2.coef = coef; l2.ldc = m; l2.nin = 1; l2.nout = 1; l2.nsets = 1;
-        l2.m = m; l2.n = n;
-        lincomb(l2, s);
-        spmm(W, AW);
-        const int nblk = have_p ? 3 : 2;
-        GramArgs g{};
-        g.a[0] = X; g.a[1] = W; g.a[2] = P; g.b[0] = AX; g.b[1] = AW; g.b[2] = AP;
-        g.na = g.nb = nblk; g.m = m; g.n = n;
-        gram(g, gbuf, gram_scr, s);
-        rayleigh_ritz(nblk);
-        LincombArgs u{};
-        u.in[0] = X; u.in[1] = W; u.in[2] = P; u.in[3] = AX; u.in[4] = AW; u.in[5] = AP;
-        u.out[0] = X; u.out[1] = P; u.out[2] = AX; u.out[3] = AP;
-        u.coef = rrcoef; u.ldc = 2 * m; u.nin = nblk; u.nout = 2; u.nsets = 2; u.m = m; u.n = n;
-        u.theta = st_d->theta; u.res = W; u.norm_part = norm_part;
-        lincomb(u, s);
-        colsum_final(norm_part, lincomb_norm_parts(n), m, st_d->norms, s);
+        auto body = [&] {
+            lincomb(orth_lc, s);
+            GramArgs g2{};
+            g2.a[0] = W; g2.b[0] = W; g2.na = g2.nb = 1; g2.m = m; g2.n = n;
+            gram(g2, gbuf, gram_scr, s);
+            OrthArgs o2{gbuf, coef, &st_d->flags[0], 0, m, 2};
+            small_orth(&o2, 1, s);
+            LincombArgs l2{};
+            l2.in[0] = W; l2.out[0] = W; l2.coef = coef; l2.ldc = m; l2.nin = 1; l2.nout = 1; l2.nsets = 1;
+            l2.m = m; l2.n = n;
+            lincomb(l2, s);
+            spmm(W, AW);
+            const int nblk = have_p ? 3 : 2;
+            GramArgs g{};
+            g.a[0] = X; g.a[1] = W; g.a[2] = P; g.b[0] = AX; g.b[1] = AW; g.b[2] = AP;
+            g.na = g.nb = nblk; g.m = m; g.n = n;
+            gram(g, gbuf, gram_scr, s);
+            rayleigh_ritz(nblk);
+            LincombArgs u{};
+            u.in[0] = X; u.in[1] = W; u.in[2] = P; u.in[3] = AX; u.in[4] = AW; u.in[5] = AP;
+            u.out[0] = X; u.out[1] = P; u.out[2] = AX; u.out[3] = AP;
+            u.coef = rrcoef; u.ldc = 2 * m; u.nin = nblk; u.nout = 2; u.nsets = 2; u.m = m; u.n = n;
+            u.theta = st_d->theta; u.res = W; u.norm_part = norm_part;
+            lincomb(u, s);
+            colsum_final(norm_part, lincomb_norm_parts(n), m, st_d->norms, s);
+            post_status();
+        };
+        if (o.graph && have_p) graphed(graph_b, body);
+        else body();
+        rep.spmm_calls++;
         have_p = true;
-        post_status();
         return true;
     }
 
@@ -435,6 +486,7 @@ int lobpcg_ctx_create(lobpcg_ctx_t *out, hsym_t H, int nev, int block_width, dou
 // Advance every context by up to `iters` iterations.  Contexts on different
 // streams overlap on the device: each phase is enqueued for all contexts
 // before any of them is waited on.
+
 int lobpcg_ctx_step(lobpcg_ctx_t *ctxs, int count, int iters) {
     return ctx_guard([&] {
         if ((!ctxs && count) || count < 0 || iters < 0) fail(HSYM_E_INVALID_ARG, "bad step arguments");

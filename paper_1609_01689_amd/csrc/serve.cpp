@@ -124,6 +124,12 @@ void run_schedule(hsym_request *q, int count, const hsym_serve_opts &o, Backend 
 // ---------------------------------------------------------------------------
 // Device backend
 // ---------------------------------------------------------------------------
+// copy the calling thread's last error message into a request
+static void note(hsym_request &x) {
+    std::strncpy(x.error, hsym_last_error(), sizeof(x.error) - 1);
+    x.error[sizeof(x.error) - 1] = 0;
+}
+
 struct DeviceBackend : Backend {
     hsym_request *q;
     const hsym_serve_opts &o;
@@ -178,6 +184,9 @@ struct DeviceBackend : Backend {
                 jobs.pop_front();
             }
             hsym_request &x = q[r];
+            // the stepping thread records graphs; the runtime refuses the
+            // loader's stream synchronisations while a capture is open
+            std::unique_lock<std::mutex> lg(capture_mutex());
             // tile geometry of the request's block width
             int st = hsym_create(&H[r], x.n, x.rowptr, x.colind, x.values, x.values_prec, x.storage,
                                  HSYM_HOST_PTRS | HSYM_GEOM_M(x.block_width), nullptr);
@@ -187,13 +196,16 @@ struct DeviceBackend : Backend {
                 op.seed = x.seed;
                 if (o.maxit > 0) op.maxit = o.maxit;
                 op.keep_history = 0;
+                op.graph = 1;          // replay each steady-state iteration as HIP graphs
                 st = lobpcg_ctx_create(&C[r], H[r], x.nev, x.block_width, x.tol, nullptr, x.precond, &op, nullptr);
             }
             if (st != HSYM_OK) {
                 x.status = st;
+                note(x);
                 if (C[r]) { lobpcg_ctx_destroy(C[r]); C[r] = nullptr; }
                 if (H[r]) { hsym_destroy(H[r]); H[r] = nullptr; }
             }
+            lg.unlock();
             {
                 std::lock_guard<std::mutex> g(mu);
                 done.push_back(r);
@@ -220,7 +232,7 @@ struct DeviceBackend : Backend {
         // some context failed: step them one by one and mark the failures
         for (int r : active) {
             const int st = lobpcg_ctx_step(&C[r], 1, iters);
-            if (st != HSYM_OK) q[r].status = st;
+            if (st != HSYM_OK) { q[r].status = st; note(q[r]); }
         }
     }
     bool finished(int r) override {
@@ -231,6 +243,7 @@ struct DeviceBackend : Backend {
         const int st = lobpcg_ctx_status(C[r], &d, x.evals, &rp);
         if (st < 0) {
             x.status = st;
+            note(x);
             return true;
         }
         if (!d) return false;
@@ -319,6 +332,7 @@ void reset_outputs(hsym_request *q, int count) {
         std::memset(q[i].evals, 0, sizeof(q[i].evals));
         q[i].admit_s = q[i].finish_s = 0.0;
         q[i].device_bytes = 0;
+        q[i].error[0] = 0;
     }
 }
 

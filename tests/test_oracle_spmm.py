@@ -83,3 +83,19 @@ def test_norm1_and_diagonal(c1):
 def test_dense_builder_matches_scipy(c1):
     H = oracle.SymMatrix.from_csr(c1)
     assert np.array_equal(H.dense(), scipy_full(c1).toarray())
+
+
+def test_spmm_rows_from_slab_matches_full():
+    """Rows of H X from a slab of the stored triangle (the form used for
+    sampled parity at sizes where the full product is not formed) agree with
+    the full product, including rows whose transposed entries come from rows
+    far above them."""
+    g = hsymgen.Generator(12000, 60, 21)
+    A = g.matrix()
+    X = hsymgen.gauss_block(5, A.n, 8)
+    Yref = oracle.SymMatrix.from_csr(A).spmm(X)
+    for lo, hi in [(0, 64), (6000, 6100), (11950, 12000)]:
+        s0 = max(0, lo - 4200)
+        rp, ci, v = g.rows(s0, hi)
+        Y = oracle.spmm_rows(s0, rp, ci, v, X, np.arange(lo, hi))
+        assert np.max(np.abs(Y - Yref[lo:hi])) <= 1e-12 * np.max(np.abs(Yref))
