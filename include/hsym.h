@@ -147,9 +147,10 @@ typedef struct {
                                lobpcg_report.phase_ms); default 0. While a context
                                records (its first steady-state iterations) the HIP
                                runtime refuses stream synchronisation in other
-                               threads of the process: step graph contexts from the
-                               thread that creates them, or use hsym_serve, which
-                               orders its loader against recording              */
+                               threads of the process: use it where one thread
+                               creates and steps the contexts (hsym_serve, whose
+                               loader thread builds requests meanwhile, leaves it
+                               off)                                             */
 } lobpcg_opts;
 
 #define HSYM_MAX_BLOCK 16

@@ -10,10 +10,6 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 
-std::mutex &capture_mutex() {
-    static std::mutex mu;
-    return mu;
-}
 
 void fail(int status, const std::string &msg) { throw Error{status, msg}; }
 

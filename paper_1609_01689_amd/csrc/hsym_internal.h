@@ -4,7 +4,6 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <functional>
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -92,9 +91,6 @@ namespace hsym {
 
 // geometry: (R, C) for a block width and storage precision
 void geometry_for(int storage, int m, int64_t n, int *R, int *C, int *G);
-// held while a context records a HIP graph; a thread that synchronises
-// while another thread may be recording holds it around that work
-std::mutex &capture_mutex();
 int spmm_lanes_per_entry(int storage, int m);
 size_t spmm_lds_bytes(int storage, int m, int R, int C);
 void free_tiles(DeviceTiles *dt);

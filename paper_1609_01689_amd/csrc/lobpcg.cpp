@@ -192,10 +192,8 @@ struct Lobpcg {
     void graphed(hipGraphExec_t &ge, F &&f) {
         if (!ge) {
             // The recorded phase makes no allocating or synchronising call.
-            // While a capture is open the runtime refuses stream
-            // synchronisation in other threads as well: threads that build
-            // matrices or contexts meanwhile hold capture_mutex().
-            std::lock_guard<std::mutex> cg(capture_mutex());
+            // While a capture is open the runtime also refuses stream
+            // synchronisation in other threads of the process.
             HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
             capturing = true;
             hipGraph_t gr = nullptr;

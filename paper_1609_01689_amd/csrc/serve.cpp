@@ -184,9 +184,6 @@ struct DeviceBackend : Backend {
                 jobs.pop_front();
             }
             hsym_request &x = q[r];
-            // the stepping thread records graphs; the runtime refuses the
-            // loader's stream synchronisations while a capture is open
-            std::unique_lock<std::mutex> lg(capture_mutex());
             // tile geometry of the request's block width
             int st = hsym_create(&H[r], x.n, x.rowptr, x.colind, x.values, x.values_prec, x.storage,
                                  HSYM_HOST_PTRS | HSYM_GEOM_M(x.block_width), nullptr);
@@ -196,7 +193,9 @@ struct DeviceBackend : Backend {
                 op.seed = x.seed;
                 if (o.maxit > 0) op.maxit = o.maxit;
                 op.keep_history = 0;
-                op.graph = 1;          // replay each steady-state iteration as HIP graphs
+                // no graph recording: the runtime refuses the loader thread's
+                // stream synchronisations while another thread records
+                op.graph = 0;
                 st = lobpcg_ctx_create(&C[r], H[r], x.nev, x.block_width, x.tol, nullptr, x.precond, &op, nullptr);
             }
             if (st != HSYM_OK) {
@@ -205,7 +204,6 @@ struct DeviceBackend : Backend {
                 if (C[r]) { lobpcg_ctx_destroy(C[r]); C[r] = nullptr; }
                 if (H[r]) { hsym_destroy(H[r]); H[r] = nullptr; }
             }
-            lg.unlock();
             {
                 std::lock_guard<std::mutex> g(mu);
                 done.push_back(r);

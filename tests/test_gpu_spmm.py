@@ -73,7 +73,7 @@ def test_spmm_fp64_ragged_and_ld():
     assert np.linalg.norm(Y - Yref) <= 1e-12 * np.linalg.norm(Yref)
 
 
-@pytest.mark.parametrize("geom_m,m", [(1, 1), (8, 8), (16, 8), (8, 4), (4, 2)])
+@pytest.mark.parametrize("geom_m,m", [(1, 1), (8, 8), (16, 8), (8, 4), (4, 2), (1, 2), (2, 4), (4, 8)])
 def test_spmm_geometries(geom_m, m):
     A = hsymgen.generate(20000, 200, 44)
     H = oracle.SymMatrix.from_csr(A)
