@@ -61,6 +61,13 @@ enum hsym_precond { HSYM_PRECOND_NONE = 0, HSYM_PRECOND_JACOBI = 1, HSYM_PRECOND
  * in bits 8..15 (0 = 16).  Any block width whose LDS footprint fits the chosen
  * geometry can be used with the handle; a narrower hint gives taller panels. */
 #define HSYM_GEOM_M(m) (((m) & 0xff) << 8)
+/* Explicit panel geometry: R = 2^lr panel rows (6 <= lr <= 15) and C = 2^lc
+ * chunk columns (3 <= lc <= lr), in bits 16..23 (0 = chosen from the block
+ * width hint and n).  hsym_create fails with HSYM_E_INVALID_ARG when C does
+ * not divide R, and spmm_sym with HSYM_E_UNSUPPORTED when the geometry does
+ * not fit the LDS at the requested block width.  hsym_autotune_geometry
+ * returns such flags. */
+#define HSYM_GEOM_PANEL(lr, lc) ((((lr) & 0xf) << 16) | (((lc) & 0xf) << 20))
 
 typedef struct hsym_matrix *hsym_t;
 typedef struct lobpcg_ctx *lobpcg_ctx_t;
@@ -132,6 +139,32 @@ int spmm_sym(hsym_t H, int m, const double *X, int64_t ldx, double *Y, int64_t l
 /* Same product on fp32 blocks (fp32 storage only; m in {1..16}). */
 int spmm_sym_f32(hsym_t H, int m, const float *X, int64_t ldx, float *Y, int64_t ldy,
                  void *stream);
+
+/*
+ * Tile-shape autotuner (request loop, "autotuned tile shape").  Takes the
+ * same host CSR as hsym_create and a block width m.  It builds a row sample of
+ * H (sample_rows rows around the middle, <= 0 for min(n, 262144); entries whose
+ * column leaves the sample are dropped) once per candidate panel geometry
+ * (R = 256..4096 rows, C = R/8, R/4, R/2 columns, those whose LDS footprint at
+ * width m fits 160 KB), times spmm_sym on it (3 warm-up calls, then 5 calls
+ * between HIP events on a private stream) and returns in *out_flags the
+ * HSYM_GEOM_M(m) | HSYM_GEOM_PANEL(..) flags of the fastest, to be or-ed into
+ * hsym_create's flags.  table (host, cap entries, may be NULL) receives every
+ * candidate tried (ms < 0 when it could not be built or run); *ntried (may be
+ * NULL) their number.  Synchronous; allocates and frees device memory.
+ * Errors: HSYM_E_INVALID_ARG (NULL pointers, m outside [1, 16], malformed
+ * rowptr or lower entries), HSYM_E_UNSUPPORTED (no candidate ran),
+ * HSYM_E_OUT_OF_MEMORY, HSYM_E_DEVICE.
+ */
+typedef struct {
+    int panel_rows;
+    int chunk_cols;
+    double ms;                  /* mean spmm_sym time on the sample, < 0: failed */
+} hsym_tune_entry;
+
+int hsym_autotune_geometry(int64_t n, const int64_t *rowptr, const int32_t *colind, const void *values,
+                           int values_prec, int storage, int m, int64_t sample_rows, int *out_flags,
+                           hsym_tune_entry *table, int cap, int *ntried);
 
 typedef struct {
     int maxit;              /* default 1000                                          */
@@ -275,11 +308,16 @@ typedef struct {
     int max_active;         /* requests in flight at most; default 64                */
     int iters_per_round;    /* iterations per active request per round; default 1   */
     int maxit;              /* per-request iteration cap; default 1000               */
+    int autotune;           /* 1: the first request of each size class (power of two
+                               of n, block width, storage) runs
+                               hsym_autotune_geometry on its matrix, and the class
+                               keeps that panel geometry; default 0                 */
 } hsym_serve_opts;
 
 typedef struct {
     double wall_s;                  /* first arrival to last finish              */
     int rounds;                     /* scheduling rounds that stepped requests   */
+    int tuned_classes;              /* size classes the autotuner ran for        */
     int max_active_seen;
     int64_t peak_reserved_bytes;    /* largest sum of admitted estimates         */
 } hsym_serve_report;

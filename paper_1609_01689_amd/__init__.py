@@ -36,10 +36,19 @@ def HSYM_GEOM_M(m: int) -> int:
     return (int(m) & 0xFF) << 8
 
 
+def HSYM_GEOM_PANEL(lr: int, lc: int) -> int:
+    """Explicit panel geometry: 2**lr panel rows, 2**lc chunk columns."""
+    return ((int(lr) & 0xF) << 16) | ((int(lc) & 0xF) << 20)
+
+
 class HsymError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("hsym status %d: %s" % (status, msg))
         self.status = status
+
+
+class hsym_tune_entry(ctypes.Structure):
+    _fields_ = [("panel_rows", ctypes.c_int), ("chunk_cols", ctypes.c_int), ("ms", ctypes.c_double)]
 
 
 class hsym_info_t(ctypes.Structure):
@@ -87,12 +96,12 @@ class hsym_request(ctypes.Structure):
 
 class hsym_serve_opts(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("max_active", ctypes.c_int),
-                ("iters_per_round", ctypes.c_int), ("maxit", ctypes.c_int)]
+                ("iters_per_round", ctypes.c_int), ("maxit", ctypes.c_int), ("autotune", ctypes.c_int)]
 
 
 class hsym_serve_report(ctypes.Structure):
-    _fields_ = [("wall_s", ctypes.c_double), ("rounds", ctypes.c_int), ("max_active_seen", ctypes.c_int),
-                ("peak_reserved_bytes", ctypes.c_int64)]
+    _fields_ = [("wall_s", ctypes.c_double), ("rounds", ctypes.c_int), ("tuned_classes", ctypes.c_int),
+                ("max_active_seen", ctypes.c_int), ("peak_reserved_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -101,6 +110,8 @@ _vp, _i64, _int, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_
 _SIGS = {
     "hsym_create": [ctypes.POINTER(_vp), _i64, _vp, _vp, _vp, _int, _int, _int, _vp],
     "hsym_create_begin": [ctypes.POINTER(_vp), _i64, _int, _int, _vp],
+    "hsym_autotune_geometry": [_i64, _vp, _vp, _vp, _int, _int, _int, _i64, ctypes.POINTER(_int),
+                               ctypes.POINTER(hsym_tune_entry), _int, ctypes.POINTER(_int)],
     "hsym_create_append": [_vp, _i64, _vp, _vp, _vp, _int],
     "hsym_create_finish": [_vp],
     "hsym_destroy": [_vp],
@@ -200,6 +211,21 @@ def hsym_create(n, rowptr, colind, values, storage=HSYM_FP64, flags=0, stream=No
     _check(lib().hsym_create(ctypes.byref(h), int(n), _hptr(rowptr), _hptr(colind), _hptr(values), vp,
                              storage, flags, _stream(stream)))
     return h
+
+
+def hsym_autotune_geometry(n, rowptr, colind, values, storage=HSYM_FP64, m=16, sample_rows=0):
+    """Fastest panel geometry for width m on a row sample: (flags, [(R, C, ms), ...])."""
+    rowptr = np.ascontiguousarray(rowptr, np.int64)
+    colind = np.ascontiguousarray(colind, np.int32)
+    values = np.ascontiguousarray(values)
+    vp = {np.dtype(np.float64): HSYM_FP64, np.dtype(np.float32): HSYM_FP32}[values.dtype]
+    cap = 64
+    table = (hsym_tune_entry * cap)()
+    flags, ntried = _int(0), _int(0)
+    _check(lib().hsym_autotune_geometry(int(n), _hptr(rowptr), _hptr(colind), _hptr(values), vp, storage, int(m),
+                                        int(sample_rows), ctypes.byref(flags), table, cap, ctypes.byref(ntried)))
+    rows = [(table[i].panel_rows, table[i].chunk_cols, table[i].ms) for i in range(min(ntried.value, cap))]
+    return flags.value, rows
 
 
 def hsym_create_begin(n, storage=HSYM_FP64, flags=0, stream=None):
@@ -343,9 +369,10 @@ def hsym_kernel_orthonormalize(V, B=(), seed=0, stream=None):
     return rep.value
 
 
-def _serve_opts(budget_bytes=0, max_active=0, iters_per_round=0, maxit=0):
+def _serve_opts(budget_bytes=0, max_active=0, iters_per_round=0, maxit=0, autotune=False):
     o = hsym_serve_opts()
     lib().hsym_serve_opts_default(ctypes.byref(o))
+    o.autotune = 1 if autotune else 0
     if budget_bytes:
         o.budget_bytes = int(budget_bytes)
     if max_active:

@@ -53,7 +53,7 @@ void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, in
     if (errst) fail(errst, err);
 }
 
-void geometry_for(int storage, int m, int64_t n, int *R, int *C, int *G) {
+void geometry_for(int storage, int m, int64_t n, int lr, int lc, int *R, int *C, int *G) {
     // Panel rows R and chunk columns C = R/4: the largest power-of-two R for
     // which the panel accumulator, the panel's X rows, the staged X chunk and
     // the chunk's transposed accumulator fit the 160 KB LDS of a gfx950 CU.
@@ -63,10 +63,17 @@ void geometry_for(int storage, int m, int64_t n, int *R, int *C, int *G) {
     // keep at least one panel per CU (256 CUs) when n allows
     while (r > 256 && (int64_t)r * 256 > n) r /= 2;
     int c = r / 4;
-    const char *er = getenv("HSYM_PANEL_ROWS");
-    const char *ec = getenv("HSYM_CHUNK_COLS");
-    if (er) r = atoi(er);
-    if (ec) c = atoi(ec);
+    if (lr > 0) {
+        // explicit geometry (hsym_create flags, e.g. from the autotuner)
+        if (lr > 16 || lc < 3 || lc > 16) fail(HSYM_E_INVALID_ARG, "panel geometry exponents out of range");
+        r = 1 << lr;
+        c = 1 << lc;
+    } else {
+        const char *er = getenv("HSYM_PANEL_ROWS");
+        const char *ec = getenv("HSYM_CHUNK_COLS");
+        if (er) r = atoi(er);
+        if (ec) c = atoi(ec);
+    }
     // the SpMM relies on chunks tiling panels and on chunk rows sharing the
     // LDS swizzle of their panel rows (a multiple of 8)
     if (r < 64 || r > 65536 || c < 8 || c % 8 || r % c)
@@ -399,7 +406,7 @@ void builder_begin(hsym_matrix *H, int64_t nnz_hint) {
     b->n = H->n;
     b->storage = H->storage;
     b->b64 = (H->flags & HSYM_BUILD_BLOCK64) != 0;
-    geometry_for(H->storage, H->geom_m, H->n, &b->R, &b->C, &b->G);
+    geometry_for(H->storage, H->geom_m, H->n, H->geom_lr, H->geom_lc, &b->R, &b->C, &b->G);
     if (b->G < 1) fail(HSYM_E_INVALID_ARG, "bad segment count");
     if (b->R % b->C != 0 || b->C > 65536 || b->R > 65535)
         fail(HSYM_E_INVALID_ARG, "panel rows must be a multiple of chunk columns (<= 65535)");

@@ -94,6 +94,9 @@ int hsym_create_begin(hsym_t *out, int64_t n, int storage, int flags, void *stre
     H->storage = storage;
     H->flags = flags;
     H->geom_m = geom_from_flags(flags);
+    H->geom_lr = (flags >> 16) & 0xf;
+    H->geom_lc = (flags >> 20) & 0xf;
+    if (H->geom_lr && !H->geom_lc) H->geom_lc = H->geom_lr - 2;
     H->stream = (hipStream_t)stream;
     HIPCHK(hipGetDevice(&H->device));
     try {

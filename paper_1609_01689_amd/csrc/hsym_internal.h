@@ -73,6 +73,7 @@ struct hsym_matrix {
     // tile format of the strictly-upper part (one panel geometry per handle)
     hsym::DeviceTiles tiles;
     int geom_m = 16;              // block width the geometry is sized for
+    int geom_lr = 0, geom_lc = 0; // explicit log2 panel rows / chunk columns (0: automatic)
     std::vector<double> d_host;   // diagonal, fp64, host copy
     std::vector<double> colsum;   // absolute column sums (streaming create)
     // block-64 preconditioner: per 64-row chunk Q (64x64, row-major) and lambda
@@ -90,7 +91,7 @@ struct hsym_matrix {
 namespace hsym {
 
 // geometry: (R, C) for a block width and storage precision
-void geometry_for(int storage, int m, int64_t n, int *R, int *C, int *G);
+void geometry_for(int storage, int m, int64_t n, int lr, int lc, int *R, int *C, int *G);
 int spmm_lanes_per_entry(int storage, int m);
 size_t spmm_lds_bytes(int storage, int m, int R, int C);
 void free_tiles(DeviceTiles *dt);

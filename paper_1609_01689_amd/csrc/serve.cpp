@@ -17,6 +17,7 @@
 #include <cstring>
 #include <deque>
 #include <limits>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -116,6 +117,7 @@ void run_schedule(hsym_request *q, int count, const hsym_serve_opts &o, Backend 
         }
         rep->wall_s = count ? last - first : 0.0;
         rep->rounds = rounds;
+        rep->tuned_classes = 0;
         rep->max_active_seen = max_act;
         rep->peak_reserved_bytes = peak;
     }
@@ -141,6 +143,9 @@ struct DeviceBackend : Backend {
     std::deque<int> jobs, done;
     bool stop = false;
     std::thread loader;
+    // panel geometry per size class (loader thread only)
+    std::map<int64_t, int> geom;
+    int tuned = 0;
 
     DeviceBackend(hsym_request *q_, int count, const hsym_serve_opts &o_) : q(q_), o(o_), H(count), C(count) {
         loader = std::thread([this] { loader_main(); });
@@ -173,6 +178,27 @@ struct DeviceBackend : Backend {
         }
         cv.notify_all();
     }
+    // tile geometry for a request: sized for its block width, or the panel
+    // shape the autotuner chose for its size class
+    int geometry(const hsym_request &x) {
+        const int dflt = HSYM_GEOM_M(x.block_width);
+        if (!o.autotune) return dflt;
+        int lg = 0;
+        while (((int64_t)2 << lg) <= x.n) lg++;
+        const int64_t key = ((int64_t)lg << 8) | (x.block_width << 1) | x.storage;
+        auto it = geom.find(key);
+        if (it == geom.end()) {
+            int f = 0;
+            if (hsym_autotune_geometry(x.n, x.rowptr, x.colind, x.values, x.values_prec, x.storage, x.block_width, 0,
+                                       &f, nullptr, 0, nullptr) == HSYM_OK)
+                tuned++;
+            else
+                f = 0;   // keep the default geometry for this class
+            it = geom.emplace(key, f).first;
+        }
+        return it->second ? it->second : dflt;
+    }
+
     void loader_main() {
         for (;;) {
             int r;
@@ -184,9 +210,8 @@ struct DeviceBackend : Backend {
                 jobs.pop_front();
             }
             hsym_request &x = q[r];
-            // tile geometry of the request's block width
             int st = hsym_create(&H[r], x.n, x.rowptr, x.colind, x.values, x.values_prec, x.storage,
-                                 HSYM_HOST_PTRS | HSYM_GEOM_M(x.block_width), nullptr);
+                                 HSYM_HOST_PTRS | geometry(x), nullptr);
             if (st == HSYM_OK) {
                 lobpcg_opts op;
                 lobpcg_opts_default(&op);
@@ -320,6 +345,7 @@ void check_opts(hsym_serve_opts &o, const hsym_serve_opts *in) {
         if (in->max_active > 0) o.max_active = in->max_active;
         if (in->iters_per_round > 0) o.iters_per_round = in->iters_per_round;
         if (in->maxit > 0) o.maxit = in->maxit;
+        o.autotune = in->autotune ? 1 : 0;
     }
 }
 
@@ -364,6 +390,7 @@ void hsym_serve_opts_default(hsym_serve_opts *o) {
     o->max_active = 64;
     o->iters_per_round = 1;
     o->maxit = 1000;
+    o->autotune = 0;
 }
 
 int hsym_serve(hsym_request *reqs, int count, const hsym_serve_opts *opts, hsym_serve_report *rep) {
@@ -380,6 +407,11 @@ int hsym_serve(hsym_request *reqs, int count, const hsym_serve_opts *opts, hsym_
         reset_outputs(reqs, count);
         DeviceBackend be(reqs, count, o);
         run_schedule(reqs, count, o, be, rep);
+        if (rep) {
+            // every load has been collected through the queue lock by now
+            std::lock_guard<std::mutex> g(be.mu);
+            rep->tuned_classes = be.tuned;
+        }
     });
 }
 
