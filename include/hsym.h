@@ -198,11 +198,13 @@ typedef struct {
     double theta[HSYM_MAX_BLOCK];     /* all m Ritz values at exit                    */
     double resnorm[HSYM_MAX_BLOCK];   /* ||r_j|| / ||H||_1 at exit, all m columns     */
     double seconds;                   /* wall time of the solve                      */
-    double phase_ms[8];               /* [0]: device time of the block SpMMs (events on
-                                         the solve stream); [1..7] reserved, 0 */
+    double phase_ms[8];               /* [0]: device time of the block SpMMs launched on
+                                         the context's own stream (events; SpMMs of
+                                         batched rounds are not timed); [1..7] 0 */
     int history_len;
     double history[HSYM_MAX_HISTORY]; /* max_{j<=nev} rho_j per iteration           */
     int rr_rounds_max;                /* most multisection rounds any Rayleigh-Ritz eigenvalue search took */
+    int batched_iters;                /* iterations run in batched rounds (lobpcg_ctx_step) */
 } lobpcg_report;
 
 void lobpcg_opts_default(lobpcg_opts *o);

@@ -71,7 +71,7 @@ class lobpcg_report(ctypes.Structure):
                 ("theta", ctypes.c_double * MAX_BLOCK), ("resnorm", ctypes.c_double * MAX_BLOCK),
                 ("seconds", ctypes.c_double), ("phase_ms", ctypes.c_double * 8),
                 ("history_len", ctypes.c_int), ("history", ctypes.c_double * MAX_HISTORY),
-                ("rr_rounds_max", ctypes.c_int)]
+                ("rr_rounds_max", ctypes.c_int), ("batched_iters", ctypes.c_int)]
 
 
 class lanczos_opts(ctypes.Structure):

@@ -83,6 +83,38 @@ struct RRArgs {
 void small_rr(const RRArgs *a, int count, hipStream_t s);
 void set_int(int *p, int v, hipStream_t s);
 
+// ---- batched forms (argument tables in device memory, blockIdx.y = problem) ----
+struct GramJob {
+    GramArgs g;
+    double *part;      // gram_scratch_bytes(n, K1, K2)
+    int64_t rpw;       // rows per partial
+    int parts;         // gram_parts(n)
+    int kk;            // K1 * K2
+    double *out;
+};
+// every job has the same K1 = na*m and K2 = nb*m
+void gram_batched(const GramJob *jobs, int count, int K1, int K2, int max_parts, hipStream_t s);
+// every table entry passes the shape checks of lincomb()
+void lincomb_batched(const LincombArgs *tab, int count, int64_t max_n, hipStream_t s);
+struct ColsumJob {
+    const double *part;
+    int64_t nparts;
+    int m;
+    double *out;
+};
+void colsum_batched(const ColsumJob *jobs, int count, int m, hipStream_t s);
+struct JacobiJob {
+    double *W;
+    const double *diag;
+    const double *mu;
+    double delta;
+    int64_t n;
+};
+void jacobi_batched(const JacobiJob *jobs, int count, int m, int64_t max_n, hipStream_t s);
+void set_ints(int *const *p, int count, int v, hipStream_t s);
+void gather_words(const int *const *src, int *dst, int words, int count, hipStream_t s);
+int gram_parts(int64_t n);
+
 struct OrthWork {
     double *gbuf;       // >= 48*16 doubles, device
     double *coef;       // >= 48*16 doubles, device

@@ -21,7 +21,8 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // MFMA f64 16x16x4 operand layout: lane l holds A[i=l%16][k=l/16] and
 // B[k=l/16][j=l%16]; accumulator register v of lane l holds D[l/16 + 4v][l%16].
 template <int T1, int T2>
-__global__ __launch_bounds__(256) void k_gram_partial(GramArgs g, double *__restrict__ part, int64_t rows_per_wg) {
+__device__ __forceinline__ void gram_partial_body(const GramArgs &g, double *__restrict__ part, int64_t rows_per_wg,
+                                                  int64_t bx) {
     __shared__ double red[4][T1 * 16][T2 * 16 + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = g.m;
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(GramArgs g, double *__rest
     for (int i = 0; i < T1; i++)
 #pragma unroll
         for (int j = 0; j < T2; j++) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
-    const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
+    const int64_t r_begin = bx * rows_per_wg;
     int64_t r_end = r_begin + rows_per_wg;
     if (r_end > g.n) r_end = g.n;
     for (int64_t r0 = r_begin + 4 * wave; r0 < r_end; r0 += 16) {
@@ -74,20 +75,33 @@ __global__ __launch_bounds__(256) void k_gram_partial(GramArgs g, double *__rest
 #pragma unroll
             for (int v = 0; v < 4; v++) red[wave][16 * i + lk + 4 * v][16 * j + li] = acc[i][j][v];
     __syncthreads();
-    double *out = part + (int64_t)blockIdx.x * K1 * K2;
+    double *out = part + bx * K1 * K2;
     for (int e = tid; e < K1 * K2; e += 256) {
         int i = e / K2, j = e - (e / K2) * K2;
         out[e] = red[0][i][j] + red[1][i][j] + red[2][i][j] + red[3][i][j];
     }
 }
 
+template <int T1, int T2>
+__global__ __launch_bounds__(256) void k_gram_partial(GramArgs g, double *__restrict__ part, int64_t rows_per_wg) {
+    gram_partial_body<T1, T2>(g, part, rows_per_wg, blockIdx.x);
+}
+
+// batched over problems: blockIdx.y selects the job
+template <int T1, int T2>
+__global__ __launch_bounds__(256) void k_gram_partial_b(const GramJob *__restrict__ jobs) {
+    const GramJob j = jobs[blockIdx.y];
+    if ((int)blockIdx.x >= j.parts) return;
+    gram_partial_body<T1, T2>(j.g, j.part, j.rpw, blockIdx.x);
+}
+
 // sum of the partial Gram matrices: 64 elements x 16 part-slices per
 // 1024-thread workgroup, slices combined by a fixed tree (bitwise reproducible)
-__global__ __launch_bounds__(1024) void k_gram_final(const double *__restrict__ part, int nparts, int kk,
-                                                     double *__restrict__ out) {
+__device__ __forceinline__ void gram_final_body(const double *__restrict__ part, int nparts, int kk,
+                                                double *__restrict__ out, int bx) {
     __shared__ double red[16][64];
     const int el = threadIdx.x & 63, sl = threadIdx.x >> 6;
-    const int e = blockIdx.x * 64 + el;
+    const int e = bx * 64 + el;
     double s0 = 0.0, s1 = 0.0;
     if (e < kk) {
         int p = sl;
@@ -104,6 +118,17 @@ __global__ __launch_bounds__(1024) void k_gram_final(const double *__restrict__ 
         __syncthreads();
     }
     if (sl == 0 && e < kk) out[e] = red[0][el];
+}
+
+__global__ __launch_bounds__(1024) void k_gram_final(const double *__restrict__ part, int nparts, int kk,
+                                                     double *__restrict__ out) {
+    gram_final_body(part, nparts, kk, out, blockIdx.x);
+}
+
+__global__ __launch_bounds__(1024) void k_gram_final_b(const GramJob *__restrict__ jobs) {
+    const GramJob j = jobs[blockIdx.y];
+    if ((int)blockIdx.x * 64 >= j.kk) return;
+    gram_final_body(j.part, j.parts, j.kk, j.out, blockIdx.x);
 }
 
 int gram_parts(int64_t n) {
@@ -155,12 +180,12 @@ void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s) {
 // (coefficients, a few KB read by every wave, cache resident) straight from
 // the coefficient matrix, so the kernel streams with no LDS staging and no
 // barrier until the fixed-order reduction of the residual norms.
-__global__ __launch_bounds__(256) void k_lincomb(LincombArgs a) {
+__device__ __forceinline__ void lincomb_body(const LincombArgs &a, int64_t bx) {
     __shared__ double nred[4][4][16];
     const int m = a.m, nin = a.nin, nout = a.nout;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int64_t w0 = (int64_t)blockIdx.x * 64 + 16 * wave;   // this wave's 16 rows
+    const int64_t w0 = bx * 64 + 16 * wave;   // this wave's 16 rows
     const int64_t ra = w0 + li;                                   // row of this lane's A values
     const bool rok = ra < a.n;
     double4_t xkeep = (double4_t){0.0, 0.0, 0.0, 0.0};
@@ -221,9 +246,17 @@ __global__ __launch_bounds__(256) void k_lincomb(LincombArgs a) {
             double s = 0.0;
             for (int w = 0; w < 4; w++)
                 for (int g = 0; g < 4; g++) s += nred[w][g][tid];
-            a.norm_part[(int64_t)blockIdx.x * m + tid] = s;
+            a.norm_part[bx * m + tid] = s;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_lincomb(LincombArgs a) { lincomb_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_lincomb_b(const LincombArgs *__restrict__ tab) {
+    const LincombArgs a = tab[blockIdx.y];
+    if ((int64_t)blockIdx.x * 64 >= a.n) return;
+    lincomb_body(a, blockIdx.x);
 }
 
 void lincomb(const LincombArgs &a, hipStream_t s) {
@@ -238,10 +271,9 @@ int64_t lincomb_norm_parts(int64_t n) { return (n + 63) / 64; }
 
 // sum of per-workgroup partial column sums: one 1024-thread workgroup per
 // column, strided partial sums combined by a fixed tree (bitwise reproducible)
-__global__ __launch_bounds__(1024) void k_colsum_final(const double *__restrict__ part, int64_t nparts, int m,
-                                                       double *__restrict__ out) {
+__device__ __forceinline__ void colsum_body(const double *__restrict__ part, int64_t nparts, int m,
+                                            double *__restrict__ out, int j) {
     __shared__ double red[1024];
-    const int j = blockIdx.x;
     double s0 = 0.0, s1 = 0.0;
     int64_t p = threadIdx.x;
     for (; p + 1024 < nparts; p += 2048) {
@@ -256,6 +288,16 @@ __global__ __launch_bounds__(1024) void k_colsum_final(const double *__restrict_
         __syncthreads();
     }
     if (threadIdx.x == 0) out[j] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void k_colsum_final(const double *__restrict__ part, int64_t nparts, int m,
+                                                       double *__restrict__ out) {
+    colsum_body(part, nparts, m, out, blockIdx.x);
+}
+
+__global__ __launch_bounds__(1024) void k_colsum_final_b(const ColsumJob *__restrict__ jobs) {
+    const ColsumJob j = jobs[blockIdx.y];
+    colsum_body(j.part, j.nparts, j.m, j.out, blockIdx.x);
 }
 
 // *p = v as a kernel (a memset cannot be recorded in a captured graph)
@@ -333,6 +375,16 @@ __global__ __launch_bounds__(256) void k_precond_jacobi(double *__restrict__ W, 
     W[e] = W[e] / guard_den(diag[r] - mu[j], delta);
 }
 
+template <int M>
+__global__ __launch_bounds__(256) void k_precond_jacobi_b(const JacobiJob *__restrict__ jobs) {
+    const JacobiJob jb = jobs[blockIdx.y];
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= jb.n * M) return;
+    const int64_t r = e / M;
+    const int j = (int)(e - r * M);
+    jb.W[e] = jb.W[e] / guard_den(jb.diag[r] - jb.mu[j], jb.delta);
+}
+
 // One workgroup per 64-row chunk: W_b = Q diag(1/g(lambda - mu_j)) Q^T R_b.
 __global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W, const double *__restrict__ Q,
                                                          const double *__restrict__ lam,
@@ -370,6 +422,67 @@ __global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W,
             W[(r0 + i) * m + j] = s;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches: one launch runs the same step for `count` problems whose
+// arguments sit in a device table; blockIdx.y selects the problem and the
+// blocks a smaller problem does not need return at once.
+// ---------------------------------------------------------------------------
+void gram_batched(const GramJob *jobs, int count, int K1, int K2, int max_parts, hipStream_t s) {
+    const int T1 = (K1 + 15) / 16, T2 = (K2 + 15) / 16;
+    const dim3 grid((unsigned)max_parts, (unsigned)count);
+#define GB(a, b) if (T1 == a && T2 == b) { hipLaunchKernelGGL((k_gram_partial_b<a, b>), grid, dim3(256), 0, s, jobs); } else
+    GB(1, 1) GB(1, 2) GB(1, 3) GB(2, 1) GB(2, 2) GB(2, 3) GB(3, 1) GB(3, 2) GB(3, 3)
+        fail(HSYM_E_UNSUPPORTED, "gram shape");
+#undef GB
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_gram_final_b, dim3((unsigned)((K1 * K2 + 63) / 64), (unsigned)count), dim3(1024), 0, s, jobs);
+    HIPCHK(hipGetLastError());
+}
+
+void lincomb_batched(const LincombArgs *tab, int count, int64_t max_n, hipStream_t s) {
+    hipLaunchKernelGGL(k_lincomb_b, dim3((unsigned)((max_n + 63) / 64), (unsigned)count), dim3(256), 0, s, tab);
+    HIPCHK(hipGetLastError());
+}
+
+void colsum_batched(const ColsumJob *jobs, int count, int m, hipStream_t s) {
+    hipLaunchKernelGGL(k_colsum_final_b, dim3((unsigned)m, (unsigned)count), dim3(1024), 0, s, jobs);
+    HIPCHK(hipGetLastError());
+}
+
+void jacobi_batched(const JacobiJob *jobs, int count, int m, int64_t max_n, hipStream_t s) {
+    const dim3 grid((unsigned)((max_n * m + 255) / 256), (unsigned)count);
+    switch (m) {
+#define HSYM_JB(MM) case MM: hipLaunchKernelGGL(k_precond_jacobi_b<MM>, grid, dim3(256), 0, s, jobs); break;
+        HSYM_JB(1) HSYM_JB(2) HSYM_JB(3) HSYM_JB(4) HSYM_JB(5) HSYM_JB(6) HSYM_JB(7) HSYM_JB(8)
+        HSYM_JB(9) HSYM_JB(10) HSYM_JB(11) HSYM_JB(12) HSYM_JB(13) HSYM_JB(14) HSYM_JB(15) HSYM_JB(16)
+#undef HSYM_JB
+        default: fail(HSYM_E_INVALID_ARG, "block width must be 1..16");
+    }
+    HIPCHK(hipGetLastError());
+}
+
+__global__ void k_set_ints(int *const *__restrict__ p, int count, int v) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < count) *p[i] = v;
+}
+
+void set_ints(int *const *p, int count, int v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_ints, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count, v);
+    HIPCHK(hipGetLastError());
+}
+
+// dst[i*words .. (i+1)*words) = src[i][0 .. words), 32-bit words, one workgroup per item
+__global__ __launch_bounds__(64) void k_gather_words(const int *const *__restrict__ src, int *__restrict__ dst,
+                                                     int words) {
+    const int *a = src[blockIdx.x];
+    for (int w = threadIdx.x; w < words; w += 64) dst[(int64_t)blockIdx.x * words + w] = a[w];
+}
+
+void gather_words(const int *const *src, int *dst, int words, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_words, dim3((unsigned)count), dim3(64), 0, s, src, dst, words);
+    HIPCHK(hipGetLastError());
 }
 
 void precond_apply(hsym_matrix *H, int kind, double *W, const double *mu, double delta, int m, hipStream_t s) {

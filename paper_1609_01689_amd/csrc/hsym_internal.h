@@ -110,6 +110,32 @@ void spmm_launch(hsym_matrix *H, int m, const void *X, int xprec, int64_t ldx, v
                  int64_t ldy, void *partials, hipStream_t s);
 size_t spmm_partial_bytes(hsym_matrix *H, int m);
 
+// one matrix of a batched SpMM (fp64 blocks with leading dimension m)
+struct SpmmJob {
+    const int64_t *ptp;
+    const TileDesc *tiles;
+    const uint32_t *idx;
+    const void *vals;
+    const void *diag;
+    const double *X;
+    int64_t ldx;
+    double *Y;
+    int64_t ldy;
+    double *partials;
+    int64_t n;
+    int R, C, G;
+    int64_t npanels;
+    int m;
+    const int32_t *red_chunks;
+    const int64_t *red_ptr;
+    const int32_t *red_slot;
+    int64_t nred;
+};
+SpmmJob spmm_job(hsym_matrix *H, int m, const double *X, double *Y, double *partials);
+// jobs: device table; host: the same table on the host (for the launch shape).
+// Every matrix has the given storage; m is the same for all.
+void spmm_batched(const SpmmJob *jobs, const SpmmJob *host, int count, int m, int storage, hipStream_t s);
+
 // small parallel-for on host threads
 void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)> &fn);
 int host_threads();

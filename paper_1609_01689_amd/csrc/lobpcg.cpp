@@ -9,6 +9,8 @@
 // orthonormal basis of the W,P-components of the new X made orthogonal to the
 // new X, so span{X_new, P_new} equals span{X_new, (I - X X^T) X_new} of step 10
 // and no full-size pass is needed to orthogonalise P.
+#include <atomic>
+#include <memory>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -100,6 +102,7 @@ struct Lobpcg {
     // with the preconditioner, phase B
     hipGraphExec_t graph_a[2] = {nullptr, nullptr}, graph_b = nullptr;
     bool capturing = false;
+    uint64_t serial = 0;          // unique per context (batch tables are keyed by it)
 
     template <class T>
     T *dalloc(size_t count) {
@@ -126,6 +129,8 @@ struct Lobpcg {
 
     void setup(hsym_matrix *H_, int nev_, int m_, double tol_, const double *X0, int pc, const lobpcg_opts *opts,
                hipStream_t s_) {
+        static std::atomic<uint64_t> next_serial{1};
+        serial = next_serial++;
         H = H_; s = s_; n = H->n; m = m_; nev = nev_; tol = tol_; precond = pc;
         lobpcg_opts_default(&o);
         if (opts) o = *opts;
@@ -306,16 +311,22 @@ struct Lobpcg {
     // apply H (the one SpMM of the iteration), Rayleigh-Ritz (steps 7-9), the
     // update of X, P, AX, AP (step 10) fused with the next residual, and post
     // the status copy.  Returns false when the flag copy must be awaited again.
+    // a deficient W (flag copy complete): replace the flagged columns and redo
+    // the first Cholesky-QR stage, ending with a new flag copy
+    void repair_once() {
+        const int flag = st_h->flags[0];
+        if (orth_attempt >= 3) fail(HSYM_E_BREAKDOWN, "block stays rank deficient after 3 random repairs");
+        int mask = flag & ((1 << m) - 1);
+        rep.w_replaced += __builtin_popcount((unsigned)mask);
+        gauss_fill(W, n, m, m, o.seed * 1000003ULL + (uint64_t)it * 101ULL + 7ULL + (uint64_t)orth_attempt, 10,
+                   mask, s);
+        orth_attempt++;
+        orth_part1();
+    }
+
     bool advance_b() {
-        int flag = st_h->flags[0];
-        if (flag) {
-            if (orth_attempt >= 3) fail(HSYM_E_BREAKDOWN, "block stays rank deficient after 3 random repairs");
-            int mask = flag & ((1 << m) - 1);
-            rep.w_replaced += __builtin_popcount((unsigned)mask);
-            gauss_fill(W, n, m, m, o.seed * 1000003ULL + (uint64_t)it * 101ULL + 7ULL + (uint64_t)orth_attempt, 10,
-                       mask, s);
-            orth_attempt++;
-            orth_part1();
+        if (st_h->flags[0]) {
+            repair_once();
             return false;
         }
         auto body = [&] {
@@ -380,6 +391,261 @@ struct Lobpcg {
         rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
 };
+
+// ---------------------------------------------------------------------------
+// Batched steady-state iterations.  Contexts that are small, in the steady
+// state (P present), use the Jacobi or no preconditioner and record no
+// graphs are stepped together: every step of the iteration is one launch
+// for all of them (argument tables in device memory, one problem per
+// blockIdx.y), on one stream, with the two host synchronisation points of
+// the iteration shared.  The arithmetic of each problem is that of
+// Lobpcg::advance_a / advance_b; only the launches are merged.
+// ---------------------------------------------------------------------------
+constexpr int64_t BATCH_MAX_N = (int64_t)1 << 18;   // larger problems fill the GPU alone
+constexpr int BATCH_CAP = 256;
+
+static bool batchable(const Lobpcg &L) {
+    return L.have_p && !L.o.graph && L.n <= BATCH_MAX_N &&
+           (L.precond == HSYM_PRECOND_NONE || L.precond == HSYM_PRECOND_JACOBI);
+}
+
+struct BatchPlan {
+    hipStream_t bs = nullptr;
+    std::vector<std::pair<const Lobpcg *, uint64_t>> key;   // contexts the tables describe
+    // device tables (one allocation) and their pinned staging
+    char *dev = nullptr, *pin = nullptr;
+    size_t bytes = 0;
+    GramJob *gA = nullptr, *gW = nullptr, *gS = nullptr;
+    LincombArgs *lcO = nullptr, *lcL2 = nullptr, *lcU = nullptr;
+    ColsumJob *cs = nullptr;
+    SpmmJob *sp = nullptr;
+    int **flag_ptr = nullptr;
+    const int **stat_src = nullptr;
+    int *stat_dst = nullptr;       // count x Status, device
+    JacobiJob *jac = nullptr;      // per round
+    double *mu = nullptr;          // per round: count x 16
+    // host-side copies needed for launch shapes and the small kernels
+    std::vector<SpmmJob> sp_h;
+    std::vector<OrthArgs> o0, o1, o2;
+    std::vector<RRArgs> rr;
+    int m = 0, storage = 0, count = 0;
+    int64_t max_n = 0;
+    int maxpA = 0, maxpW = 0, maxpS = 0;
+
+    ~BatchPlan() {
+        if (dev) (void)hipFree(dev);
+        if (pin) (void)hipHostFree(pin);
+        if (bs) (void)hipStreamDestroy(bs);
+    }
+
+    // (re)build the tables for the contexts in cs
+    void build(const std::vector<Lobpcg *> &ctxs) {
+        count = (int)ctxs.size();
+        m = ctxs[0]->m;
+        storage = ctxs[0]->H->storage;
+        if (!bs) HIPCHK(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
+        if (!dev) {
+            // layout for BATCH_CAP problems: offsets first, then one allocation
+            size_t off = 0;
+            auto at = [&](size_t each) {
+                off = (off + 255) & ~(size_t)255;
+                const size_t o = off;
+                off += each * BATCH_CAP;
+                return o;
+            };
+            const size_t oA = at(sizeof(GramJob)), oW = at(sizeof(GramJob)), oS = at(sizeof(GramJob));
+            const size_t oO = at(sizeof(LincombArgs)), o2 = at(sizeof(LincombArgs)), oU = at(sizeof(LincombArgs));
+            const size_t oC = at(sizeof(ColsumJob)), oP = at(sizeof(SpmmJob)), oF = at(sizeof(int *));
+            const size_t oR = at(sizeof(int *)), oT = at(sizeof(Status)), oJ = at(sizeof(JacobiJob));
+            const size_t oM = at(sizeof(double) * HSYM_MAX_BLOCK);
+            bytes = off;
+            HIPCHK(hipMalloc((void **)&dev, bytes));
+            HIPCHK(hipHostMalloc((void **)&pin, bytes, hipHostMallocDefault));
+            gA = (GramJob *)(dev + oA); gW = (GramJob *)(dev + oW); gS = (GramJob *)(dev + oS);
+            lcO = (LincombArgs *)(dev + oO); lcL2 = (LincombArgs *)(dev + o2); lcU = (LincombArgs *)(dev + oU);
+            cs = (ColsumJob *)(dev + oC); sp = (SpmmJob *)(dev + oP); flag_ptr = (int **)(dev + oF);
+            stat_src = (const int **)(dev + oR); stat_dst = (int *)(dev + oT); jac = (JacobiJob *)(dev + oJ);
+            mu = (double *)(dev + oM);
+        }
+        auto host = [&](const void *d) { return pin + ((const char *)d - dev); };
+        GramJob *hgA = (GramJob *)host(gA), *hgW = (GramJob *)host(gW), *hgS = (GramJob *)host(gS);
+        LincombArgs *hlO = (LincombArgs *)host(lcO), *hl2 = (LincombArgs *)host(lcL2), *hlU = (LincombArgs *)host(lcU);
+        ColsumJob *hcs = (ColsumJob *)host(cs);
+        SpmmJob *hsp = (SpmmJob *)host(sp);
+        int **hfl = (int **)host(flag_ptr);
+        const int **hss = (const int **)host(stat_src);
+        sp_h.assign((size_t)count, SpmmJob{});
+        o0.clear(); o1.clear(); o2.clear(); rr.clear();
+        key.clear();
+        max_n = 0; maxpA = maxpW = maxpS = 0;
+        auto gjob = [&](Lobpcg &L, const double *a0, const double *a1, const double *a2, const double *b0,
+                        const double *b1, const double *b2, int na, int nb, int &maxp) {
+            GramJob j{};
+            j.g.a[0] = a0; j.g.a[1] = a1; j.g.a[2] = a2; j.g.b[0] = b0; j.g.b[1] = b1; j.g.b[2] = b2;
+            j.g.na = na; j.g.nb = nb; j.g.m = L.m; j.g.n = L.n;
+            j.parts = gram_parts(L.n);
+            int64_t rpw = (L.n + j.parts - 1) / j.parts;
+            j.rpw = (rpw + 3) / 4 * 4;
+            j.part = L.gram_scr;
+            j.kk = na * L.m * nb * L.m;
+            j.out = L.gbuf;
+            maxp = std::max(maxp, j.parts);
+            return j;
+        };
+        for (int i = 0; i < count; i++) {
+            Lobpcg &L = *ctxs[(size_t)i];
+            key.emplace_back(&L, L.serial);
+            max_n = std::max(max_n, L.n);
+            hgA[i] = gjob(L, L.X, L.P, L.W, L.W, nullptr, nullptr, 3, 1, maxpA);
+            hgW[i] = gjob(L, L.W, nullptr, nullptr, L.W, nullptr, nullptr, 1, 1, maxpW);
+            hgS[i] = gjob(L, L.X, L.W, L.P, L.AX, L.AW, L.AP, 3, 3, maxpS);
+            LincombArgs lo{};
+            lo.in[0] = L.X; lo.in[1] = L.P; lo.in[2] = L.W; lo.out[0] = L.W; lo.coef = L.coef; lo.ldc = L.m;
+            lo.nin = 3; lo.nout = 1; lo.nsets = 1; lo.m = L.m; lo.n = L.n;
+            hlO[i] = lo;
+            LincombArgs l2{};
+            l2.in[0] = L.W; l2.out[0] = L.W; l2.coef = L.coef; l2.ldc = L.m; l2.nin = 1; l2.nout = 1; l2.nsets = 1;
+            l2.m = L.m; l2.n = L.n;
+            hl2[i] = l2;
+            LincombArgs u{};
+            u.in[0] = L.X; u.in[1] = L.W; u.in[2] = L.P; u.in[3] = L.AX; u.in[4] = L.AW; u.in[5] = L.AP;
+            u.out[0] = L.X; u.out[1] = L.P; u.out[2] = L.AX; u.out[3] = L.AP;
+            u.coef = L.rrcoef; u.ldc = 2 * L.m; u.nin = 3; u.nout = 2; u.nsets = 2; u.m = L.m; u.n = L.n;
+            u.theta = L.st_d->theta; u.res = L.W; u.norm_part = L.norm_part;
+            hlU[i] = u;
+            hcs[i] = ColsumJob{L.norm_part, lincomb_norm_parts(L.n), L.m, L.st_d->norms};
+            hsp[i] = spmm_job(L.H, L.m, L.W, L.AW, L.spmm_part);
+            sp_h[(size_t)i] = hsp[i];
+            hfl[i] = &L.st_d->flags[0];
+            hss[i] = (const int *)L.st_d;
+            o0.push_back(OrthArgs{L.gbuf, L.coef, &L.st_d->flags[0], 2, L.m, 0});
+            o1.push_back(OrthArgs{L.gbuf, L.coef, &L.st_d->flags[0], 2, L.m, 1});
+            o2.push_back(OrthArgs{L.gbuf, L.coef, &L.st_d->flags[0], 0, L.m, 2});
+            RRArgs r{};
+            r.gram = L.gbuf; r.coef = L.rrcoef; r.theta = L.st_d->theta; r.evals_all = nullptr;
+            r.flag = &L.st_d->flags[1]; r.nblk = 3; r.m = L.m;
+            rr.push_back(r);
+        }
+        // the static tables: everything before the per-round Jacobi jobs
+        const size_t static_bytes = (size_t)((char *)jac - dev);
+        HIPCHK(hipMemcpyAsync(dev, pin, static_bytes, hipMemcpyHostToDevice, bs));
+    }
+
+    bool matches(const std::vector<Lobpcg *> &ctxs) const {
+        if (!dev || ctxs.size() != key.size()) return false;
+        for (size_t i = 0; i < ctxs.size(); i++)
+            if (key[i].first != ctxs[i] || key[i].second != ctxs[i]->serial) return false;
+        return true;
+    }
+
+    // one iteration of every context (all evaluated, none done)
+    void round(const std::vector<Lobpcg *> &ctxs) {
+        std::vector<hipStream_t> own;
+        for (Lobpcg *L : ctxs) {
+            own.push_back(L->s);
+            L->s = bs;
+        }
+        auto restore = [&] {
+            for (size_t i = 0; i < ctxs.size(); i++) ctxs[i]->s = own[i];
+        };
+        try {
+            // ---- phase A: shifts, preconditioner, first Cholesky-QR stage ----
+            JacobiJob *hj = (JacobiJob *)(pin + ((char *)jac - dev));
+            double *hmu = (double *)(pin + ((char *)mu - dev));
+            int npre = 0;
+            for (int i = 0; i < count; i++) {
+                Lobpcg &L = *ctxs[(size_t)i];
+                L.it++;
+                L.orth_attempt = 0;
+                L.orth_lc = LincombArgs{};
+                L.orth_lc.in[0] = L.X; L.orth_lc.in[1] = L.P; L.orth_lc.in[2] = L.W; L.orth_lc.out[0] = L.W;
+                L.orth_lc.coef = L.coef; L.orth_lc.ldc = L.m; L.orth_lc.nin = 3; L.orth_lc.nout = 1;
+                L.orth_lc.nsets = 1; L.orth_lc.m = L.m; L.orth_lc.n = L.n;
+                if (L.shifts(L.rho_, L.rnorm_, L.st_h->theta)) {
+                    double *row = hmu + (size_t)npre * HSYM_MAX_BLOCK;
+                    for (int j = 0; j < L.m; j++) row[j] = L.mu_h[j];
+                    hj[npre] = JacobiJob{L.W, L.H->diag64, mu + (size_t)npre * HSYM_MAX_BLOCK,
+                                         L.o.guard * L.H->norm1, L.n};
+                    npre++;
+                }
+            }
+            if (npre) {
+                HIPCHK(hipMemcpyAsync(jac, hj, sizeof(JacobiJob) * (size_t)npre, hipMemcpyHostToDevice, bs));
+                HIPCHK(hipMemcpyAsync(mu, hmu, sizeof(double) * HSYM_MAX_BLOCK * (size_t)npre,
+                                      hipMemcpyHostToDevice, bs));
+                jacobi_batched(jac, npre, m, max_n, bs);
+            }
+            set_ints(flag_ptr, count, 0, bs);
+            gram_batched(gA, count, 3 * m, m, maxpA, bs);
+            small_orth(o0.data(), count, bs);
+            lincomb_batched(lcO, count, max_n, bs);
+            gram_batched(gA, count, 3 * m, m, maxpA, bs);
+            small_orth(o1.data(), count, bs);
+            gather_words(stat_src, stat_dst, (int)(sizeof(Status) / 4), count, bs);
+            Status *hst = (Status *)(pin + ((char *)stat_dst - dev));
+            HIPCHK(hipMemcpyAsync(hst, stat_dst, sizeof(Status) * (size_t)count, hipMemcpyDeviceToHost, bs));
+            HIPCHK(hipStreamSynchronize(bs));
+            // rare: deficient W blocks are repaired one by one (same stream)
+            for (int i = 0; i < count; i++) {
+                Lobpcg &L = *ctxs[(size_t)i];
+                L.st_h->flags[0] = hst[i].flags[0];
+                while (L.st_h->flags[0]) {
+                    L.repair_once();
+                    HIPCHK(hipStreamSynchronize(bs));
+                }
+            }
+            // ---- phase B: second stage, SpMM, Rayleigh-Ritz, update ----
+            lincomb_batched(lcO, count, max_n, bs);
+            gram_batched(gW, count, m, m, maxpW, bs);
+            small_orth(o2.data(), count, bs);
+            lincomb_batched(lcL2, count, max_n, bs);
+            spmm_batched(sp, sp_h.data(), count, m, storage, bs);
+            gram_batched(gS, count, 3 * m, 3 * m, maxpS, bs);
+            small_rr(rr.data(), count, bs);
+            lincomb_batched(lcU, count, max_n, bs);
+            colsum_batched(cs, count, m, bs);
+            gather_words(stat_src, stat_dst, (int)(sizeof(Status) / 4), count, bs);
+            HIPCHK(hipMemcpyAsync(hst, stat_dst, sizeof(Status) * (size_t)count, hipMemcpyDeviceToHost, bs));
+            HIPCHK(hipStreamSynchronize(bs));
+            for (int i = 0; i < count; i++) {
+                Lobpcg &L = *ctxs[(size_t)i];
+                memcpy(L.st_h, &hst[i], sizeof(Status));
+                L.rep.spmm_calls++;
+                L.rep.batched_iters++;
+            }
+        } catch (...) {
+            (void)hipStreamSynchronize(bs);
+            restore();
+            throw;
+        }
+        restore();
+    }
+};
+
+// per stepping thread: the plans of the batches stepped last (one per
+// block width and storage precision)
+struct BatchPlans {
+    std::vector<std::pair<int, std::unique_ptr<BatchPlan>>> plans;
+    BatchPlan &get(int key) {
+        for (auto &p : plans)
+            if (p.first == key) return *p.second;
+        plans.emplace_back(key, std::make_unique<BatchPlan>());
+        return *plans.back().second;
+    }
+};
+
+static void step_batched(std::vector<Lobpcg *> &group) {
+    static thread_local BatchPlans tp;
+    const int key = group[0]->m * 2 + group[0]->H->storage;
+    // groups larger than a plan's capacity run in slices, each with its plan
+    for (size_t b0 = 0, slice = 0; b0 < group.size(); b0 += BATCH_CAP, slice++) {
+        std::vector<Lobpcg *> part(group.begin() + (long)b0,
+                                   group.begin() + (long)std::min(group.size(), b0 + BATCH_CAP));
+        BatchPlan &P = tp.get(key + (int)slice * 64);
+        if (!P.matches(part)) P.build(part);
+        P.round(part);
+    }
+}
 
 }  // namespace hsym
 
@@ -499,8 +765,30 @@ int lobpcg_ctx_step(lobpcg_ctx_t *ctxs, int count, int iters) {
                 if (!L.evaluate()) act.push_back(&L);
             }
             if (act.empty()) break;
-            for (Lobpcg *L : act) L->advance_a();
-            pend = act;
+            // small steady-state contexts of equal block width and storage
+            // step together (one launch per step for all of them)
+            std::vector<std::vector<Lobpcg *>> groups;
+            std::vector<Lobpcg *> solo;
+            for (Lobpcg *L : act) {
+                if (!batchable(*L)) {
+                    solo.push_back(L);
+                    continue;
+                }
+                bool placed = false;
+                for (auto &g : groups)
+                    if (g[0]->m == L->m && g[0]->H->storage == L->H->storage) {
+                        g.push_back(L);
+                        placed = true;
+                        break;
+                    }
+                if (!placed) groups.push_back({L});
+            }
+            for (auto &g : groups)
+                if (g.size() < 2) solo.push_back(g[0]);
+            for (Lobpcg *L : solo) L->advance_a();
+            for (auto &g : groups)
+                if (g.size() >= 2) step_batched(g);
+            pend = solo;
             while (!pend.empty()) {
                 std::vector<Lobpcg *> next;
                 for (Lobpcg *L : pend) {

@@ -101,21 +101,20 @@ __device__ __forceinline__ void read_row(const T *rowp, int r, int k0, double *o
 // precisions (a product of two fp32 numbers is exact in fp64, and the LDS fp64
 // atomic add is several times cheaper than the fp32 one on gfx950)
 template <int M, typename T, typename XIN, typename YT>
-__global__ __launch_bounds__(1024) void k_spmm_panel(
+__device__ __forceinline__ void spmm_panel_body(
     const int64_t *__restrict__ ptp, const TileDesc *__restrict__ tiles, const uint32_t *__restrict__ idx,
     const T *__restrict__ vals, const T *__restrict__ diag, const XIN *__restrict__ X, int64_t ldx,
     YT *__restrict__ Y, int64_t ldy, double *__restrict__ partials, int64_t n, int R, int C, int G,
-    int64_t npanels, int m) {
+    int64_t npanels, int m, int64_t blk, unsigned char *smem_raw) {
     using XL = RowLay<M, T, false>;
     using AL = RowLay<M, double, true>;
     constexpr int NT = 1024, MW = mw_of(M), LPE = M / MW, GK = NT / LPE;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     double *acc = reinterpret_cast<double *>(smem_raw);
     double *ts = acc + (size_t)R * M;
     T *xp = reinterpret_cast<T *>(ts + (size_t)C * M);
     T *xs = xp + (size_t)R * M;
     const int tid = threadIdx.x, g = tid / LPE, q = tid % LPE, k0 = q * MW;
-    const int64_t p = xcd_panel(blockIdx.x, npanels);
+    const int64_t p = xcd_panel(blk, npanels);
     const int64_t row0 = p * (int64_t)R;
     const int nrow = (int)((n - row0) < R ? (n - row0) : R);
 
@@ -225,14 +224,36 @@ __global__ __launch_bounds__(1024) void k_spmm_panel(
     }
 }
 
+template <int M, typename T, typename XIN, typename YT>
+__global__ __launch_bounds__(1024) void k_spmm_panel(
+    const int64_t *__restrict__ ptp, const TileDesc *__restrict__ tiles, const uint32_t *__restrict__ idx,
+    const T *__restrict__ vals, const T *__restrict__ diag, const XIN *__restrict__ X, int64_t ldx,
+    YT *__restrict__ Y, int64_t ldy, double *__restrict__ partials, int64_t n, int R, int C, int G,
+    int64_t npanels, int m) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    spmm_panel_body<M, T, XIN, YT>(ptp, tiles, idx, vals, diag, X, ldx, Y, ldy, partials, n, R, C, G, npanels, m,
+                                   blockIdx.x, smem_raw);
+}
+
+// batched over matrices (fp64 blocks): blockIdx.y selects the job
+template <int M, typename T>
+__global__ __launch_bounds__(1024) void k_spmm_panel_b(const SpmmJob *__restrict__ jobs) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const SpmmJob J = jobs[blockIdx.y];
+    if ((int64_t)blockIdx.x >= J.npanels) return;
+    spmm_panel_body<M, T, double, double>(J.ptp, J.tiles, J.idx, (const T *)J.vals, (const T *)J.diag, J.X, J.ldx,
+                                          J.Y, J.ldy, J.partials, J.n, J.R, J.C, J.G, J.npanels, J.m, blockIdx.x,
+                                          smem_raw);
+}
+
 // Y[chunk rows] += sum of the partial slots of that chunk, in slot order.
 template <int M, typename YT, int NT>
-__global__ __launch_bounds__(NT) void k_spmm_reduce(const int32_t *__restrict__ red_chunks,
-                                                    const int64_t *__restrict__ red_ptr,
-                                                    const int32_t *__restrict__ red_slot,
-                                                    const double *__restrict__ partials, YT *__restrict__ Y,
-                                                    int64_t ldy, int64_t n, int C, int m) {
-    const int64_t g = red_chunks[blockIdx.x];
+__device__ __forceinline__ void spmm_reduce_body(const int32_t *__restrict__ red_chunks,
+                                                 const int64_t *__restrict__ red_ptr,
+                                                 const int32_t *__restrict__ red_slot,
+                                                 const double *__restrict__ partials, YT *__restrict__ Y,
+                                                 int64_t ldy, int64_t n, int C, int m, int64_t blk) {
+    const int64_t g = red_chunks[blk];
     const int64_t col0 = g * C;
     const int ncol = (int)((n - col0) < C ? (n - col0) : C);
     const int64_t q0 = red_ptr[g], q1 = red_ptr[g + 1];
@@ -244,6 +265,23 @@ __global__ __launch_bounds__(NT) void k_spmm_reduce(const int32_t *__restrict__ 
         YT *y = Y + (col0 + r) * ldy + k;
         *y = (YT)((double)*y + s);
     }
+}
+
+template <int M, typename YT, int NT>
+__global__ __launch_bounds__(NT) void k_spmm_reduce(const int32_t *__restrict__ red_chunks,
+                                                    const int64_t *__restrict__ red_ptr,
+                                                    const int32_t *__restrict__ red_slot,
+                                                    const double *__restrict__ partials, YT *__restrict__ Y,
+                                                    int64_t ldy, int64_t n, int C, int m) {
+    spmm_reduce_body<M, YT, NT>(red_chunks, red_ptr, red_slot, partials, Y, ldy, n, C, m, blockIdx.x);
+}
+
+template <int M, int NT>
+__global__ __launch_bounds__(NT) void k_spmm_reduce_b(const SpmmJob *__restrict__ jobs) {
+    const SpmmJob J = jobs[blockIdx.y];
+    if ((int64_t)blockIdx.x >= J.nred) return;
+    spmm_reduce_body<M, double, NT>(J.red_chunks, J.red_ptr, J.red_slot, J.partials, J.Y, J.ldy, J.n, J.C, J.m,
+                                    blockIdx.x);
 }
 
 template <int M, typename T, typename XIN, typename YT>
@@ -279,6 +317,52 @@ static void launch_m(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y,
         case 4: launch_typed<4, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
         case 8: launch_typed<8, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
         default: launch_typed<16, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
+    }
+}
+
+SpmmJob spmm_job(hsym_matrix *H, int m, const double *X, double *Y, double *partials) {
+    const DeviceTiles &dt = H->tiles;
+    SpmmJob J{};
+    J.ptp = dt.panel_tile_ptr; J.tiles = dt.tiles; J.idx = dt.idx; J.vals = dt.vals;
+    J.diag = H->storage == HSYM_FP64 ? (const void *)H->diag64 : (const void *)H->diag32;
+    J.X = X; J.ldx = m; J.Y = Y; J.ldy = m; J.partials = partials;
+    J.n = H->n; J.R = dt.R; J.C = dt.C; J.G = dt.G; J.npanels = dt.npanels; J.m = m;
+    J.red_chunks = dt.red_chunks; J.red_ptr = dt.red_ptr; J.red_slot = dt.red_slot; J.nred = dt.nred_chunks;
+    return J;
+}
+
+template <int M, typename T>
+static void batched_typed(const SpmmJob *jobs, const SpmmJob *host, int count, hipStream_t s) {
+    size_t lds = 0;
+    int64_t maxp = 0, maxr = 0;
+    for (int i = 0; i < count; i++) {
+        lds = std::max(lds, (size_t)(host[i].R + host[i].C) * M * (sizeof(double) + sizeof(T)));
+        maxp = std::max(maxp, host[i].npanels);
+        maxr = std::max(maxr, host[i].nred);
+    }
+    if (lds > 160 * 1024) fail(HSYM_E_UNSUPPORTED, "block width too large for a handle's panel geometry");
+    auto kp = k_spmm_panel_b<M, T>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        HIPCHK(hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(kp, dim3((unsigned)maxp, (unsigned)count), dim3(1024), lds, s, jobs);
+    HIPCHK(hipGetLastError());
+    if (maxr > 0) {
+        hipLaunchKernelGGL((k_spmm_reduce_b<M, 256>), dim3((unsigned)maxr, (unsigned)count), dim3(256), 0, s, jobs);
+        HIPCHK(hipGetLastError());
+    }
+}
+
+void spmm_batched(const SpmmJob *jobs, const SpmmJob *host, int count, int m, int storage, hipStream_t s) {
+    const bool f64 = storage == HSYM_FP64;
+    switch (round_m(m)) {
+        case 1: if (f64) batched_typed<1, double>(jobs, host, count, s); else batched_typed<1, float>(jobs, host, count, s); break;
+        case 2: if (f64) batched_typed<2, double>(jobs, host, count, s); else batched_typed<2, float>(jobs, host, count, s); break;
+        case 4: if (f64) batched_typed<4, double>(jobs, host, count, s); else batched_typed<4, float>(jobs, host, count, s); break;
+        case 8: if (f64) batched_typed<8, double>(jobs, host, count, s); else batched_typed<8, float>(jobs, host, count, s); break;
+        default: if (f64) batched_typed<16, double>(jobs, host, count, s); else batched_typed<16, float>(jobs, host, count, s); break;
     }
 }
 

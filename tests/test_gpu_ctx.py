@@ -77,3 +77,57 @@ def test_graph_replays_match_eager():
         hs.lobpcg_ctx_destroy(c)
     MA.close()
     MB.close()
+
+
+def test_batched_rounds_match_solo_solves():
+    """lobpcg_ctx_step merges the steady-state iterations of small contexts of
+    equal block width and storage into batched launches.  Every context ends
+    where its solve run alone ends (eigenvalues to 1e-9, iteration counts
+    within rounding), contexts outside a batch (block64, a group of one) are
+    stepped alone, and a context destroyed and created anew mid-run is solved
+    from its start."""
+    cases = [
+        (4000, 1, 4, 8, hs.HSYM_FP64, "jacobi"), (9000, 2, 6, 8, hs.HSYM_FP64, "jacobi"),
+        (2500, 3, 3, 8, hs.HSYM_FP64, "none"), (5000, 4, 5, 8, hs.HSYM_FP32, "jacobi"),
+        (7000, 5, 2, 8, hs.HSYM_FP32, "jacobi"), (6000, 6, 8, 16, hs.HSYM_FP64, "jacobi"),
+        (3000, 7, 10, 16, hs.HSYM_FP64, "jacobi"), (4000, 8, 4, 8, hs.HSYM_FP64, "block64"),
+        (3500, 9, 3, 4, hs.HSYM_FP64, "jacobi"),
+    ]
+    tol = 1e-8
+    mats = [hs.Matrix(hsymgen.generate(n, 40, seed), storage=st, geom_m=m, block64=(pc == "block64"))
+            for n, seed, nev, m, st, pc in cases]
+
+    def opts(seed):
+        return hs.default_lobpcg_opts(seed=seed, keep_history=0)
+
+    alone = []
+    for M, (n, seed, nev, m, st, pc) in zip(mats, cases):
+        s, ev, rep = hs.lobpcg_solve(M.h, nev, m, tol, precond=pc, opts=opts(seed))
+        assert s == hs.HSYM_OK
+        alone.append((ev, rep.iters))
+    ctxs = [hs.lobpcg_ctx_create(M.h, nev, m, tol, precond=pc, opts=opts(seed))
+            for M, (n, seed, nev, m, st, pc) in zip(mats, cases)]
+    for step in range(2000):
+        if step == 6:
+            # replace a batched context: its plan entry must not be reused
+            hs.lobpcg_ctx_destroy(ctxs[1])
+            n, seed, nev, m, st, pc = cases[1]
+            ctxs[1] = hs.lobpcg_ctx_create(mats[1].h, nev, m, tol, precond=pc, opts=opts(seed))
+        hs.lobpcg_ctx_step(ctxs, iters=1)
+        if all(hs.lobpcg_ctx_status(c, cs[2])[0] for c, cs in zip(ctxs, cases)):
+            break
+    for i, (c, (n, seed, nev, m, st, pc), (ev0, it0)) in enumerate(zip(ctxs, cases, alone)):
+        done, s, ev, rep = hs.lobpcg_ctx_status(c, nev)
+        print("case %d n=%d m=%d %s: iters %d (alone %d), batched %d, max rel diff %.2e"
+              % (i, n, m, pc, rep.iters, it0, rep.batched_iters, np.max(np.abs(ev - ev0) / np.abs(ev0))))
+        assert done and s == hs.HSYM_OK
+        assert np.max(np.abs(ev - ev0) / np.abs(ev0)) <= 1e-9
+        assert abs(rep.iters - it0) <= 2
+        if pc == "block64" or m == 4:
+            assert rep.batched_iters == 0          # outside every batch (a group of one for m = 4)
+        else:
+            # batched while another context of its group is still running
+            assert rep.batched_iters >= rep.iters // 2
+        hs.lobpcg_ctx_destroy(c)
+    for M in mats:
+        M.close()
