@@ -107,7 +107,8 @@ def serving(hs, torch, count, seed=5):
     Baseline: the same requests solved one at a time in arrival order with
     fp64 storage (service time = build + solve + free, measured); arrivals
     are Poisson at twice the baseline's solves/s.  The request loop serves
-    the trace with fp32 storage (mixed form) on the device."""
+    the trace with fp32 storage (mixed form) on the device, then the same
+    requests all present at once (its capacity)."""
     import hsymgen
     rng = np.random.default_rng(seed)
     ns = np.round(10 ** rng.uniform(3, np.log10(2e6), count)).astype(np.int64)
@@ -147,6 +148,16 @@ def serving(hs, torch, count, seed=5):
                                   "solves_per_s": count / rep["wall_s"], "converged": ok,
                                   "max_active": rep["max_active_seen"], "rounds": rep["rounds"],
                                   "peak_reserved_GB": rep["peak_reserved_bytes"] / 1e9}}
+    # capacity: the same requests all present at t = 0
+    for q in reqs:
+        q["arrival_s"] = 0.0
+    res, rep = hs.hsym_serve(reqs)
+    lat = np.array([x["latency_s"] for x in res])
+    out["request_loop_saturated"] = {"solves_per_s": count / rep["wall_s"],
+                                     "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                                     "converged": sum(x["status"] == hs.HSYM_OK for x in res),
+                                     "max_active": rep["max_active_seen"]}
+    out["fifo_fp64_capacity_solves_per_s"] = float(1.0 / svc.mean())
     log("serving: %s" % json.dumps(out))
     return out
 
