@@ -314,6 +314,8 @@ typedef struct {
                                of n, block width, storage) runs
                                hsym_autotune_geometry on its matrix, and the class
                                keeps that panel geometry; default 0                 */
+    int loaders;            /* threads that build admitted requests (tile build and
+                               context set-up) in parallel; 1..16, default 2      */
 } hsym_serve_opts;
 
 typedef struct {

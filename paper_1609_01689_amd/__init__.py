@@ -96,7 +96,8 @@ class hsym_request(ctypes.Structure):
 
 class hsym_serve_opts(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("max_active", ctypes.c_int),
-                ("iters_per_round", ctypes.c_int), ("maxit", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("iters_per_round", ctypes.c_int), ("maxit", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("loaders", ctypes.c_int)]
 
 
 class hsym_serve_report(ctypes.Structure):
@@ -369,10 +370,12 @@ def hsym_kernel_orthonormalize(V, B=(), seed=0, stream=None):
     return rep.value
 
 
-def _serve_opts(budget_bytes=0, max_active=0, iters_per_round=0, maxit=0, autotune=False):
+def _serve_opts(budget_bytes=0, max_active=0, iters_per_round=0, maxit=0, autotune=False, loaders=0):
     o = hsym_serve_opts()
     lib().hsym_serve_opts_default(ctypes.byref(o))
     o.autotune = 1 if autotune else 0
+    if loaders:
+        o.loaders = int(loaders)
     if budget_bytes:
         o.budget_bytes = int(budget_bytes)
     if max_active:

@@ -45,7 +45,10 @@ void gauss_fill(double *V, int64_t n, int m, int64_t ld, uint64_t seed, uint64_t
 void sign_fix_copy(const double *X, int m, int nev, int64_t n, double *evecs, double *scratch, hipStream_t s);
 size_t sign_fix_scratch_bytes(int64_t n, int m);
 
-void dots(const double *V, int64_t ldv, int k, const double *w, int64_t n, double *h, hipStream_t s);
+// h[0..k) = V_j . w (V_j = V + j*ldv, n long); scratch >= dots_scratch_bytes(n, k)
+void dots(const double *V, int64_t ldv, int k, const double *w, int64_t n, double *h, double *scratch,
+          hipStream_t s);
+size_t dots_scratch_bytes(int64_t n, int k);
 void sub_vh(const double *V, int64_t ldv, const double *h, int k, double *w, int64_t n, hipStream_t s);
 void axpby2(double *w, const double *v1, const double *ab, const double *v0, int64_t n, hipStream_t s);
 void scale_to(const double *w, const double *nrm2, double *v, int64_t n, hipStream_t s);

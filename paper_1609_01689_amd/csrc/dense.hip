@@ -617,16 +617,53 @@ void to_f32(const double *x, float *y, int64_t cnt, hipStream_t s) {
 // Lanczos helpers: V is k x n (one basis vector per row, contiguous).
 // h = V^T w (one workgroup per basis vector), then w -= V^T h.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_dots(const double *__restrict__ V, int64_t ldv, const double *__restrict__ w,
-                                              int64_t n, double *__restrict__ h) {
-    __shared__ double red[4];
-    const double *v = V + (int64_t)blockIdx.x * ldv;
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) s = fma(v[i], w[i], s);
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+// h[j] = V_j . w for the k vectors V_j (each n long, ld ldv): every
+// workgroup takes DOT_ROWS rows of all k vectors (w staged once in LDS, one
+// wave per vector at a time), then one workgroup per vector sums the
+// per-chunk partials in a fixed order.
+constexpr int DOT_ROWS = 2048;
+
+int dots_parts(int64_t n) { return (int)((n + DOT_ROWS - 1) / DOT_ROWS); }
+
+size_t dots_scratch_bytes(int64_t n, int k) { return (size_t)dots_parts(n) * (size_t)k * sizeof(double); }
+
+__global__ __launch_bounds__(256) void k_dots_part(const double *__restrict__ V, int64_t ldv,
+                                                   const double *__restrict__ w, int64_t n, int k,
+                                                   double *__restrict__ part) {
+    __shared__ double ws[DOT_ROWS];
+    const int64_t r0 = (int64_t)blockIdx.x * DOT_ROWS;
+    const int rows = (int)((n - r0) < DOT_ROWS ? (n - r0) : DOT_ROWS);
+    for (int i = threadIdx.x; i < DOT_ROWS; i += 256) ws[i] = i < rows ? w[r0 + i] : 0.0;
     __syncthreads();
-    if (threadIdx.x == 0) h[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = wave; j < k; j += 4) {
+        const double *v = V + (int64_t)j * ldv + r0;
+        double s0 = 0.0, s1 = 0.0;
+        int i = lane;
+        for (; i + 64 < rows; i += 128) {
+            s0 = fma(v[i], ws[i], s0);
+            s1 = fma(v[i + 64], ws[i + 64], s1);
+        }
+        if (i < rows) s0 = fma(v[i], ws[i], s0);
+        double t = s0 + s1;
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+        if (lane == 0) part[(int64_t)blockIdx.x * k + j] = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dots_final(const double *__restrict__ part, int nparts, int k,
+                                                    double *__restrict__ h) {
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int c = threadIdx.x; c < nparts; c += 256) s += part[(int64_t)c * k + j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) h[j] = red[0];
 }
 
 __global__ __launch_bounds__(256) void k_sub_vh(const double *__restrict__ V, int64_t ldv, const double *__restrict__ h,
@@ -641,8 +678,12 @@ __global__ __launch_bounds__(256) void k_sub_vh(const double *__restrict__ V, in
     w[i] -= s;
 }
 
-void dots(const double *V, int64_t ldv, int k, const double *w, int64_t n, double *h, hipStream_t s) {
-    hipLaunchKernelGGL(k_dots, dim3(k), dim3(256), 0, s, V, ldv, w, n, h);
+void dots(const double *V, int64_t ldv, int k, const double *w, int64_t n, double *h, double *scratch,
+          hipStream_t s) {
+    const int parts = dots_parts(n);
+    hipLaunchKernelGGL(k_dots_part, dim3((unsigned)parts), dim3(256), 0, s, V, ldv, w, n, k, scratch);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_dots_final, dim3((unsigned)k), dim3(256), 0, s, scratch, parts, k, h);
     HIPCHK(hipGetLastError());
 }
 

@@ -135,6 +135,7 @@ extern "C" int lanczos_solve(hsym_t H, int nev, double tol, const double *v0, co
         double *V = (double *)dal(sizeof(double) * (size_t)(kmax + 1) * n);
         double *w = (double *)dal(sizeof(double) * n);
         double *h = (double *)dal(sizeof(double) * (kmax + 1));
+        double *dscr = (double *)dal(dots_scratch_bytes(n, kmax + 1));
         double *alpha = (double *)dal(sizeof(double) * (kmax + 1));
         double *beta2 = (double *)dal(sizeof(double) * (kmax + 1));   // squared norms
         double *beta = (double *)dal(sizeof(double) * (kmax + 1));
@@ -144,7 +145,7 @@ extern "C" int lanczos_solve(hsym_t H, int nev, double tol, const double *v0, co
         // v_1 = v0 / ||v0||
         if (v0) HIPCHK(hipMemcpyAsync(w, v0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
         else gauss_fill(w, n, 1, 1, seed, 9, -1, s);
-        dots(w, n, 1, w, n, beta2, s);
+        dots(w, n, 1, w, n, beta2, dscr, s);
         scale_to(w, beta2, V, n, s);
         const int NEV = 512;
         for (int i = 0; i < 2 * NEV; i++) {
@@ -169,14 +170,14 @@ extern "C" int lanczos_solve(hsym_t H, int nev, double tol, const double *v0, co
                 hipLaunchKernelGGL(k_axpy_dev, dim3(gb), dim3(256), 0, s, w, vj - n, beta + (j - 2), n);
                 HIPCHK(hipGetLastError());
             }
-            dots(vj, n, 1, w, n, alpha + (j - 1), s);
+            dots(vj, n, 1, w, n, alpha + (j - 1), dscr, s);
             hipLaunchKernelGGL(k_axpy_dev, dim3(gb), dim3(256), 0, s, w, vj, alpha + (j - 1), n);
             HIPCHK(hipGetLastError());
             for (int pass = 0; pass < 2; pass++) {
-                dots(V, n, j, w, n, h, s);
+                dots(V, n, j, w, n, h, dscr, s);
                 sub_vh(V, n, h, j, w, n, s);
             }
-            dots(w, n, 1, w, n, beta2 + (j - 1), s);
+            dots(w, n, 1, w, n, beta2 + (j - 1), dscr, s);
             hipLaunchKernelGGL(k_sqrt_to, dim3(1), dim3(1), 0, s, beta2 + (j - 1), beta + (j - 1));
             HIPCHK(hipGetLastError());
             scale_to(w, beta2 + (j - 1), V + (int64_t)j * n, n, s);

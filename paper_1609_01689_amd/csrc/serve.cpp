@@ -1,7 +1,7 @@
 // Request loop around the solver: continuous batching of LOBPCG solves at
 // iteration granularity.  Requests arrive over time (arrival_s), are admitted
 // in arrival order while their estimated device memory fits a budget, are
-// loaded (tile-format build and context set-up) by a loader thread, and every
+// loaded (tile-format build and context set-up) by loader threads, and every
 // active request is advanced by a few iterations per scheduling round, so a
 // short request does not wait for a long one to finish.  The paper runs one
 // solve per job; this loop is the serving layer around its method.
@@ -142,13 +142,14 @@ struct DeviceBackend : Backend {
     std::condition_variable cv;
     std::deque<int> jobs, done;
     bool stop = false;
-    std::thread loader;
-    // panel geometry per size class (loader thread only)
+    std::vector<std::thread> loaders;
+    // panel geometry per size class (shared by the loader threads)
+    std::mutex geom_mu;
     std::map<int64_t, int> geom;
     int tuned = 0;
 
     DeviceBackend(hsym_request *q_, int count, const hsym_serve_opts &o_) : q(q_), o(o_), H(count), C(count) {
-        loader = std::thread([this] { loader_main(); });
+        for (int i = 0; i < o.loaders; i++) loaders.emplace_back([this] { loader_main(); });
     }
     ~DeviceBackend() override {
         {
@@ -156,7 +157,7 @@ struct DeviceBackend : Backend {
             stop = true;
         }
         cv.notify_all();
-        loader.join();
+        for (auto &t : loaders) t.join();
         for (size_t r = 0; r < C.size(); r++) retire((int)r);
     }
     double now() override {
@@ -186,6 +187,8 @@ struct DeviceBackend : Backend {
         int lg = 0;
         while (((int64_t)2 << lg) <= x.n) lg++;
         const int64_t key = ((int64_t)lg << 8) | (x.block_width << 1) | x.storage;
+        // one tuning per class: other loaders wait for it
+        std::lock_guard<std::mutex> g(geom_mu);
         auto it = geom.find(key);
         if (it == geom.end()) {
             int f = 0;
@@ -346,6 +349,7 @@ void check_opts(hsym_serve_opts &o, const hsym_serve_opts *in) {
         if (in->iters_per_round > 0) o.iters_per_round = in->iters_per_round;
         if (in->maxit > 0) o.maxit = in->maxit;
         o.autotune = in->autotune ? 1 : 0;
+        if (in->loaders > 0) o.loaders = std::min(in->loaders, 16);
     }
 }
 
@@ -391,6 +395,7 @@ void hsym_serve_opts_default(hsym_serve_opts *o) {
     o->iters_per_round = 1;
     o->maxit = 1000;
     o->autotune = 0;
+    o->loaders = 2;
 }
 
 int hsym_serve(hsym_request *reqs, int count, const hsym_serve_opts *opts, hsym_serve_report *rep) {
@@ -409,7 +414,7 @@ int hsym_serve(hsym_request *reqs, int count, const hsym_serve_opts *opts, hsym_
         run_schedule(reqs, count, o, be, rep);
         if (rep) {
             // every load has been collected through the queue lock by now
-            std::lock_guard<std::mutex> g(be.mu);
+            std::lock_guard<std::mutex> g(be.geom_mu);
             rep->tuned_classes = be.tuned;
         }
     });
