@@ -121,6 +121,12 @@ class Generator:
         _load().hsg_blocks(self._h, _ptr(st), _ptr(lb))
         return st, lb
 
+    def levels(self) -> np.ndarray:
+        """Level label q of every row (its block's label), int32[n]: the
+        stand-in for a configuration's excitation quanta."""
+        st, lb = self.blocks()
+        return np.repeat(lb, np.diff(st)).astype(np.int32)
+
     def count_rows(self, r0: int, r1: int) -> np.ndarray:
         c = np.empty(r1 - r0, np.int64)
         _load().hsg_count_rows(self._h, r0, r1, _ptr(c))
@@ -149,6 +155,11 @@ def generate(n: int, N: float, seed: int, dtype=np.float64, variant: str = "band
              **kw) -> UpperCSR:
     """GEN(n, N, seed): whole upper-triangle CSR."""
     return Generator(n, N, seed, variant=variant, **kw).matrix(dtype)
+
+
+def levels(n: int, N: float, seed: int, variant: str = "banded", **kw) -> np.ndarray:
+    """Row level labels of GEN(n, N, seed)."""
+    return Generator(n, N, seed, variant=variant, **kw).levels()
 
 
 def config(name: str, dtype=np.float64) -> UpperCSR:

@@ -225,6 +225,33 @@ int lobpcg_solve(hsym_t H, int nev, int block_width, double tol, const double *X
                  int precond, const lobpcg_opts *opts, double *evals, double *evecs,
                  lobpcg_report *rep, void *stream);
 
+/*
+ * Multi-level start block (Section 3.3.1, eq. 12, applied recursively as the
+ * section's closing remark describes).  Takes the host CSR of hsym_create and
+ * level (host int32[n]): the level of every row, for CI matrices the
+ * excitation quanta of its configuration.  caps (host int32[ncaps], strictly
+ * ascending, 1 <= ncaps <= 16) lists the smaller configuration spaces.  For
+ * each cap in turn, the library:
+ *   1. takes the principal submatrix H11 on the rows with level <= cap
+ *      (order kept);
+ *   2. solves for its m lowest eigenpairs with lobpcg_solve (block width m,
+ *      tol, precond, opts, all m columns gating convergence);
+ *   3. starts that solve from a seeded Gaussian block for the first cap, and
+ *      from the previous cap's eigenvectors padded with zeros (eq. 12) for
+ *      the others.
+ * X0 (device n x m, row-major ld m, caller-owned) receives the last cap's
+ * eigenvectors padded with zeros: the start block of the full solve.
+ * iters (host int[ncaps], may be NULL) receives each sub-solve's iteration
+ * count; a sub-solve that stops at maxit is not an error.  Synchronous.
+ * Errors: HSYM_E_INVALID_ARG (NULL pointers, malformed CSR, caps not
+ * ascending, a cap keeping fewer than 3m rows), and those of hsym_create and
+ * lobpcg_solve.
+ */
+int lobpcg_guess_multilevel(int64_t n, const int64_t *rowptr, const int32_t *colind, const void *values,
+                            int values_prec, const int32_t *level, int ncaps, const int32_t *caps,
+                            int storage, int m, double tol, int precond, const lobpcg_opts *opts,
+                            double *X0, int *iters, void *stream);
+
 typedef struct {
     int maxit;        /* default 2000 (also capped by n)                             */
     uint64_t seed;    /* Gaussian start vector when v0 is NULL                       */

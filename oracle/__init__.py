@@ -11,6 +11,7 @@ step by step after the paper:
   (Section 3.2, eq. 11) and the conservative shift rules of Section 4.3.
 * Lanczos with full re-orthogonalisation (Section 3, opening paragraph) and
   the convergence-check schedule of footnote 7 (Section 5.2).
+* The multi-level start block of Section 3.3.1 (eq. 12, used recursively).
 
 Readings taken where the paper is silent (each is listed with its reason in
 the design notes of the repository): the relative residual is
@@ -413,6 +414,59 @@ def lobpcg(A: SymMatrix, nev, m, tol, X0=None, precond="jacobi", maxit=1000, see
     res.X = X
     res.seconds = time.perf_counter() - t0
     return res
+
+
+# --------------------------------------------------------------------------
+# Multi-level initial guess (Section 3.3.1)
+# --------------------------------------------------------------------------
+def principal_submatrix(A: SymMatrix, rows):
+    """H11: the rows and columns of H in the ascending index set `rows`,
+    renumbered in order (the Hamiltonian of the smaller configuration space)."""
+    rows = np.asarray(rows, np.int64)
+    pos = np.full(A.n, -1, np.int64)
+    pos[rows] = np.arange(rows.size)
+    rp = [0]
+    ci, vals = [], []
+    for i in rows:
+        for p in range(A.rowptr[i], A.rowptr[i + 1]):
+            j = pos[A.colind[p]]
+            if j >= 0:
+                ci.append(j)
+                vals.append(A.values[p])
+        rp.append(len(ci))
+    return SymMatrix(rows.size, np.array(rp, np.int64), np.array(ci, np.int32), np.array(vals, np.float64))
+
+
+def pad_with_zeros(X1, rows, n):
+    """Eq. 12: X0 = [X1; 0], the rows of the smaller space keep X1."""
+    X0 = np.zeros((n, X1.shape[1]))
+    X0[np.asarray(rows, np.int64)] = X1
+    return X0
+
+
+def multilevel_guess(A: SymMatrix, level, caps, m, tol, precond="jacobi", maxit=1000, seed=0):
+    """Start block for the full solve, built recursively over the smaller
+    spaces {i : level_i <= cap} for the ascending caps: the m lowest
+    eigenvectors of each space (LOBPCG, every column gating convergence),
+    started from a Gaussian block on the first space and from the previous
+    space's eigenvectors padded with zeros (eq. 12) on the others; the last
+    space's eigenvectors padded with zeros are returned, with each sub-solve's
+    iteration count."""
+    level = np.asarray(level)
+    prev_rows, prev_X = None, None
+    iters = []
+    for cap in caps:
+        rows = np.flatnonzero(level <= cap)
+        H11 = principal_submatrix(A, rows)
+        X0 = None
+        if prev_rows is not None:
+            pos = np.full(A.n, -1, np.int64)
+            pos[rows] = np.arange(rows.size)
+            X0 = pad_with_zeros(prev_X, pos[prev_rows], rows.size)
+        r = lobpcg(H11, m, m, tol, X0=X0, precond=precond, maxit=maxit, seed=seed, keep_history=False)
+        iters.append(r.iters)
+        prev_rows, prev_X = rows, r.X[:, :m]
+    return pad_with_zeros(prev_X, prev_rows, A.n), iters
 
 
 # --------------------------------------------------------------------------

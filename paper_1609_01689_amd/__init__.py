@@ -111,6 +111,8 @@ _vp, _i64, _int, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_
 _SIGS = {
     "hsym_create": [ctypes.POINTER(_vp), _i64, _vp, _vp, _vp, _int, _int, _int, _vp],
     "hsym_create_begin": [ctypes.POINTER(_vp), _i64, _int, _int, _vp],
+    "lobpcg_guess_multilevel": [_i64, _vp, _vp, _vp, _int, _vp, _int, _vp, _int, _int, _dbl, _int,
+                                ctypes.POINTER(lobpcg_opts), _vp, _vp, _vp],
     "hsym_autotune_geometry": [_i64, _vp, _vp, _vp, _int, _int, _int, _i64, ctypes.POINTER(_int),
                                ctypes.POINTER(hsym_tune_entry), _int, ctypes.POINTER(_int)],
     "hsym_create_append": [_vp, _i64, _vp, _vp, _vp, _int],
@@ -291,6 +293,25 @@ def lobpcg_solve(h, nev, block_width, tol, X0=None, precond="jacobi", opts=None,
                                    ctypes.byref(o), _hptr(evals), _dptr(evecs), ctypes.byref(rep),
                                    _stream(stream)))
     return st, evals, rep
+
+
+def lobpcg_guess_multilevel(csr, level, caps, X0, m, tol, storage=HSYM_FP64, precond="jacobi", opts=None,
+                            stream=None):
+    """Eq. 12 start block over the level caps into the device tensor X0 (n x m); returns the
+    sub-solves' iteration counts."""
+    rowptr = np.ascontiguousarray(csr.rowptr, np.int64)
+    colind = np.ascontiguousarray(csr.colind, np.int32)
+    values = np.ascontiguousarray(csr.values)
+    vp = {np.dtype(np.float64): HSYM_FP64, np.dtype(np.float32): HSYM_FP32}[values.dtype]
+    level = np.ascontiguousarray(level, np.int32)
+    caps = np.ascontiguousarray(caps, np.int32)
+    iters = np.zeros(len(caps), np.int32)
+    o = opts if opts is not None else default_lobpcg_opts()
+    _check(lib().lobpcg_guess_multilevel(int(csr.n), _hptr(rowptr), _hptr(colind), _hptr(values), vp,
+                                         _hptr(level), len(caps), _hptr(caps), storage, int(m), float(tol),
+                                         PRECOND[precond], ctypes.byref(o), _dptr(X0), _hptr(iters),
+                                         _stream(stream)))
+    return iters
 
 
 def lanczos_solve(h, nev, tol, v0=None, maxit=2000, seed=0, evecs=None, stream=None):
