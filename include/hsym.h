@@ -50,9 +50,14 @@ enum hsym_status {
 enum hsym_prec { HSYM_FP64 = 0, HSYM_FP32 = 1 };
 
 /* Preconditioners of Section 3.2 (eq. 11): none, the diagonal of H
- * ("the extreme case" of a block-diagonal approximation), or the dense 64x64
- * diagonal blocks of H solved directly with fp64 factors. */
-enum hsym_precond { HSYM_PRECOND_NONE = 0, HSYM_PRECOND_JACOBI = 1, HSYM_PRECOND_BLOCK64 = 2 };
+ * ("the extreme case" of a block-diagonal approximation), the dense 64x64
+ * diagonal blocks of H solved directly with fp64 factors, or the paper's own
+ * choice (end of Section 3.2, Section 4.3): the diagonal tiles of the
+ * many-body groups (hsym_attach_group_tiles), each shifted system solved by
+ * lobpcg_opts.fom_iters steps of the full orthogonalization method per
+ * right-hand side. */
+enum hsym_precond { HSYM_PRECOND_NONE = 0, HSYM_PRECOND_JACOBI = 1, HSYM_PRECOND_BLOCK64 = 2,
+                     HSYM_PRECOND_FOM = 3 };
 
 /* hsym_create flags */
 #define HSYM_HOST_PTRS     0x0   /* rowptr/colind/values are host memory (default)   */
@@ -119,6 +124,20 @@ int hsym_create_append(hsym_t H, int64_t nrows, const int64_t *rowptr_local,
                        const int32_t *colind, const void *values, int values_prec);
 int hsym_create_finish(hsym_t H);
 
+/*
+ * Diagonal group tiles for HSYM_PRECOND_FOM (Section 4.3: a separate matrix
+ * of the diagonal tiles, set up next to H).  group_start (host
+ * int64[ngroups+1]) holds ascending group boundaries, group_start[0] = 0 and
+ * group_start[ngroups] = n; groups longer than 64 rows are cut into 64-row
+ * pieces.  rowptr/colind/values are the same upper CSR as hsym_create's (the
+ * entries inside each group's diagonal tile are kept, densely, in fp64).
+ * Replaces tiles attached before.  Synchronous.  Errors: HSYM_E_INVALID_ARG
+ * (NULL pointers, bad boundaries, malformed CSR), HSYM_E_OUT_OF_MEMORY,
+ * HSYM_E_DEVICE.
+ */
+int hsym_attach_group_tiles(hsym_t H, int64_t ngroups, const int64_t *group_start, const int64_t *rowptr,
+                            const int32_t *colind, const void *values, int values_prec);
+
 int hsym_destroy(hsym_t H);
 int hsym_info(hsym_t H, hsym_info_t *out);
 
@@ -184,6 +203,8 @@ typedef struct {
                                creates and steps the contexts (hsym_serve, whose
                                loader thread builds requests meanwhile, leaves it
                                off)                                             */
+    int fom_iters;          /* FOM steps of HSYM_PRECOND_FOM, 1..4; default 3 (the
+                               paper performs up to three)                       */
 } lobpcg_opts;
 
 #define HSYM_MAX_BLOCK 16

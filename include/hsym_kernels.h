@@ -51,6 +51,9 @@ int hsym_kernel_rayleigh_ritz(int nblk, int m, const double *A, double *theta, d
  * W_j <- (Htilde - mu_j I)^{-1} W_j with Htilde = diag(H) (HSYM_PRECOND_JACOBI)
  * or the 64x64 diagonal blocks (HSYM_PRECOND_BLOCK64, handle built with
  * HSYM_BUILD_BLOCK64); mu device[m]; denominators are kept >= delta in size.
+ * HSYM_PRECOND_FOM (group tiles attached with hsym_attach_group_tiles) gives
+ * 3 steps of the full orthogonalization method per tile and column, the
+ * pivots of its small Hessenberg solve kept >= delta in size.
  */
 int hsym_kernel_precond(hsym_t H, int kind, int m, double *W, const double *mu, double delta, void *stream);
 

@@ -228,16 +228,80 @@ def guard(d, delta):
     return np.where(np.abs(d) >= delta, d, np.where(d >= 0, delta, -delta))
 
 
+def fom_solve(A, b, k, delta):
+    """Approximate solution of A x = b by k steps of the full orthogonalization
+    method (Saad, Iterative Methods for Sparse Linear Systems, Algorithm 6.4):
+    Arnoldi with modified Gram-Schmidt builds V_k and the Hessenberg H_k from
+    v_1 = b / ||b||, then x = V_k y with H_k y = ||b|| e_1.  The Arnoldi
+    process stops early when the next basis vector vanishes (the Krylov space
+    is invariant).  H_k y = ||b|| e_1 is solved by Gaussian elimination with
+    partial pivoting whose pivots are kept at least delta from zero (the
+    guard of the shifted denominators)."""
+    n = b.shape[0]
+    beta = np.linalg.norm(b)
+    if beta == 0.0:
+        return np.zeros(n)
+    V = np.zeros((n, k + 1))
+    Hh = np.zeros((k + 1, k))
+    V[:, 0] = b / beta
+    kk = k
+    for i in range(k):
+        w = A @ V[:, i]
+        for l in range(i + 1):
+            Hh[l, i] = w @ V[:, l]
+            w = w - Hh[l, i] * V[:, l]
+        Hh[i + 1, i] = np.linalg.norm(w)
+        if Hh[i + 1, i] <= 1e-14 * beta or i + 1 == k:
+            kk = i + 1
+            if Hh[i + 1, i] > 1e-14 * beta:
+                V[:, i + 1] = w / Hh[i + 1, i]
+            break
+        V[:, i + 1] = w / Hh[i + 1, i]
+    T = Hh[:kk, :kk].copy()
+    rhs = np.zeros(kk)
+    rhs[0] = beta
+    # Gaussian elimination with partial pivoting, guarded pivots
+    for c in range(kk):
+        p = c + int(np.argmax(np.abs(T[c:, c])))
+        if p != c:
+            T[[c, p]] = T[[p, c]]
+            rhs[[c, p]] = rhs[[p, c]]
+        T[c, c] = float(guard(T[c, c], delta))
+        for r in range(c + 1, kk):
+            f = T[r, c] / T[c, c]
+            T[r, c:] -= f * T[c, c:]
+            rhs[r] -= f * rhs[c]
+    y = np.zeros(kk)
+    for c in range(kk - 1, -1, -1):
+        y[c] = (rhs[c] - T[c, c + 1:] @ y[c + 1:]) / T[c, c]
+    return V[:, :kk] @ y
+
+
 class Preconditioner:
     """T_j = Htilde - mu_j I with Htilde = diag(H) ('jacobi') or the dense 64x64
-    diagonal blocks of H ('block64'), solved directly (eq. 11)."""
+    diagonal blocks of H ('block64'), solved directly (eq. 11), or the
+    diagonal group tiles of H ('fom', Section 3.2 end and Section 4.3: the
+    tiles of the many-body groups, each system solved by fom_iters steps of
+    FOM per right-hand side with its own shift)."""
 
-    def __init__(self, kind, A: SymMatrix, bs=64):
+    def __init__(self, kind, A: SymMatrix, bs=64, groups=None, fom_iters=3):
         self.kind = kind
         self.A = A
         self.delta = GUARD * A.norm1()
         self.bs = bs
-        if kind == "jacobi":
+        if kind == "fom":
+            # groups: ascending starts [0, ..., n]; groups above 64 rows are cut in 64-row pieces
+            st = [0]
+            g = np.asarray(groups, np.int64)
+            for a, b in zip(g[:-1], g[1:]):
+                for c in range(int(a), int(b), 64):
+                    st.append(min(int(b), c + 64))
+            self.starts = np.array(st, np.int64)
+            self.tiles = []
+            for a, b in zip(self.starts[:-1], self.starts[1:]):
+                self.tiles.append(principal_submatrix(A, np.arange(a, b)).dense())
+            self.fom_iters = fom_iters
+        elif kind == "jacobi":
             self.d = A.diagonal()
         elif kind == "block64":
             blocks = A.diag_blocks(bs)
@@ -258,6 +322,13 @@ class Preconditioner:
     def apply(self, R, mu):
         if self.kind == "jacobi":
             return R / guard(self.d[:, None] - mu[None, :], self.delta)
+        if self.kind == "fom":
+            W = np.empty_like(R)
+            for t, (a, b) in enumerate(zip(self.starts[:-1], self.starts[1:])):
+                Ht = self.tiles[t]
+                for j in range(R.shape[1]):
+                    W[a:b, j] = fom_solve(Ht - mu[j] * np.eye(b - a), R[a:b, j], self.fom_iters, self.delta)
+            return W
         n, m = R.shape
         bs = self.bs
         W = np.empty_like(R)
@@ -317,7 +388,7 @@ def _project(V, bases):
 
 
 def lobpcg(A: SymMatrix, nev, m, tol, X0=None, precond="jacobi", maxit=1000, seed=0,
-           keep_history=True, spmm=None):
+           keep_history=True, spmm=None, groups=None, fom_iters=3):
     """Lowest nev eigenpairs of H by LOBPCG with block width m (m >= nev).
 
     Follows Algorithm 1: Rayleigh quotient of the start block (step 1); per
@@ -331,7 +402,7 @@ def lobpcg(A: SymMatrix, nev, m, tol, X0=None, precond="jacobi", maxit=1000, see
         raise ValueError("need 1 <= nev <= m and 3m <= n")
     Hx = spmm or A.spmm
     normH = A.norm1()
-    pre = None if precond == "none" else Preconditioner(precond, A)
+    pre = None if precond == "none" else Preconditioner(precond, A, groups=groups, fom_iters=fom_iters)
     if X0 is None:
         from hsymgen import gauss_block
         X0 = gauss_block(seed, n, m)

@@ -26,7 +26,7 @@ HSYM_OK, HSYM_NOT_CONVERGED = 0, 1
 HSYM_E_INVALID_ARG, HSYM_E_OUT_OF_MEMORY, HSYM_E_DEVICE = -1, -2, -3
 HSYM_E_BREAKDOWN, HSYM_E_NUMERIC, HSYM_E_UNSUPPORTED = -4, -5, -6
 HSYM_FP64, HSYM_FP32 = 0, 1
-PRECOND = {"none": 0, "jacobi": 1, "block64": 2}
+PRECOND = {"none": 0, "jacobi": 1, "block64": 2, "fom": 3}
 HSYM_BUILD_BLOCK64 = 0x2
 MAX_BLOCK = 16
 MAX_HISTORY = 4096
@@ -62,7 +62,7 @@ class hsym_info_t(ctypes.Structure):
 class lobpcg_opts(ctypes.Structure):
     _fields_ = [("maxit", ctypes.c_int), ("seed", ctypes.c_uint64), ("check_every", ctypes.c_int),
                 ("no_precond_iters", ctypes.c_int), ("near", ctypes.c_double), ("guard", ctypes.c_double),
-                ("keep_history", ctypes.c_int), ("graph", ctypes.c_int)]
+                ("keep_history", ctypes.c_int), ("graph", ctypes.c_int), ("fom_iters", ctypes.c_int)]
 
 
 class lobpcg_report(ctypes.Structure):
@@ -111,6 +111,7 @@ _vp, _i64, _int, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_
 _SIGS = {
     "hsym_create": [ctypes.POINTER(_vp), _i64, _vp, _vp, _vp, _int, _int, _int, _vp],
     "hsym_create_begin": [ctypes.POINTER(_vp), _i64, _int, _int, _vp],
+    "hsym_attach_group_tiles": [_vp, _i64, _vp, _vp, _vp, _vp, _int],
     "lobpcg_guess_multilevel": [_i64, _vp, _vp, _vp, _int, _vp, _int, _vp, _int, _int, _dbl, _int,
                                 ctypes.POINTER(lobpcg_opts), _vp, _vp, _vp],
     "hsym_autotune_geometry": [_i64, _vp, _vp, _vp, _int, _int, _int, _i64, ctypes.POINTER(_int),
@@ -229,6 +230,16 @@ def hsym_autotune_geometry(n, rowptr, colind, values, storage=HSYM_FP64, m=16, s
                                         int(sample_rows), ctypes.byref(flags), table, cap, ctypes.byref(ntried)))
     rows = [(table[i].panel_rows, table[i].chunk_cols, table[i].ms) for i in range(min(ntried.value, cap))]
     return flags.value, rows
+
+
+def hsym_attach_group_tiles(h, group_start, csr):
+    """Diagonal group tiles (FOM preconditioner) from ascending group boundaries [0, ..., n]."""
+    gs = np.ascontiguousarray(group_start, np.int64)
+    rowptr = np.ascontiguousarray(csr.rowptr, np.int64)
+    colind = np.ascontiguousarray(csr.colind, np.int32)
+    values = np.ascontiguousarray(csr.values)
+    vp = {np.dtype(np.float64): HSYM_FP64, np.dtype(np.float32): HSYM_FP32}[values.dtype]
+    _check(lib().hsym_attach_group_tiles(h, len(gs) - 1, _hptr(gs), _hptr(rowptr), _hptr(colind), _hptr(values), vp))
 
 
 def hsym_create_begin(n, storage=HSYM_FP64, flags=0, stream=None):

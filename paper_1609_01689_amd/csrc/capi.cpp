@@ -1,4 +1,5 @@
 // C ABI entry points: argument checks, error capture, handle lifetime.
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 
@@ -70,6 +71,9 @@ static void destroy_matrix(hsym_matrix *H) {
     if (H->diag32) (void)hipFree(H->diag32);
     if (H->pre_q) (void)hipFree(H->pre_q);
     if (H->pre_lam) (void)hipFree(H->pre_lam);
+    if (H->tg_start) (void)hipFree(H->tg_start);
+    if (H->tg_off) (void)hipFree(H->tg_off);
+    if (H->tg_dense) (void)hipFree(H->tg_dense);
     delete H;
 }
 
@@ -155,6 +159,79 @@ int hsym_create(hsym_t *out, int64_t n, const int64_t *rowptr, const int32_t *co
         throw;
     }
     *out = H;
+    API_END
+}
+
+int hsym_attach_group_tiles(hsym_t H, int64_t ngroups, const int64_t *group_start, const int64_t *rowptr,
+                            const int32_t *colind, const void *values, int values_prec) {
+    API_BEGIN
+    if (!H || !H->ready) fail(HSYM_E_INVALID_ARG, "invalid handle");
+    if (!group_start || !rowptr || !colind || !values) fail(HSYM_E_INVALID_ARG, "NULL argument");
+    if (values_prec != HSYM_FP64 && values_prec != HSYM_FP32) fail(HSYM_E_INVALID_ARG, "bad values precision");
+    const int64_t n = H->n;
+    if (ngroups < 1 || group_start[0] != 0 || group_start[ngroups] != n)
+        fail(HSYM_E_INVALID_ARG, "group boundaries must run from 0 to n");
+    if (rowptr[0] != 0) fail(HSYM_E_INVALID_ARG, "rowptr[0] != 0");
+    // tiles: the groups, cut into pieces of at most 64 rows
+    std::vector<int64_t> st{0};
+    for (int64_t g = 0; g < ngroups; g++) {
+        if (group_start[g + 1] <= group_start[g]) fail(HSYM_E_INVALID_ARG, "group boundaries must ascend");
+        for (int64_t a = group_start[g]; a < group_start[g + 1]; a += 64)
+            st.push_back(std::min(group_start[g + 1], a + 64));
+    }
+    const int64_t nt = (int64_t)st.size() - 1;
+    std::vector<int64_t> off((size_t)nt + 1, 0);
+    for (int64_t t = 0; t < nt; t++) {
+        const int64_t sz = st[(size_t)t + 1] - st[(size_t)t];
+        off[(size_t)t + 1] = off[(size_t)t] + sz * sz;
+    }
+    std::vector<double> dense((size_t)off[(size_t)nt], 0.0);
+    parallel_for(nt, 64, [&](int64_t t0, int64_t t1) {
+        for (int64_t t = t0; t < t1; t++) {
+            const int64_t a = st[(size_t)t], b = st[(size_t)t + 1], sz = b - a;
+            double *D = dense.data() + off[(size_t)t];
+            for (int64_t r = a; r < b; r++) {
+                if (rowptr[r + 1] < rowptr[r]) fail(HSYM_E_INVALID_ARG, "rowptr decreases at row " + std::to_string(r));
+                for (int64_t p = rowptr[r]; p < rowptr[r + 1]; p++) {
+                    const int64_t c = colind[p];
+                    if (c < r || c >= n) fail(HSYM_E_INVALID_ARG, "column outside [row, n) in row " + std::to_string(r));
+                    if (c >= b) break;
+                    const double v = values_prec == HSYM_FP64 ? ((const double *)values)[p]
+                                                              : (double)((const float *)values)[p];
+                    D[(r - a) * sz + (c - a)] = v;
+                    D[(c - a) * sz + (r - a)] = v;
+                }
+            }
+        }
+    });
+    int64_t *d_st = nullptr, *d_off = nullptr;
+    double *d_dense = nullptr;
+    auto cleanup = [&] {
+        if (d_st) (void)hipFree(d_st);
+        if (d_off) (void)hipFree(d_off);
+        if (d_dense) (void)hipFree(d_dense);
+    };
+    try {
+        HIPCHK(hipMalloc((void **)&d_st, sizeof(int64_t) * st.size()));
+        HIPCHK(hipMalloc((void **)&d_off, sizeof(int64_t) * off.size()));
+        HIPCHK(hipMalloc((void **)&d_dense, sizeof(double) * std::max<size_t>(1, dense.size())));
+        HIPCHK(hipMemcpy(d_st, st.data(), sizeof(int64_t) * st.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_dense, dense.data(), sizeof(double) * dense.size(), hipMemcpyHostToDevice));
+    } catch (...) {
+        cleanup();
+        throw;
+    }
+    if (H->tg_start) (void)hipFree(H->tg_start);
+    if (H->tg_off) (void)hipFree(H->tg_off);
+    if (H->tg_dense) (void)hipFree(H->tg_dense);
+    H->bytes -= H->tg_bytes;
+    H->ntg = nt;
+    H->tg_start = d_st;
+    H->tg_off = d_off;
+    H->tg_dense = d_dense;
+    H->tg_bytes = (int64_t)(sizeof(int64_t) * (st.size() + off.size()) + sizeof(double) * dense.size());
+    H->bytes += H->tg_bytes;
     API_END
 }
 

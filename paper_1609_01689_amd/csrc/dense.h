@@ -32,7 +32,8 @@ int64_t lincomb_norm_parts(int64_t n);
 void colsum_final(const double *part, int64_t nparts, int m, double *out, hipStream_t s);
 void residual(const double *X, const double *AX, const double *theta, double *R, double *norm_part, int64_t n,
               int m, hipStream_t s);
-void precond_apply(hsym_matrix *H, int kind, double *W, const double *mu, double delta, int m, hipStream_t s);
+void precond_apply(hsym_matrix *H, int kind, double *W, const double *mu, double delta, int m, hipStream_t s,
+                   int fom_iters = 3);
 void to_f32(const double *x, float *y, int64_t cnt, hipStream_t s);
 
 // Gaussian block from the counter-based generator (SplitMix64 over a Weyl

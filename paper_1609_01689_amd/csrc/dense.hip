@@ -425,6 +425,140 @@ __global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W,
 }
 
 // ---------------------------------------------------------------------------
+// Tile-diagonal preconditioner (end of Section 3.2, Section 4.3): for every
+// diagonal group tile (rows [a, a+s), s <= 64, dense in LDS) and every column
+// j, `iters` steps of the full orthogonalization method (Saad, Algorithm 6.4)
+// on (Ht - mu_j I) w = r_j, started from w = 0: Arnoldi with modified
+// Gram-Schmidt from v_1 = r_j / ||r_j||, stopped early when the next basis
+// vector vanishes, then w = V y with H y = ||r_j|| e_1 solved by Gaussian
+// elimination with partial pivoting, pivots kept delta away from zero.
+// One wave per column (lane = tile row); the inner products are butterfly
+// sums, identical in every lane.
+// ---------------------------------------------------------------------------
+constexpr int FOM_KMAX = 4;
+
+__device__ __forceinline__ double wave_allsum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(1024) void k_precond_fom(double *__restrict__ W, const int64_t *__restrict__ gstart,
+                                                      const int64_t *__restrict__ goff,
+                                                      const double *__restrict__ gdense,
+                                                      const double *__restrict__ mu, double delta, int iters,
+                                                      int m) {
+    __shared__ double Ht[64][65];
+    __shared__ double vs[16][64];
+    const int64_t t = blockIdx.x;
+    const int64_t a = gstart[t];
+    const int s = (int)(gstart[t + 1] - a);
+    const double *D = gdense + goff[t];
+    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        const int r = e >> 6, c = e & 63;
+        Ht[r][c] = (r < s && c < s) ? D[r * s + c] : 0.0;
+    }
+    __syncthreads();
+    // from here on the waves (columns) are independent: no further barrier
+    const int lane = threadIdx.x & 63, j = threadIdx.x >> 6;
+    if (j >= m) return;
+    const bool in = lane < s;
+    const double shift = mu[j];
+    const double b = in ? W[(a + lane) * m + j] : 0.0;
+    const double beta = sqrt(wave_allsum(b * b));
+    if (beta == 0.0) {
+        if (in) W[(a + lane) * m + j] = 0.0;
+        return;
+    }
+    double V[FOM_KMAX + 1];
+    double Hh[FOM_KMAX + 1][FOM_KMAX];
+#pragma unroll
+    for (int i = 0; i <= FOM_KMAX; i++) {
+        V[i] = 0.0;
+#pragma unroll
+        for (int k = 0; k < FOM_KMAX; k++) Hh[i][k] = 0.0;
+    }
+    V[0] = b / beta;
+    int kk = iters;
+#pragma unroll
+    for (int i = 0; i < FOM_KMAX; i++) {
+        if (i >= iters) break;
+        vs[j][lane] = V[i];
+        __builtin_amdgcn_wave_barrier();
+        double w = 0.0;
+        for (int c = 0; c < 64; c++) w = fma(Ht[lane][c], vs[j][c], w);
+        __builtin_amdgcn_wave_barrier();
+        w = in ? w - shift * V[i] : 0.0;
+#pragma unroll
+        for (int l = 0; l <= i; l++) {
+            const double h = wave_allsum(w * V[l]);
+            Hh[l][i] = h;
+            w -= h * V[l];
+        }
+        const double hn = sqrt(wave_allsum(w * w));
+        Hh[i + 1][i] = hn;
+        const bool live = hn > 1e-14 * beta;
+        if (live) V[i + 1] = w / hn;
+        if (!live || i + 1 == iters) {
+            kk = i + 1;
+            break;
+        }
+    }
+    // H y = beta e_1 (kk x kk upper Hessenberg), the same in every lane
+    double T[FOM_KMAX][FOM_KMAX], rhs[FOM_KMAX], y[FOM_KMAX];
+#pragma unroll
+    for (int r = 0; r < FOM_KMAX; r++) {
+        rhs[r] = r == 0 ? beta : 0.0;
+        y[r] = 0.0;
+#pragma unroll
+        for (int c = 0; c < FOM_KMAX; c++) T[r][c] = Hh[r][c];
+    }
+#pragma unroll
+    for (int c = 0; c < FOM_KMAX; c++) {
+        if (c >= kk) break;
+        int p = c;
+#pragma unroll
+        for (int r = c + 1; r < FOM_KMAX; r++)
+            if (r < kk && fabs(T[r][c]) > fabs(T[p][c])) p = r;
+        if (p != c) {
+#pragma unroll
+            for (int q = 0; q < FOM_KMAX; q++) {
+                const double x = T[c][q];
+                T[c][q] = T[p][q];
+                T[p][q] = x;
+            }
+            const double x = rhs[c];
+            rhs[c] = rhs[p];
+            rhs[p] = x;
+        }
+        T[c][c] = guard_den(T[c][c], delta);
+#pragma unroll
+        for (int r = c + 1; r < FOM_KMAX; r++) {
+            if (r >= kk) break;
+            const double f = T[r][c] / T[c][c];
+#pragma unroll
+            for (int q = 0; q < FOM_KMAX; q++)
+                if (q >= c) T[r][q] -= f * T[c][q];
+            rhs[r] -= f * rhs[c];
+        }
+    }
+#pragma unroll
+    for (int c = FOM_KMAX - 1; c >= 0; c--) {
+        if (c >= kk) continue;
+        double acc = rhs[c];
+#pragma unroll
+        for (int q = 0; q < FOM_KMAX; q++)
+            if (q > c && q < kk) acc -= T[c][q] * y[q];
+        y[c] = acc / T[c][c];
+    }
+    double x = 0.0;
+#pragma unroll
+    for (int i = 0; i < FOM_KMAX; i++)
+        if (i < kk) x = fma(V[i], y[i], x);
+    if (in) W[(a + lane) * m + j] = x;
+}
+
+// ---------------------------------------------------------------------------
 // Batched launches: one launch runs the same step for `count` problems whose
 // arguments sit in a device table; blockIdx.y selects the problem and the
 // blocks a smaller problem does not need return at once.
@@ -485,8 +619,18 @@ void gather_words(const int *const *src, int *dst, int words, int count, hipStre
     HIPCHK(hipGetLastError());
 }
 
-void precond_apply(hsym_matrix *H, int kind, double *W, const double *mu, double delta, int m, hipStream_t s) {
+void precond_apply(hsym_matrix *H, int kind, double *W, const double *mu, double delta, int m, hipStream_t s,
+                   int fom_iters) {
     const int64_t n = H->n;
+    if (kind == HSYM_PRECOND_FOM) {
+        if (!H->tg_dense) fail(HSYM_E_INVALID_ARG, "FOM preconditioner needs hsym_attach_group_tiles");
+        if (fom_iters < 1 || fom_iters > FOM_KMAX) fail(HSYM_E_INVALID_ARG, "fom_iters must be in [1, 4]");
+        if (m < 1 || m > 16) fail(HSYM_E_INVALID_ARG, "block width must be 1..16");
+        hipLaunchKernelGGL(k_precond_fom, dim3((unsigned)H->ntg), dim3((unsigned)(64 * m)), 0, s, W, H->tg_start,
+                           H->tg_off, H->tg_dense, mu, delta, fom_iters, m);
+        HIPCHK(hipGetLastError());
+        return;
+    }
     if (kind == HSYM_PRECOND_JACOBI) {
         const unsigned grid = (unsigned)((n * m + 255) / 256);
         switch (m) {

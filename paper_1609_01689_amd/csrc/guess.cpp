@@ -68,6 +68,8 @@ extern "C" int lobpcg_guess_multilevel(int64_t n, const int64_t *rowptr, const i
         if (ncaps < 1 || ncaps > 16) fail(HSYM_E_INVALID_ARG, "need 1 <= ncaps <= 16");
         if (m < 1 || m > HSYM_MAX_BLOCK) fail(HSYM_E_INVALID_ARG, "block width must be in [1, 16]");
         if (values_prec != HSYM_FP64 && values_prec != HSYM_FP32) fail(HSYM_E_INVALID_ARG, "bad values precision");
+        if (precond == HSYM_PRECOND_FOM)
+            fail(HSYM_E_INVALID_ARG, "the sub-solves take the none, Jacobi or block64 preconditioner");
         for (int k = 1; k < ncaps; k++)
             if (caps[k] <= caps[k - 1]) fail(HSYM_E_INVALID_ARG, "level caps must be strictly ascending");
         if (rowptr[0] != 0) fail(HSYM_E_INVALID_ARG, "rowptr[0] != 0");

@@ -80,6 +80,13 @@ struct hsym_matrix {
     double *pre_q = nullptr;
     double *pre_lam = nullptr;
     int64_t pre_nchunks = 0;
+    // diagonal group tiles (FOM preconditioner): tile t covers rows
+    // [tg_start[t], tg_start[t+1]) (at most 64), dense fp64 at tg_dense + tg_off[t]
+    int64_t ntg = 0;
+    int64_t *tg_start = nullptr;
+    int64_t *tg_off = nullptr;
+    double *tg_dense = nullptr;
+    int64_t tg_bytes = 0;
     int64_t bytes = 0;
     // streaming create
     int64_t stream_rows = 0;

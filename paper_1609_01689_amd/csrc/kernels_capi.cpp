@@ -97,7 +97,8 @@ int hsym_kernel_precond(hsym_t H, int kind, int m, double *W, const double *mu, 
         if (!H || !H->ready) fail(HSYM_E_INVALID_ARG, "invalid handle");
         check_nm(H->n, m);
         if (!W || !mu) fail(HSYM_E_INVALID_ARG, "NULL block");
-        if (kind != HSYM_PRECOND_JACOBI && kind != HSYM_PRECOND_BLOCK64) fail(HSYM_E_INVALID_ARG, "bad kind");
+        if (kind != HSYM_PRECOND_JACOBI && kind != HSYM_PRECOND_BLOCK64 && kind != HSYM_PRECOND_FOM)
+            fail(HSYM_E_INVALID_ARG, "bad kind");
         if (kind == HSYM_PRECOND_BLOCK64 && !H->pre_q) fail(HSYM_E_INVALID_ARG, "block64 factors not built");
         precond_apply(H, kind, W, mu, delta, m, (hipStream_t)stream);
     });

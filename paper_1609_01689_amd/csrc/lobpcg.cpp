@@ -136,6 +136,9 @@ struct Lobpcg {
         if (opts) o = *opts;
         if (o.maxit < 1) o.maxit = 1000;
         if (o.check_every < 1) o.check_every = 1;
+        if (pc == HSYM_PRECOND_FOM && !H->tg_dense)
+            fail(HSYM_E_INVALID_ARG, "FOM preconditioner needs hsym_attach_group_tiles on the handle");
+        if (o.fom_iters < 1 || o.fom_iters > 4) fail(HSYM_E_INVALID_ARG, "fom_iters must be in [1, 4]");
         if (pc == HSYM_PRECOND_BLOCK64 && !H->pre_q)
             fail(HSYM_E_INVALID_ARG, "block64 preconditioner needs a handle created with HSYM_BUILD_BLOCK64");
         size_t nm = (size_t)n * m;
@@ -299,7 +302,7 @@ struct Lobpcg {
         auto body = [&] {
             if (pre) {
                 HIPCHK(hipMemcpyAsync(mu, mu_h, sizeof(double) * m, hipMemcpyHostToDevice, s));
-                precond_apply(H, precond, W, mu, o.guard * H->norm1, m, s);
+                precond_apply(H, precond, W, mu, o.guard * H->norm1, m, s, o.fom_iters);
             }
             orth_part1();
         };
@@ -663,6 +666,7 @@ void lobpcg_opts_default(lobpcg_opts *o) {
     o->near = 0.1;
     o->guard = 1e-4;
     o->keep_history = 1;
+    o->fom_iters = 3;
 }
 
 static void check_solve_args(hsym_t H, int nev, int m, double tol) {
@@ -677,7 +681,7 @@ int lobpcg_solve(hsym_t H, int nev, int block_width, double tol, const double *X
     try {
         check_solve_args(H, nev, block_width, tol);
         if (!evals) fail(HSYM_E_INVALID_ARG, "NULL evals");
-        if (precond < HSYM_PRECOND_NONE || precond > HSYM_PRECOND_BLOCK64) fail(HSYM_E_INVALID_ARG, "bad precond");
+        if (precond < HSYM_PRECOND_NONE || precond > HSYM_PRECOND_FOM) fail(HSYM_E_INVALID_ARG, "bad precond");
         Lobpcg L;
         L.setup(H, nev, block_width, tol, X0, precond, opts, (hipStream_t)stream);
         L.run();
@@ -727,7 +731,7 @@ int lobpcg_ctx_create(lobpcg_ctx_t *out, hsym_t H, int nev, int block_width, dou
     return ctx_guard([&] {
         if (!out) fail(HSYM_E_INVALID_ARG, "NULL context pointer");
         check_solve_args(H, nev, block_width, tol);
-        if (precond < HSYM_PRECOND_NONE || precond > HSYM_PRECOND_BLOCK64) fail(HSYM_E_INVALID_ARG, "bad precond");
+        if (precond < HSYM_PRECOND_NONE || precond > HSYM_PRECOND_FOM) fail(HSYM_E_INVALID_ARG, "bad precond");
         lobpcg_ctx *c = new lobpcg_ctx();
         try {
             hipStream_t s = (hipStream_t)stream;
