@@ -48,7 +48,7 @@ def kernel_source_hash():
 
 def measured_traffic(m):
     """HBM bytes per SpMM call from the committed counter summary (FETCH_SIZE
-    and WRITE_SIZE of k_spmm_panel + k_spmm_reduce, scaled by the factor the
+    and WRITE_SIZE of k_zero_rows + k_spmm_panel, scaled by the factor the
     same counters give for an elementwise kernel of known size), or None when
     the summary is absent, for another block width, or the kernel sources
     changed since it was taken."""
@@ -243,7 +243,7 @@ def scale_workload(args, name):
                                                                  precond)},
         "roofline": {"bound": "hbm", "achieved": res["mixed"]["spmm_GBs_algorithmic"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": res["mixed"]["spmm_GBs_algorithmic"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "spmm_sym fp32 storage m=16 (k_spmm_panel + k_spmm_reduce)",
+                     "kernel": "spmm_sym fp32 storage m=16 (k_zero_rows + k_spmm_panel)",
                      "launch_ms": res["mixed"]["spmm_ms_in_solve"]},
         "cpu_baseline": None,
         "mixed_vs_fp64_speedup": res["fp64"]["s_to_tol"] / res["mixed"]["s_to_tol"],
@@ -455,7 +455,7 @@ def main():
         "iters": int(np.median(iters)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(m),
-                     "kernel": "spmm_sym fp64 m=%d (k_spmm_panel + k_spmm_reduce)" % m,
+                     "kernel": "spmm_sym fp64 m=%d (k_zero_rows + k_spmm_panel)" % m,
                      "launch_ms": live_ms, "launches_timed": spmm_live_calls, "algorithmic_bytes": alg,
                      "microbench_ms": spmm_ms},
         "cpu_baseline": cpu,

@@ -149,7 +149,8 @@ int hsym_info(hsym_t H, hsym_info_t *out);
  * are held in fp32 (X rounded once as it is staged); every product is formed
  * and summed in fp64 (the product of two fp32 numbers is exact in fp64) and
  * Y is returned in fp64.  The transposed half is summed with workgroup-local
- * atomics, so repeated calls agree to rounding, not bitwise.
+ * atomics and added into Y with device-scope atomics, so repeated calls agree
+ * to rounding, not bitwise.
  * X and Y must not overlap.  Errors: HSYM_E_INVALID_ARG, HSYM_E_DEVICE.
  */
 int spmm_sym(hsym_t H, int m, const double *X, int64_t ldx, double *Y, int64_t ldy,

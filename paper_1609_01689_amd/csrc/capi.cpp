@@ -291,7 +291,7 @@ int spmm_sym_f32(hsym_t H, int m, const float *X, int64_t ldx, float *Y, int64_t
     if (H->storage != HSYM_FP32) fail(HSYM_E_INVALID_ARG, "spmm_sym_f32 needs fp32 storage");
     hipStream_t s = (hipStream_t)stream;
     void *pp = nullptr;
-    HIPCHK(hipMallocAsync(&pp, spmm_partial_bytes(H, m), s));
+    HIPCHK(hipMallocAsync(&pp, spmm_partial_bytes(H, m, T_F32), s));
     try {
         spmm_launch(H, m, X, T_F32, ldx, Y, T_F32, ldy, pp, s);
     } catch (...) {

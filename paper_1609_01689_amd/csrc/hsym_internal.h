@@ -35,7 +35,7 @@ void check_hip(hipError_t e, const char *what);
 // base + e*G + s, so G lane groups stream a tile with coalesced loads and equal
 // work.  A tile is "own" when its chunk lies inside the panel (its transposed
 // half lands in the panel's rows) and "external" otherwise; every external tile
-// owns one partial-sum slot of C rows.
+// owns one partial-sum slot of C rows (used when the output is fp32).
 // ---------------------------------------------------------------------------
 struct TileDesc {
     int64_t base;          // first stored entry
@@ -115,7 +115,9 @@ struct Scratch {
 enum { T_F64 = 0, T_F32 = 1 };
 void spmm_launch(hsym_matrix *H, int m, const void *X, int xprec, int64_t ldx, void *Y, int yprec,
                  int64_t ldy, void *partials, hipStream_t s);
-size_t spmm_partial_bytes(hsym_matrix *H, int m);
+// partial-slot scratch of one SpMM call: fp32 outputs sum the transposed half
+// of external tiles through slots and a reduction; fp64 outputs add it into Y
+size_t spmm_partial_bytes(hsym_matrix *H, int m, int yprec = T_F64);
 
 // one matrix of a batched SpMM (fp64 blocks with leading dimension m)
 struct SpmmJob {
