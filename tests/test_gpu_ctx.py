@@ -121,7 +121,15 @@ def test_batched_rounds_match_solo_solves():
         print("case %d n=%d m=%d %s: iters %d (alone %d), batched %d, max rel diff %.2e"
               % (i, n, m, pc, rep.iters, it0, rep.batched_iters, np.max(np.abs(ev - ev0) / np.abs(ev0))))
         assert done and s == hs.HSYM_OK
-        assert np.max(np.abs(ev - ev0) / np.abs(ev0)) <= 1e-9
+        if st == hs.HSYM_FP64:
+            lim = 1e-9
+        else:
+            # fp32 storage stages X rounded to fp32 in every SpMM: the operator
+            # carries a rounding term of up to u32 |H| |X| that follows the
+            # (run to run different) last bits of X, so two solves agree to
+            # about 2 u32 ||H||_1 / |lambda|, not to the residual tolerance
+            lim = 2 * 2.0 ** -24 * mats[i].info["norm1"] / np.min(np.abs(ev0))
+        assert np.max(np.abs(ev - ev0) / np.abs(ev0)) <= lim
         assert abs(rep.iters - it0) <= 2
         if pc == "block64" or m == 4:
             assert rep.batched_iters == 0          # outside every batch (a group of one for m = 4)
