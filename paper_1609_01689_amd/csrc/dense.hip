@@ -54,19 +54,27 @@ __device__ __forceinline__ void gram_partial_body(const GramArgs &g, double *__r
     const int64_t r_begin = bx * rows_per_wg;
     int64_t r_end = r_begin + rows_per_wg;
     if (r_end > g.n) r_end = g.n;
-    for (int64_t r0 = r_begin + 4 * wave; r0 < r_end; r0 += 16) {
-        const int64_t r = r0 + lk;
-        const bool ok = r < r_end;
-        double av[T1], bv[T2];
+    // GU row steps of 16 are loaded before their MFMAs (more loads in flight
+    // per wave); each accumulator still takes the rows in ascending order
+    constexpr int GU = 4;
+    for (int64_t r0 = r_begin + 4 * wave; r0 < r_end; r0 += 16 * GU) {
+        double av[GU][T1], bv[GU][T2];
 #pragma unroll
-        for (int t = 0; t < T1; t++) av[t] = (ok && ca[t]) ? pa[t][r * m] : 0.0;
+        for (int u = 0; u < GU; u++) {
+            const int64_t r = r0 + 16 * u + lk;
+            const bool ok = r < r_end;
 #pragma unroll
-        for (int t = 0; t < T2; t++) bv[t] = (ok && cb[t]) ? pb[t][r * m] : 0.0;
+            for (int t = 0; t < T1; t++) av[u][t] = (ok && ca[t]) ? pa[t][r * m] : 0.0;
 #pragma unroll
-        for (int i = 0; i < T1; i++)
+            for (int t = 0; t < T2; t++) bv[u][t] = (ok && cb[t]) ? pb[t][r * m] : 0.0;
+        }
 #pragma unroll
-            for (int j = 0; j < T2; j++)
-                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+        for (int u = 0; u < GU; u++)
+#pragma unroll
+            for (int i = 0; i < T1; i++)
+#pragma unroll
+                for (int j = 0; j < T2; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i], bv[u][j], acc[i][j], 0, 0, 0);
     }
 #pragma unroll
     for (int i = 0; i < T1; i++)
@@ -190,17 +198,37 @@ __device__ __forceinline__ void lincomb_body(const LincombArgs &a, int64_t bx) {
     const bool rok = ra < a.n;
     double4_t xkeep = (double4_t){0.0, 0.0, 0.0, 0.0};
     double nrm = 0.0;
-    for (int set = 0; set < a.nsets; set++) {
-        double av[3][4];
+    // every input value of this wave's 16 rows (both sets) and every
+    // coefficient it needs are loaded before the first store: a wave reads and
+    // writes only its own rows, so outputs may alias inputs, and all the loads
+    // are in flight together
+    double av[2][3][4], bv[2][3][4];
 #pragma unroll
-        for (int i = 0; i < 3; i++) {
+    for (int set = 0; set < 2; set++)
+#pragma unroll
+        for (int i = 0; i < 3; i++)
 #pragma unroll
             for (int s4 = 0; s4 < 4; s4++) {
                 const int kk = 4 * s4 + lk;
-                av[i][s4] = (i < nin && rok && kk < m) ? a.in[set * 3 + i][ra * m + kk] : 0.0;
+                av[set][i][s4] =
+                    (set < a.nsets && i < nin && rok && kk < m) ? a.in[set * 3 + i][ra * m + kk] : 0.0;
             }
-        }
-        for (int q = 0; q < nout; q++) {
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int s4 = 0; s4 < 4; s4++) {
+                const int kk = 4 * s4 + lk;
+                bv[q][i][s4] = (q < nout && i < nin && kk < m && li < m)
+                                   ? a.coef[(i * m + kk) * a.ldc + q * m + li] : 0.0;
+            }
+#pragma unroll
+    for (int set = 0; set < 2; set++) {
+        if (set >= a.nsets) break;
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            if (q >= nout) break;
             double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int i = 0; i < 3; i++) {
@@ -208,9 +236,7 @@ __device__ __forceinline__ void lincomb_body(const LincombArgs &a, int64_t bx) {
 #pragma unroll
                 for (int s4 = 0; s4 < 4; s4++) {
                     if (4 * s4 >= m) break;
-                    const int kk = 4 * s4 + lk;
-                    const double bv = (kk < m && li < m) ? a.coef[(i * m + kk) * a.ldc + q * m + li] : 0.0;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s4], bv, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[set][i][s4], bv[q][i][s4], acc, 0, 0, 0);
                 }
             }
             // accumulator register v holds row lk + 4v, column li of this wave's 16 rows
