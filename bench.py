@@ -371,6 +371,14 @@ def main():
         spmv_ms = time_spmm(hs, torch, M1, 1, args.spmm_reps, torch.float64)
         M1.close()
         extras["spmv_fp64"] = {"ms": spmv_ms, "GB/s": spmm_algorithmic_bytes(A.nnz, A.n, 1, 8, 8, 8) / spmv_ms / 1e6}
+        # 16-bit tile-local index codes: handle memory against SpMM time
+        M16 = hs.Matrix(A, storage=hs.HSYM_FP64, geom_m=m, flags=hs.HSYM_INDEX16)
+        i16 = M16.info
+        spmm16_ms = time_spmm(hs, torch, M16, m, args.spmm_reps, torch.float64)
+        M16.close()
+        extras["spmm_index16"] = {"index_bytes": i16["index_bytes"], "handle_GB": i16["device_bytes"] / 1e9,
+                                  "handle_GB_index32": M.info["device_bytes"] / 1e9, "ms": spmm16_ms,
+                                  "ms_index32": spmm_ms}
         # mixed precision: fp32 storage and SpMM, fp64 everything else
         Mf = hs.Matrix(A, storage=hs.HSYM_FP32, geom_m=m)
         spmm32_ms = time_spmm(hs, torch, Mf, m, args.spmm_reps, torch.float32)

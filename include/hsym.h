@@ -62,6 +62,12 @@ enum hsym_precond { HSYM_PRECOND_NONE = 0, HSYM_PRECOND_JACOBI = 1, HSYM_PRECOND
 /* hsym_create flags */
 #define HSYM_HOST_PTRS     0x0   /* rowptr/colind/values are host memory (default)   */
 #define HSYM_BUILD_BLOCK64 0x2   /* also build the 64x64 block preconditioner factors */
+/* Store the tile-local index codes (local row and column packed together) in
+ * 16 bits instead of 32 when the chunk width C is a power of two and
+ * R * C <= 2^16 (Section 4.2: indices local to a block need only 16 bits):
+ * 2 bytes less per stored entry, for a slightly slower SpMM.  Other
+ * geometries keep 32-bit codes; hsym_info reports the width in use. */
+#define HSYM_INDEX16       0x4
 /* Tile geometry hint: the block width (1..16) the panel sizes are chosen for,
  * in bits 8..15 (0 = 16).  Any block width whose LDS footprint fits the chosen
  * geometry can be used with the handle; a narrower hint gives taller panels. */
@@ -90,6 +96,7 @@ typedef struct {
     int64_t padded_entries;     /* stored off-diagonal entries after slice padding    */
     int64_t device_bytes;       /* device memory held by the handle                   */
     int has_block64;
+    int index_bytes;            /* bytes of one tile-local index code: 2 or 4         */
 } hsym_info_t;
 
 /*
@@ -103,7 +110,8 @@ typedef struct {
  *   storage precision of the device copy: HSYM_FP64 (plain form) or HSYM_FP32
  *           (mixed form, Section 4.4 footnote 5: H stored and multiplied in
  *           single precision); fp64 input is rounded to nearest once;
- *   flags   HSYM_HOST_PTRS | optional HSYM_BUILD_BLOCK64.
+ *   flags   HSYM_HOST_PTRS | optional HSYM_BUILD_BLOCK64, HSYM_INDEX16,
+ *           HSYM_GEOM_M, HSYM_GEOM_PANEL.
  * The call copies: the caller may free its arrays on return.  Synchronous.
  * Errors: HSYM_E_INVALID_ARG for any CSR violation listed above or n < 1 or
  * n >= 2^31; HSYM_E_OUT_OF_MEMORY; HSYM_E_DEVICE.  *H is NULL on error.

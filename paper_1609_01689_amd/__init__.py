@@ -28,6 +28,7 @@ HSYM_E_BREAKDOWN, HSYM_E_NUMERIC, HSYM_E_UNSUPPORTED = -4, -5, -6
 HSYM_FP64, HSYM_FP32 = 0, 1
 PRECOND = {"none": 0, "jacobi": 1, "block64": 2, "fom": 3}
 HSYM_BUILD_BLOCK64 = 0x2
+HSYM_INDEX16 = 0x4
 MAX_BLOCK = 16
 MAX_HISTORY = 4096
 
@@ -56,7 +57,7 @@ class hsym_info_t(ctypes.Structure):
                 ("storage", ctypes.c_int), ("panel_rows", ctypes.c_int), ("chunk_cols", ctypes.c_int),
                 ("npanels", ctypes.c_int64), ("ntiles", ctypes.c_int64), ("nslots", ctypes.c_int64),
                 ("padded_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("has_block64", ctypes.c_int)]
+                ("has_block64", ctypes.c_int), ("index_bytes", ctypes.c_int)]
 
 
 class lobpcg_opts(ctypes.Structure):
@@ -477,8 +478,8 @@ def hsym_serve_sim(arrival_s, iters, iter_s, nbytes, load_s, nev=1, **opts):
 class Matrix:
     """Owning wrapper of an hsym handle (create from an upper-triangle CSR)."""
 
-    def __init__(self, csr, storage=HSYM_FP64, block64=False, geom_m=16, stream=None):
-        flags = (HSYM_BUILD_BLOCK64 if block64 else 0) | HSYM_GEOM_M(geom_m)
+    def __init__(self, csr, storage=HSYM_FP64, block64=False, geom_m=16, stream=None, flags=0):
+        flags |= (HSYM_BUILD_BLOCK64 if block64 else 0) | HSYM_GEOM_M(geom_m)
         self.n = csr.n
         self.storage = storage
         self.h = hsym_create(csr.n, csr.rowptr, csr.colind, csr.values, storage, flags, stream)

@@ -129,7 +129,7 @@ static void block64_factor(int64_t c0, int sz, int64_t slab_row0, const int64_t 
 
 // Rows [r0, r1) of the matrix; rp/ci/v index the caller's slab whose first row
 // is slab_row0.  dg receives the diagonal of the panel rows.
-static void build_panel(int64_t n, int64_t r0, int64_t r1, int R, int C, int G, int storage, bool b64,
+static void build_panel(int64_t n, int64_t r0, int64_t r1, int R, int C, int G, int cs, int storage, bool b64,
                         int64_t slab_row0, const int64_t *rp, const int32_t *ci,
                         const double *vin64, const float *vin32, double *dg, PanelOut &out) {
     const int nr = (int)(r1 - r0);
@@ -199,7 +199,7 @@ static void build_panel(int64_t n, int64_t r0, int64_t r1, int R, int C, int G, 
         const size_t sz = (size_t)td.len * G;
         const size_t b0 = out.idx.size();
         // padding: zero values on the last row (keeps a segment's row run unbroken)
-        out.idx.resize(b0 + sz, (uint32_t)last << 16);
+        out.idx.resize(b0 + sz, (uint32_t)last << cs);
         if (storage == HSYM_FP64) out.v64.resize(b0 + sz, 0.0);
         else out.v32.resize(b0 + sz, 0.0f);
         int64_t logical = 0;
@@ -208,7 +208,7 @@ static void build_panel(int64_t n, int64_t r0, int64_t r1, int R, int C, int G, 
                 int64_t p = cur[i] + e;
                 const int64_t seg = logical / td.len, pos = logical - seg * td.len;
                 const size_t at = b0 + (size_t)pos * G + (size_t)seg;
-                out.idx[at] = ((uint32_t)i << 16) | (uint32_t)(ci[p] - g * (int64_t)C);
+                out.idx[at] = ((uint32_t)i << cs) | (uint32_t)(ci[p] - g * (int64_t)C);
                 if (storage == HSYM_FP64) out.v64[at] = vin64 ? vin64[p] : (double)vin32[p];
                 else out.v32[at] = vin64 ? (float)vin64[p] : vin32[p];
             }
@@ -247,6 +247,8 @@ struct DevVec {
 
 struct Builder {
     int R = 0, C = 0, G = 256;
+    bool idx16 = false;             // 16-bit index codes (shift log2 C)
+    int cs = 16;                    // code shift: local row << cs | local column
     int storage = HSYM_FP64;
     bool b64 = false;
     DevVec<double> preq, prelam;
@@ -262,6 +264,7 @@ struct Builder {
     // device arrays
     DevVec<TileDesc> tiles;
     DevVec<uint32_t> idx;
+    DevVec<uint16_t> idx16v;
     DevVec<double> v64;
     DevVec<float> v32;
     std::vector<int64_t> panel_tile_ptr{0};
@@ -272,7 +275,7 @@ struct Builder {
     int64_t nentries = 0, ntiles = 0;
 
     void release() {
-        tiles.release(); idx.release(); v64.release(); v32.release();
+        tiles.release(); idx.release(); idx16v.release(); v64.release(); v32.release();
         preq.release(); prelam.release();
     }
 
@@ -287,7 +290,7 @@ struct Builder {
                 for (int64_t k = a; k < b; k++) {
                     int64_t p = b0 + k;
                     int64_t r0 = p * R, r1 = std::min(n, r0 + R);
-                    build_panel(n, r0, r1, R, C, G, storage, b64, slab_row0, rp, ci, vin64, vin32,
+                    build_panel(n, r0, r1, R, C, G, cs, storage, b64, slab_row0, rp, ci, vin64, vin32,
                                 diag.data() + r0, outs[(size_t)k]);
                 }
             });
@@ -319,7 +322,12 @@ struct Builder {
                 PanelOut().tiles.swap(o.tiles);
             }
             tiles.append(t.data(), (int64_t)t.size());
-            idx.append(c.data(), (int64_t)c.size());
+            if (idx16) {
+                std::vector<uint16_t> c16(c.begin(), c.end());
+                idx16v.append(c16.data(), (int64_t)c16.size());
+            } else {
+                idx.append(c.data(), (int64_t)c.size());
+            }
             if (storage == HSYM_FP64) v64.append(d64.data(), (int64_t)d64.size());
             else v32.append(d32.data(), (int64_t)d32.size());
             if (b64) { preq.append(pq.data(), (int64_t)pq.size()); prelam.append(pl.data(), (int64_t)pl.size()); }
@@ -410,11 +418,17 @@ void builder_begin(hsym_matrix *H, int64_t nnz_hint) {
     if (b->G < 1) fail(HSYM_E_INVALID_ARG, "bad segment count");
     if (b->R % b->C != 0 || b->C > 65536 || b->R > 65535)
         fail(HSYM_E_INVALID_ARG, "panel rows must be a multiple of chunk columns (<= 65535)");
+    // 16-bit codes on request, when a tile's local row and column fit in 16 bits together
+    if ((H->flags & HSYM_INDEX16) && (b->C & (b->C - 1)) == 0 && (int64_t)b->R * b->C <= 65536) {
+        b->idx16 = true;
+        b->cs = 0;
+        while ((1 << b->cs) < b->C) b->cs++;
+    }
     b->diag.assign((size_t)H->n, 0.0);
     b->abssum.assign((size_t)H->n, 0.0);
     if (nnz_hint > 0) {
         int64_t est = nnz_hint + nnz_hint / 8 + 4096;
-        b->idx.reserve(est);
+        if (b->idx16) b->idx16v.reserve(est); else b->idx.reserve(est);
         if (H->storage == HSYM_FP64) b->v64.reserve(est); else b->v32.reserve(est);
     }
     std::lock_guard<std::mutex> g(g_builders_mu);
@@ -450,12 +464,16 @@ void builder_finish(hsym_matrix *H) {
     dt.nchunks = (H->n + b->C - 1) / b->C;
     dt.ntiles = b->ntiles; dt.nentries = b->nentries;
     dt.nslots = (int64_t)b->slot_chunk.size();
-    dt.tiles = b->tiles.p; dt.idx = b->idx.p;
+    dt.tiles = b->tiles.p;
+    dt.idx = b->idx16 ? (void *)b->idx16v.p : (void *)b->idx.p;
+    dt.idx_bytes = b->idx16 ? 2 : 4;
+    dt.idx_shift = b->cs;
     dt.vals = H->storage == HSYM_FP64 ? (void *)b->v64.p : (void *)b->v32.p;
-    b->tiles.p = nullptr; b->idx.p = nullptr;
+    const int64_t idx_cap_bytes = b->idx16 ? b->idx16v.cap * 2 : b->idx.cap * 4;
+    b->tiles.p = nullptr; b->idx.p = nullptr; b->idx16v.p = nullptr;
     b->v64.p = nullptr; b->v32.p = nullptr;
     int vs = H->storage == HSYM_FP64 ? 8 : 4;
-    dt.bytes = b->tiles.cap * (int64_t)sizeof(TileDesc) + b->idx.cap * 4 +
+    dt.bytes = b->tiles.cap * (int64_t)sizeof(TileDesc) + idx_cap_bytes +
                (H->storage == HSYM_FP64 ? b->v64.cap : b->v32.cap) * vs;
     // panel pointers
     HIPCHK(hipMalloc(&dt.panel_tile_ptr, sizeof(int64_t) * b->panel_tile_ptr.size()));

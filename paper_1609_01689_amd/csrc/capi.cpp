@@ -259,6 +259,7 @@ int hsym_info(hsym_t H, hsym_info_t *o) {
     o->padded_entries = H->tiles.nentries;
     o->device_bytes = H->bytes;
     o->has_block64 = H->pre_q != nullptr;
+    o->index_bytes = H->tiles.idx_bytes;
     API_END
 }
 

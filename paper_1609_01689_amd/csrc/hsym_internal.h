@@ -29,8 +29,10 @@ void check_hip(hipError_t e, const char *what);
 // coordinate form with 16-bit local row and column offsets).  Rows are cut
 // into panels of R rows and columns into chunks of C columns (R a multiple of
 // C).  The strictly-upper entries of one panel that fall into one chunk form a
-// tile, stored row-major as 32-bit words (local row << 16 | local column) plus
-// values.  A tile's entries are cut into G equal segments (the last one padded
+// tile, stored row-major as index codes (local row << shift | local column)
+// plus values: 32-bit codes with shift = 16, or, on request (HSYM_INDEX16),
+// 16-bit codes with shift = log2 C when C is a power of two and R * C <= 2^16
+// (Section 4.2: indices local to a block need only 16 bits).  A tile's entries are cut into G equal segments (the last one padded
 // with zero values) stored interleaved: entry e of segment s sits at
 // base + e*G + s, so G lane groups stream a tile with coalesced loads and equal
 // work.  A tile is "own" when its chunk lies inside the panel (its transposed
@@ -51,7 +53,9 @@ struct DeviceTiles {
     int64_t nred_chunks = 0;
     int64_t *panel_tile_ptr = nullptr;
     TileDesc *tiles = nullptr;
-    uint32_t *idx = nullptr;
+    void *idx = nullptr;          // uint16_t codes when idx_bytes == 2, else uint32_t
+    int idx_bytes = 4;
+    int idx_shift = 16;           // local row << idx_shift | local column
     void *vals = nullptr;
     int64_t *red_ptr = nullptr;
     int32_t *red_slot = nullptr;
@@ -123,7 +127,8 @@ size_t spmm_partial_bytes(hsym_matrix *H, int m, int yprec = T_F64);
 struct SpmmJob {
     const int64_t *ptp;
     const TileDesc *tiles;
-    const uint32_t *idx;
+    const void *idx;
+    int idx_bytes, idx_shift;
     const void *vals;
     const void *diag;
     const double *X;

@@ -7,7 +7,10 @@
 // One 1024-thread workgroup owns one row panel of R rows and walks its tiles
 // in column order, as the CSB traversal of Section 4.4 does.  In LDS it keeps
 // the panel's accumulator and X rows, plus the X rows and the transposed
-// accumulator of the current external chunk.  A tile's entries are split in
+// accumulator of the current external chunk.  Entries carry tile-local index
+// codes (local row << shift | local column), 32-bit, or 16-bit on request when
+// R * C <= 2^16 (measured 4% slower at fp64, m = 16; 17% less handle memory).
+// A tile's entries are split in
 // equal segments, one per group of LPE lanes; each lane of a group handles
 // MW = M/LPE adjacent columns (2 when M >= 2):
 //   - row half: a register accumulator for the current row, added to the
@@ -105,9 +108,10 @@ __device__ __forceinline__ void read_row(const T *rowp, int r, int k0, double *o
 // T: stored values and staged X; products and sums are fp64 for both storage
 // precisions (a product of two fp32 numbers is exact in fp64, and the LDS fp64
 // atomic add is several times cheaper than the fp32 one on gfx950)
-template <int M, typename T, typename XIN, typename YT>
+// IT: uint16_t or uint32_t index codes, local row << cs | local column
+template <int M, typename T, typename XIN, typename YT, typename IT>
 __device__ __forceinline__ void spmm_panel_body(
-    const int64_t *__restrict__ ptp, const TileDesc *__restrict__ tiles, const uint32_t *__restrict__ idx,
+    const int64_t *__restrict__ ptp, const TileDesc *__restrict__ tiles, const IT *__restrict__ idx, int cs,
     const T *__restrict__ vals, const T *__restrict__ diag, const XIN *__restrict__ X, int64_t ldx,
     YT *__restrict__ Y, int64_t ldy, double *__restrict__ partials, int64_t n, int R, int C, int G,
     int64_t npanels, int m, int64_t blk, unsigned char *smem_raw) {
@@ -119,6 +123,7 @@ __device__ __forceinline__ void spmm_panel_body(
     T *xp = reinterpret_cast<T *>(ts + (size_t)C * M);
     T *xs = xp + (size_t)R * M;
     const int tid = threadIdx.x, g = tid / LPE, q = tid % LPE, k0 = q * MW;
+    const uint32_t cmask = (1u << cs) - 1u;   // 16-bit codes: local row << cs | local column
     const int64_t p = xcd_panel(blk, npanels);
     const int64_t row0 = p * (int64_t)R;
     const int nrow = (int)((n - row0) < R ? (n - row0) : R);
@@ -154,7 +159,7 @@ __device__ __forceinline__ void spmm_panel_body(
         double *tgt = ext ? ts : acc + (col0 - row0) * M;
         const int len = td.len;
         for (int seg = g; seg < G; seg += GK) {
-            const uint32_t *ip = idx + td.base + seg;
+            const IT *ip = idx + td.base + seg;
             const T *vp = vals + td.base + seg;
             int cur = -1;
             double ra[MW], xr[MW];
@@ -173,7 +178,14 @@ __device__ __forceinline__ void spmm_panel_body(
 #pragma unroll
                 for (int u = 0; u < B; u++) {
                     if (u >= cnt) break;
-                    const int r = (int)(w[u] >> 16), c = (int)(w[u] & 0xffffu);
+                    int r, c;
+                    if constexpr (sizeof(IT) == 2) {
+                        r = (int)(w[u] >> cs);
+                        c = (int)(w[u] & cmask);
+                    } else {   // 32-bit codes: row << 16 | column
+                        r = (int)(w[u] >> 16);
+                        c = (int)(w[u] & 0xffffu);
+                    }
                     if (r != cur) {
                         if (cur >= 0) {
 #pragma unroll
@@ -240,15 +252,15 @@ __device__ __forceinline__ void spmm_panel_body(
     }
 }
 
-template <int M, typename T, typename XIN, typename YT>
+template <int M, typename T, typename XIN, typename YT, typename IT>
 __global__ __launch_bounds__(1024) void k_spmm_panel(
-    const int64_t *__restrict__ ptp, const TileDesc *__restrict__ tiles, const uint32_t *__restrict__ idx,
+    const int64_t *__restrict__ ptp, const TileDesc *__restrict__ tiles, const IT *__restrict__ idx, int cs,
     const T *__restrict__ vals, const T *__restrict__ diag, const XIN *__restrict__ X, int64_t ldx,
     YT *__restrict__ Y, int64_t ldy, double *__restrict__ partials, int64_t n, int R, int C, int G,
     int64_t npanels, int m) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    spmm_panel_body<M, T, XIN, YT>(ptp, tiles, idx, vals, diag, X, ldx, Y, ldy, partials, n, R, C, G, npanels, m,
-                                   blockIdx.x, smem_raw);
+    spmm_panel_body<M, T, XIN, YT, IT>(ptp, tiles, idx, cs, vals, diag, X, ldx, Y, ldy, partials, n, R, C, G,
+                                       npanels, m, blockIdx.x, smem_raw);
 }
 
 // batched over matrices (fp64 blocks): blockIdx.y selects the job
@@ -257,9 +269,17 @@ __global__ __launch_bounds__(1024) void k_spmm_panel_b(const SpmmJob *__restrict
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SpmmJob J = jobs[blockIdx.y];
     if ((int64_t)blockIdx.x >= J.npanels) return;
-    spmm_panel_body<M, T, double, double>(J.ptp, J.tiles, J.idx, (const T *)J.vals, (const T *)J.diag, J.X, J.ldx,
-                                          J.Y, J.ldy, J.partials, J.n, J.R, J.C, J.G, J.npanels, J.m, blockIdx.x,
-                                          smem_raw);
+    // the index width is a property of each job's handle (uniform per workgroup)
+    if (J.idx_bytes == 2)
+        spmm_panel_body<M, T, double, double, uint16_t>(J.ptp, J.tiles, (const uint16_t *)J.idx, J.idx_shift,
+                                                        (const T *)J.vals, (const T *)J.diag, J.X, J.ldx, J.Y, J.ldy,
+                                                        J.partials, J.n, J.R, J.C, J.G, J.npanels, J.m, blockIdx.x,
+                                                        smem_raw);
+    else
+        spmm_panel_body<M, T, double, double, uint32_t>(J.ptp, J.tiles, (const uint32_t *)J.idx, J.idx_shift,
+                                                        (const T *)J.vals, (const T *)J.diag, J.X, J.ldx, J.Y, J.ldy,
+                                                        J.partials, J.n, J.R, J.C, J.G, J.npanels, J.m, blockIdx.x,
+                                                        smem_raw);
 }
 
 // Y[chunk rows] += sum of the partial slots of that chunk, in slot order.
@@ -325,12 +345,12 @@ static void zero_rows(double *Y, int64_t n, int m, int64_t ldy, hipStream_t s) {
     HIPCHK(hipGetLastError());
 }
 
-template <int M, typename T, typename XIN, typename YT>
+template <int M, typename T, typename XIN, typename YT, typename IT>
 static void launch_typed(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y, int64_t ldy,
                          void *partials, hipStream_t s) {
     const DeviceTiles &dt = H->tiles;
     size_t lds = (size_t)(dt.R + dt.C) * M * (sizeof(double) + sizeof(T));
-    auto kp = k_spmm_panel<M, T, XIN, YT>;
+    auto kp = k_spmm_panel<M, T, XIN, YT, IT>;
     static bool attr_set = false;
     if (!attr_set) {
         HIPCHK(hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
@@ -339,8 +359,8 @@ static void launch_typed(hsym_matrix *H, int m, const void *X, int64_t ldx, void
     const T *diag = (const T *)(H->storage == HSYM_FP64 ? (const void *)H->diag64 : (const void *)H->diag32);
     constexpr bool atomic_out = sizeof(YT) == 8;
     if (atomic_out) zero_rows((double *)Y, H->n, m, ldy, s);
-    hipLaunchKernelGGL(kp, dim3((unsigned)dt.npanels), dim3(1024), lds, s, dt.panel_tile_ptr, dt.tiles, dt.idx,
-                       (const T *)dt.vals, diag, (const XIN *)X, ldx, (YT *)Y, ldy, (double *)partials, H->n, dt.R,
+    hipLaunchKernelGGL(kp, dim3((unsigned)dt.npanels), dim3(1024), lds, s, dt.panel_tile_ptr, dt.tiles,
+                       (const IT *)dt.idx, dt.idx_shift, (const T *)dt.vals, diag, (const XIN *)X, ldx, (YT *)Y, ldy, (double *)partials, H->n, dt.R,
                        dt.C, dt.G, dt.npanels, m);
     HIPCHK(hipGetLastError());
     if (!atomic_out && dt.nred_chunks > 0) {
@@ -351,22 +371,30 @@ static void launch_typed(hsym_matrix *H, int m, const void *X, int64_t ldx, void
     }
 }
 
+template <typename T, typename XIN, typename YT, typename IT>
+static void launch_mi(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y, int64_t ldy, void *part,
+                      hipStream_t s) {
+    switch (round_m(m)) {
+        case 1: launch_typed<1, T, XIN, YT, IT>(H, m, X, ldx, Y, ldy, part, s); break;
+        case 2: launch_typed<2, T, XIN, YT, IT>(H, m, X, ldx, Y, ldy, part, s); break;
+        case 4: launch_typed<4, T, XIN, YT, IT>(H, m, X, ldx, Y, ldy, part, s); break;
+        case 8: launch_typed<8, T, XIN, YT, IT>(H, m, X, ldx, Y, ldy, part, s); break;
+        default: launch_typed<16, T, XIN, YT, IT>(H, m, X, ldx, Y, ldy, part, s); break;
+    }
+}
+
 template <typename T, typename XIN, typename YT>
 static void launch_m(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y, int64_t ldy, void *part,
                      hipStream_t s) {
-    switch (round_m(m)) {
-        case 1: launch_typed<1, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
-        case 2: launch_typed<2, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
-        case 4: launch_typed<4, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
-        case 8: launch_typed<8, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
-        default: launch_typed<16, T, XIN, YT>(H, m, X, ldx, Y, ldy, part, s); break;
-    }
+    if (H->tiles.idx_bytes == 2) launch_mi<T, XIN, YT, uint16_t>(H, m, X, ldx, Y, ldy, part, s);
+    else launch_mi<T, XIN, YT, uint32_t>(H, m, X, ldx, Y, ldy, part, s);
 }
 
 SpmmJob spmm_job(hsym_matrix *H, int m, const double *X, double *Y, double *partials) {
     const DeviceTiles &dt = H->tiles;
     SpmmJob J{};
     J.ptp = dt.panel_tile_ptr; J.tiles = dt.tiles; J.idx = dt.idx; J.vals = dt.vals;
+    J.idx_bytes = dt.idx_bytes; J.idx_shift = dt.idx_shift;
     J.diag = H->storage == HSYM_FP64 ? (const void *)H->diag64 : (const void *)H->diag32;
     J.X = X; J.ldx = m; J.Y = Y; J.ldy = m; J.partials = partials;
     J.n = H->n; J.R = dt.R; J.C = dt.C; J.G = dt.G; J.npanels = dt.npanels; J.m = m;

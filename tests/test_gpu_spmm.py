@@ -175,3 +175,39 @@ def test_streaming_create_matches_whole():
     hs.hsym_destroy(h)
     Ys = Yd.cpu().numpy()
     assert np.linalg.norm(Ys - Yw) <= 1e-13 * np.linalg.norm(Yw)
+
+
+@pytest.mark.parametrize("storage", [hs.HSYM_FP64, hs.HSYM_FP32])
+def test_index_code_widths(storage):
+    """16-bit tile-local codes on request where R * C <= 2^16, 32-bit
+    otherwise; the product is the same within rounding either way."""
+    A = hsymgen.generate(9001, 150, 17)
+    H = oracle.SymMatrix.from_csr(A)
+    X = hsymgen.gauss_block(4, A.n, 16)
+    Yref = H.spmm(X)
+    tol = 1e-12 if storage == hs.HSYM_FP64 else 1e-5
+    I16 = hs.HSYM_INDEX16
+    cases = [(hs.HSYM_GEOM_M(16) | I16, 2),                            # R = 256, C = 64
+             (hs.HSYM_GEOM_M(16), 4),
+             (hs.HSYM_GEOM_PANEL(9, 7) | I16, 2),                      # R * C = 2^16 exactly
+             (hs.HSYM_GEOM_PANEL(9, 8) | hs.HSYM_GEOM_M(8) | I16, 4)]  # 2^17: 32-bit codes
+    out = []
+    for flags, width in cases:
+        M = hs.Matrix(A, storage=storage, flags=flags)
+        info = M.info
+        assert info["index_bytes"] == width, (flags, info)
+        es = 8 if storage == hs.HSYM_FP64 else 4
+        m = 16 if (info["panel_rows"] + info["chunk_cols"]) * 16 * (8 + es) <= 160 * 1024 else 8
+        Xd = torch.from_numpy(X[:, :m].copy()).to(_dev())
+        Yd = torch.empty_like(Xd)
+        hs.spmm_sym(M.h, Xd, Yd)
+        torch.cuda.synchronize()
+        Y = Yd.cpu().numpy()
+        assert np.linalg.norm(Y - Yref[:, :m]) <= tol * np.linalg.norm(Yref[:, :m])
+        out.append((info, Y))
+        M.close()
+    # the same geometry with 16- and 32-bit codes: 2 bytes less per padded entry
+    (i16, y16), (i32, y32) = out[0], out[1]
+    assert i16["padded_entries"] == i32["padded_entries"]
+    assert i16["device_bytes"] <= i32["device_bytes"] - 2 * i32["padded_entries"] + 4096
+    assert np.linalg.norm(y16 - y32) <= 1e-13 * np.linalg.norm(y32)
