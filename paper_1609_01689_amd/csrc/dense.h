@@ -83,6 +83,11 @@ struct RRArgs {
     double *evals_all;    // k (diagnostics), or null: then only the m lowest are computed
     int *flag;            // 1 + multisection rounds used (>0), or -1 on failure
     int nblk, m;
+    // optional (nblk >= 2): the W block of the basis is W' U with U (m x m,
+    // row-major) applied implicitly: gram holds [X W' P]^T A [X W' P], the
+    // eigenproblem is solved for T^T gram T with T = diag(I, U, I), and the W
+    // rows of coef are returned for W' (premultiplied by U)
+    const double *wtrans;
 };
 void small_rr(const RRArgs *a, int count, hipStream_t s);
 void set_int(int *p, int v, hipStream_t s);

@@ -110,16 +110,22 @@ __device__ __forceinline__ void gram_final_body(const double *__restrict__ part,
     __shared__ double red[16][64];
     const int el = threadIdx.x & 63, sl = threadIdx.x >> 6;
     const int e = bx * 64 + el;
-    double s0 = 0.0, s1 = 0.0;
+    // four independent chains per thread, so the loads of four part-slices
+    // are in flight together; the order of the sums is fixed
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     if (e < kk) {
         int p = sl;
-        for (; p + 16 < nparts; p += 32) {
-            s0 += part[(int64_t)p * kk + e];
-            s1 += part[(int64_t)(p + 16) * kk + e];
+        for (; p + 48 < nparts; p += 64) {
+            const double a0 = part[(int64_t)p * kk + e], a1 = part[(int64_t)(p + 16) * kk + e];
+            const double a2 = part[(int64_t)(p + 32) * kk + e], a3 = part[(int64_t)(p + 48) * kk + e];
+            s0 += a0;
+            s1 += a1;
+            s2 += a2;
+            s3 += a3;
         }
-        if (p < nparts) s0 += part[(int64_t)p * kk + e];
+        for (; p < nparts; p += 16) s0 += part[(int64_t)p * kk + e];
     }
-    red[sl][el] = s0 + s1;
+    red[sl][el] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     for (int h = 8; h > 0; h >>= 1) {
         if (sl < h) red[sl][el] += red[sl + h][el];
@@ -300,14 +306,18 @@ int64_t lincomb_norm_parts(int64_t n) { return (n + 63) / 64; }
 __device__ __forceinline__ void colsum_body(const double *__restrict__ part, int64_t nparts, int m,
                                             double *__restrict__ out, int j) {
     __shared__ double red[1024];
-    double s0 = 0.0, s1 = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int64_t p = threadIdx.x;
-    for (; p + 1024 < nparts; p += 2048) {
-        s0 += part[p * m + j];
-        s1 += part[(p + 1024) * m + j];
+    for (; p + 3072 < nparts; p += 4096) {
+        const double a0 = part[p * m + j], a1 = part[(p + 1024) * m + j];
+        const double a2 = part[(p + 2048) * m + j], a3 = part[(p + 3072) * m + j];
+        s0 += a0;
+        s1 += a1;
+        s2 += a2;
+        s3 += a3;
     }
-    if (p < nparts) s0 += part[p * m + j];
-    red[threadIdx.x] = s0 + s1;
+    for (; p < nparts; p += 1024) s0 += part[p * m + j];
+    red[threadIdx.x] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     for (int off = 512; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];

@@ -4,7 +4,10 @@
 // values) to run the convergence test and the shift rules.
 //
 // Basis handling: S = [X W P] is kept orthonormal.  W is orthonormalised
-// against [X P] and itself by Cholesky-QR passes driven by Gram matrices;
+// against [X P] and itself by Cholesky-QR passes driven by Gram matrices; the
+// factor U of the last pass is not applied to W (the basis holds W U, with U
+// folded into the Rayleigh-Ritz problem and its W coefficients), which saves
+// a full pass over W;
 // after Rayleigh-Ritz the new P is built in coefficient space as an
 // orthonormal basis of the W,P-components of the new X made orthogonal to the
 // new X, so span{X_new, P_new} equals span{X_new, (I - X X^T) X_new} of step 10
@@ -222,10 +225,12 @@ struct Lobpcg {
         HIPCHK(hipGraphLaunch(ge, s));
     }
 
-    void rayleigh_ritz(int nblk) {
+    // wtrans: the second Cholesky-QR factor of W (coef), applied inside the
+    // Rayleigh-Ritz step instead of to W itself
+    void rayleigh_ritz(int nblk, const double *wtrans = nullptr) {
         RRArgs r{};
         r.gram = gbuf; r.coef = rrcoef; r.theta = st_d->theta; r.evals_all = nullptr;   // only the m lowest are needed
-        r.flag = &st_d->flags[1]; r.nblk = nblk; r.m = m;
+        r.flag = &st_d->flags[1]; r.nblk = nblk; r.m = m; r.wtrans = wtrans;
         small_rr(&r, 1, s);
     }
 
@@ -337,19 +342,18 @@ struct Lobpcg {
             GramArgs g2{};
             g2.a[0] = W; g2.b[0] = W; g2.na = g2.nb = 1; g2.m = m; g2.n = n;
             gram(g2, gbuf, gram_scr, s);
+            // second Cholesky-QR pass: its factor U (W_orth = W U) is not
+            // applied to W; the SpMM takes W as it is and the Rayleigh-Ritz
+            // step applies U to the Gram matrix and to the W coefficients
             OrthArgs o2{gbuf, coef, &st_d->flags[0], 0, m, 2};
             small_orth(&o2, 1, s);
-            LincombArgs l2{};
-            l2.in[0] = W; l2.out[0] = W; l2.coef = coef; l2.ldc = m; l2.nin = 1; l2.nout = 1; l2.nsets = 1;
-            l2.m = m; l2.n = n;
-            lincomb(l2, s);
             spmm(W, AW);
             const int nblk = have_p ? 3 : 2;
             GramArgs g{};
             g.a[0] = X; g.a[1] = W; g.a[2] = P; g.b[0] = AX; g.b[1] = AW; g.b[2] = AP;
             g.na = g.nb = nblk; g.m = m; g.n = n;
             gram(g, gbuf, gram_scr, s);
-            rayleigh_ritz(nblk);
+            rayleigh_ritz(nblk, coef);
             LincombArgs u{};
             u.in[0] = X; u.in[1] = W; u.in[2] = P; u.in[3] = AX; u.in[4] = AW; u.in[5] = AP;
             u.out[0] = X; u.out[1] = P; u.out[2] = AX; u.out[3] = AP;
@@ -419,7 +423,7 @@ struct BatchPlan {
     char *dev = nullptr, *pin = nullptr;
     size_t bytes = 0;
     GramJob *gA = nullptr, *gW = nullptr, *gS = nullptr;
-    LincombArgs *lcO = nullptr, *lcL2 = nullptr, *lcU = nullptr;
+    LincombArgs *lcO = nullptr, *lcU = nullptr;
     ColsumJob *cs = nullptr;
     SpmmJob *sp = nullptr;
     int **flag_ptr = nullptr;
@@ -457,7 +461,7 @@ struct BatchPlan {
                 return o;
             };
             const size_t oA = at(sizeof(GramJob)), oW = at(sizeof(GramJob)), oS = at(sizeof(GramJob));
-            const size_t oO = at(sizeof(LincombArgs)), o2 = at(sizeof(LincombArgs)), oU = at(sizeof(LincombArgs));
+            const size_t oO = at(sizeof(LincombArgs)), oU = at(sizeof(LincombArgs));
             const size_t oC = at(sizeof(ColsumJob)), oP = at(sizeof(SpmmJob)), oF = at(sizeof(int *));
             const size_t oR = at(sizeof(int *)), oT = at(sizeof(Status)), oJ = at(sizeof(JacobiJob));
             const size_t oM = at(sizeof(double) * HSYM_MAX_BLOCK);
@@ -465,14 +469,14 @@ struct BatchPlan {
             HIPCHK(hipMalloc((void **)&dev, bytes));
             HIPCHK(hipHostMalloc((void **)&pin, bytes, hipHostMallocDefault));
             gA = (GramJob *)(dev + oA); gW = (GramJob *)(dev + oW); gS = (GramJob *)(dev + oS);
-            lcO = (LincombArgs *)(dev + oO); lcL2 = (LincombArgs *)(dev + o2); lcU = (LincombArgs *)(dev + oU);
+            lcO = (LincombArgs *)(dev + oO); lcU = (LincombArgs *)(dev + oU);
             cs = (ColsumJob *)(dev + oC); sp = (SpmmJob *)(dev + oP); flag_ptr = (int **)(dev + oF);
             stat_src = (const int **)(dev + oR); stat_dst = (int *)(dev + oT); jac = (JacobiJob *)(dev + oJ);
             mu = (double *)(dev + oM);
         }
         auto host = [&](const void *d) { return pin + ((const char *)d - dev); };
         GramJob *hgA = (GramJob *)host(gA), *hgW = (GramJob *)host(gW), *hgS = (GramJob *)host(gS);
-        LincombArgs *hlO = (LincombArgs *)host(lcO), *hl2 = (LincombArgs *)host(lcL2), *hlU = (LincombArgs *)host(lcU);
+        LincombArgs *hlO = (LincombArgs *)host(lcO), *hlU = (LincombArgs *)host(lcU);
         ColsumJob *hcs = (ColsumJob *)host(cs);
         SpmmJob *hsp = (SpmmJob *)host(sp);
         int **hfl = (int **)host(flag_ptr);
@@ -506,10 +510,6 @@ struct BatchPlan {
             lo.in[0] = L.X; lo.in[1] = L.P; lo.in[2] = L.W; lo.out[0] = L.W; lo.coef = L.coef; lo.ldc = L.m;
             lo.nin = 3; lo.nout = 1; lo.nsets = 1; lo.m = L.m; lo.n = L.n;
             hlO[i] = lo;
-            LincombArgs l2{};
-            l2.in[0] = L.W; l2.out[0] = L.W; l2.coef = L.coef; l2.ldc = L.m; l2.nin = 1; l2.nout = 1; l2.nsets = 1;
-            l2.m = L.m; l2.n = L.n;
-            hl2[i] = l2;
             LincombArgs u{};
             u.in[0] = L.X; u.in[1] = L.W; u.in[2] = L.P; u.in[3] = L.AX; u.in[4] = L.AW; u.in[5] = L.AP;
             u.out[0] = L.X; u.out[1] = L.P; u.out[2] = L.AX; u.out[3] = L.AP;
@@ -526,7 +526,7 @@ struct BatchPlan {
             o2.push_back(OrthArgs{L.gbuf, L.coef, &L.st_d->flags[0], 0, L.m, 2});
             RRArgs r{};
             r.gram = L.gbuf; r.coef = L.rrcoef; r.theta = L.st_d->theta; r.evals_all = nullptr;
-            r.flag = &L.st_d->flags[1]; r.nblk = 3; r.m = L.m;
+            r.flag = &L.st_d->flags[1]; r.nblk = 3; r.m = L.m; r.wtrans = L.coef;
             rr.push_back(r);
         }
         // the static tables: everything before the per-round Jacobi jobs
@@ -601,7 +601,6 @@ struct BatchPlan {
             lincomb_batched(lcO, count, max_n, bs);
             gram_batched(gW, count, m, m, maxpW, bs);
             small_orth(o2.data(), count, bs);
-            lincomb_batched(lcL2, count, max_n, bs);
             spmm_batched(sp, sp_h.data(), count, m, storage, bs);
             gram_batched(gS, count, 3 * m, 3 * m, maxpS, bs);
             small_rr(rr.data(), count, bs);

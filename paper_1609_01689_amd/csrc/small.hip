@@ -21,11 +21,23 @@ struct Batch {
 __global__ __launch_bounds__(256) void k_small_orth(Batch<OrthArgs> b) {
     __shared__ double S[16][17], Li[16][17];
     __shared__ double dsc[16];
+    __shared__ double G[KMAX * 16];   // the Gram matrix, (KB + m) x m, staged from global memory
     __shared__ int bad;
     const OrthArgs a = b.a[blockIdx.x];
     const int m = a.m, kb = a.kb, KB = kb * m;
-    const double *G = a.gram;   // (KB + m) x m
     const int tid = threadIdx.x;
+    {
+        // all loads issued before any is used: the loops below read G in
+        // dependent chains, which would otherwise wait on global memory per step
+        const int cnt = (KB + m) * m;
+        double v[3];
+#pragma unroll
+        for (int t = 0; t < 3; t++) v[t] = tid + 256 * t < cnt ? a.gram[tid + 256 * t] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 3; t++)
+            if (tid + 256 * t < cnt) G[tid + 256 * t] = v[t];
+    }
+    __syncthreads();
     if (a.stage == 0) {
         if (tid < m) {
             const int j = tid;
@@ -84,7 +96,13 @@ __global__ __launch_bounds__(256) void k_small_orth(Batch<OrthArgs> b) {
         __syncthreads();
     }
     __syncthreads();
-    if (bad >= 0) return;
+    if (bad >= 0) {
+        // the block is already orthonormal to working accuracy after stage 1:
+        // a failed second pass leaves it as it is
+        if (a.stage == 2)
+            for (int e = tid; e < m * m; e += 256) a.coef[e] = (e / m == e % m) ? 1.0 : 0.0;
+        return;
+    }
     // Li = L^{-1}: column c by forward substitution, one thread per column
     if (tid < m) {
         const int c = tid;
@@ -339,17 +357,74 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
     __shared__ unsigned char piv[KMAX][17];
     __shared__ double Z[KMAX][17];
     __shared__ double G[16][17];
+    __shared__ double Us[16][17];             // the W transform of RRArgs::wtrans
     __shared__ double sh[40];
     __shared__ int bad, nrounds;
     const RRArgs a = b.a[blockIdx.x];
     const int m = a.m, k = a.nblk * m;
     const int tid = threadIdx.x, lane = tid & 63;
+    {
+        // all loads in flight together, then the average of the two triangles
+        double v[9];
+#pragma unroll
+        for (int t = 0; t < 9; t++) v[t] = tid + 256 * t < k * k ? a.gram[tid + 256 * t] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 9; t++) {
+            const int e0 = tid + 256 * t;
+            if (e0 < k * k) {
+                const int i = e0 / k, j = e0 - (e0 / k) * k;
+                A[i][j] = v[t];
+            }
+        }
+    }
+    __syncthreads();
     for (int e0 = tid; e0 < k * k; e0 += 256) {
         const int i = e0 / k, j = e0 - (e0 / k) * k;
-        A[i][j] = 0.5 * (a.gram[i * k + j] + a.gram[j * k + i]);
+        if (i < j) {
+            const double v = 0.5 * (A[i][j] + A[j][i]);
+            A[i][j] = v;
+            A[j][i] = v;
+        }
     }
     if (tid == 0) { bad = 0; nrounds = 0; }
+    const bool wt = a.wtrans != nullptr;
+    if (wt && tid < m * m) Us[tid / m][tid % m] = a.wtrans[tid];   // staged: read in dependent chains below
     __syncthreads();
+    if (wt) {
+        // A <- T^T A T, T = diag(I, U, I) on the W block (rows and columns
+        // m .. 2m).  With Z = A T restricted to the W columns, the new W
+        // columns are Z, the new W rows are Z^T (A is symmetric, so both come
+        // from the same sums), and the W x W block is U^T Z_W, formed for
+        // c <= d and mirrored: A stays exactly symmetric.
+        for (int e0 = tid; e0 < k * m; e0 += 256) {
+            const int i = e0 / m, c = e0 - (e0 / m) * m;
+            double v = 0.0;
+            for (int q = 0; q < m; q++) v = fma(A[i][m + q], Us[q][c], v);
+            Z[i][c] = v;
+        }
+        __syncthreads();
+        {
+            const int c = tid >> 4, d = tid & 15;
+            if (c < m && d < m && c <= d) {
+                double v = 0.0;
+                for (int q = 0; q < m; q++) v = fma(Us[q][c], Z[m + q][d], v);
+                Y[c][d] = v;
+            }
+        }
+        __syncthreads();
+        for (int e0 = tid; e0 < k * m; e0 += 256) {
+            const int i = e0 / m, c = e0 - (e0 / m) * m;
+            if (i >= m && i < 2 * m) {
+                const int d = i - m;
+                const double v = c <= d ? Y[c][d] : Y[d][c];
+                A[i][m + c] = v;
+            } else {
+                A[i][m + c] = Z[i][c];
+                A[m + c][i] = Z[i][c];
+            }
+        }
+        __syncthreads();
+    }
     // 1. tridiagonalisation; the arithmetic deciding each reflector is
     // repeated identically in every wave, so no broadcast is needed
     {
@@ -543,9 +618,15 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
     }
     __syncthreads();
     if (tid == 0) a.flag[0] = bad ? -1 : 1 + nrounds;
+    // coefficients of the basis as stored: the W rows premultiplied by U
     for (int e0 = tid; e0 < k * m; e0 += 256) {
         const int i = e0 / m, j = e0 - (e0 / m) * m;
-        a.coef[i * 2 * m + j] = Y[i][j];
+        double v = Y[i][j];
+        if (wt && i >= m && i < 2 * m) {
+            v = 0.0;
+            for (int c = 0; c < m; c++) v = fma(Us[i - m][c], Y[m + c][j], v);
+        }
+        a.coef[i * 2 * m + j] = v;
     }
     // Next search direction in coefficient space: the W,P-components of C_X,
     // made orthogonal to C_X and orthonormal (span{C_X, C_P} = span{C_X, Y}
@@ -627,7 +708,12 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
     }
     for (int e0 = tid; e0 < k * m; e0 += 256) {
         const int i = e0 / m, j = e0 - (e0 / m) * m;
-        a.coef[i * 2 * m + m + j] = Z[i][j];
+        double v = Z[i][j];
+        if (wt && i >= m && i < 2 * m) {
+            v = 0.0;
+            for (int c = 0; c < m; c++) v = fma(Us[i - m][c], Z[m + c][j], v);
+        }
+        a.coef[i * 2 * m + m + j] = v;
     }
 }
 
