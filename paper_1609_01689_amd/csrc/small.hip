@@ -18,6 +18,36 @@ struct Batch {
     int count;
 };
 
+// Cross-lane moves of a double through DPP (no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+// Sums over a quad / a row of 16 lanes / the wave.  Every lane receives the
+// bitwise identical sum (each butterfly step adds the same two operands, in
+// either order).  Called with the whole wave active.
+__device__ __forceinline__ double quad_sum(double v) {
+    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    return v;
+}
+__device__ __forceinline__ double row_sum(double v) {
+    v = quad_sum(v);
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+    v = row_sum(v);
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
 __global__ __launch_bounds__(256) void k_small_orth(Batch<OrthArgs> b) {
     __shared__ double S[16][17], Li[16][17];
     __shared__ double dsc[16];
@@ -25,7 +55,7 @@ __global__ __launch_bounds__(256) void k_small_orth(Batch<OrthArgs> b) {
     __shared__ int bad;
     const OrthArgs a = b.a[blockIdx.x];
     const int m = a.m, kb = a.kb, KB = kb * m;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     {
         // all loads issued before any is used: the loops below read G in
         // dependent chains, which would otherwise wait on global memory per step
@@ -62,38 +92,54 @@ __global__ __launch_bounds__(256) void k_small_orth(Batch<OrthArgs> b) {
         return;
     }
     // stages 1 and 2: M = S - G_B^T G_B, Cholesky, coefficients [-G_B L^-T; L^-T]
-    for (int e = tid; e < m * m; e += 256) {
-        int i = e / m, j = e - (e / m) * m;
-        double v = 0.5 * (G[(KB + i) * m + j] + G[(KB + j) * m + i]);
-        for (int k = 0; k < KB; k++) v -= G[k * m + i] * G[k * m + j];
+    // (M is padded to 16 x 16 with the identity, as in wg_cholqr)
+    {
+        const int i = tid >> 4, j = tid & 15;
+        double v = i == j ? 1.0 : 0.0;
+        if (i < m && j < m) {
+            v = 0.5 * (G[(KB + i) * m + j] + G[(KB + j) * m + i]);
+            for (int k = 0; k < KB; k++) v -= G[k * m + i] * G[k * m + j];
+        }
         S[i][j] = v;
     }
-    if (tid == 0) bad = -1;
     __syncthreads();
-    // right-looking Cholesky S = L L^T, in place in the lower triangle
-    double dmax = 0.0;
-    for (int j = 0; j < m; j++) dmax = fmax(dmax, fabs(S[j][j]));
-    for (int j = 0; j < m; j++) {
-        const double d = S[j][j];
-        if (!(d > 1e-14 * dmax) || !isfinite(d)) {
-            if (tid == 0) {
-                bad = j;
+    // Cholesky M = L L^T by the first wave, rows in registers (lane r & 15 holds
+    // row r), column entries broadcast with readlane; the first pivot that is
+    // not clearly positive marks itself and the columns after it deficient
+    if (wave == 0) {
+        const int r = lane & 15;
+        double g[16], dmax = 0.0;
+#pragma unroll
+        for (int c = 0; c < 16; c++) {
+            g[c] = c <= r ? S[r][c] : 0.0;
+            dmax = c < m ? fmax(dmax, fabs(S[c][c])) : dmax;
+        }
+        int badj = -1;
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const double pj = read_lane(g[j], j);
+            if (j < m && badj < 0 && (!(pj > 1e-14 * dmax) || !isfinite(pj))) badj = j;
+            const double dj = sqrt(fmax(pj, 1e-300));
+            const double rj = 1.0 / dj;
+            const double l = (r == j) ? dj : g[j] * rj;
+            g[j] = l;
+#pragma unroll
+            for (int c = j + 1; c < 16; c++) g[c] = fma(-l, read_lane(l, c), g[c]);
+            if (lane == j) dsc[j] = rj;   // reciprocal pivots for the inverse below
+        }
+        if (lane < 16) {
+#pragma unroll
+            for (int c = 0; c < 16; c++)
+                if (c <= lane) S[lane][c] = g[c];
+        }
+        if (lane == 0) {
+            bad = badj;
+            if (badj >= 0) {
                 int mask = 0;
-                for (int jj = j; jj < m; jj++) mask |= 1 << jj;
+                for (int jj = badj; jj < m; jj++) mask |= 1 << jj;
                 atomicOr(a.flag, mask);
             }
-            break;
         }
-        const double sd = sqrt(d);
-        __syncthreads();
-        if (tid < m && tid > j) S[tid][j] /= sd;
-        if (tid == 0) S[j][j] = sd;
-        __syncthreads();
-        for (int e = tid; e < m * m; e += 256) {
-            const int i = e / m, l = e - (e / m) * m;
-            if (l > j && i >= l) S[i][l] -= S[i][j] * S[l][j];
-        }
-        __syncthreads();
     }
     __syncthreads();
     if (bad >= 0) {
@@ -107,11 +153,11 @@ __global__ __launch_bounds__(256) void k_small_orth(Batch<OrthArgs> b) {
     if (tid < m) {
         const int c = tid;
         for (int i = 0; i < c; i++) Li[i][c] = 0.0;
-        Li[c][c] = 1.0 / S[c][c];
+        Li[c][c] = dsc[c];
         for (int i = c + 1; i < m; i++) {
             double v = 0.0;
             for (int l = c; l < i; l++) v += S[i][l] * Li[l][c];
-            Li[i][c] = -v / S[i][i];
+            Li[i][c] = -v * dsc[i];
         }
     }
     __syncthreads();
@@ -154,36 +200,6 @@ void small_orth(const OrthArgs *a, int count, hipStream_t s) {
 //      by one more solve and orthogonalised again;
 //   4. back-transformation C_X = Q Y, 16 lanes per vector.
 // ---------------------------------------------------------------------------
-// Cross-lane moves of a double through DPP (no LDS round trip).
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double read_lane(double v, int l) {
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                            __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-// Sums over a quad / a row of 16 lanes / the wave.  Every lane receives the
-// bitwise identical sum (each butterfly step adds the same two operands, in
-// either order).  Called with the whole wave active.
-__device__ __forceinline__ double quad_sum(double v) {
-    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
-    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
-    return v;
-}
-__device__ __forceinline__ double row_sum(double v) {
-    v = quad_sum(v);
-    v += dpp_mov<0x141>(v);   // row_half_mirror
-    v += dpp_mov<0x140>(v);   // row_mirror
-    return v;
-}
-__device__ __forceinline__ double wave_sum(double v) {
-    v = row_sum(v);
-    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
-}
-
 // Number of eigenvalues of the (scaled, |d|, |e| <= 1) tridiagonal T below x:
 // the number of negative pivots q_i = p_i / p_{i-1} of the LDL^T
 // factorisation of T - xI, carried division-free as the pair (p_i, p_{i-1})
@@ -256,48 +272,49 @@ __device__ void inv_iter(int c, int k, int nit, const double (*Fd)[17], const do
 // factorisation (the squared sine of the smallest angle between a column and
 // the span of the ones before it, plus shift) in sh[32].  sh holds >= 33
 // doubles, G >= 16 x 17.
+// The factorisation always runs on 16 x 16: columns m .. 15 are padded with
+// the identity (their pivots are 1 + shift and they do not touch the leading
+// m x m factor), so the unrolled code has no data-dependent branches.
 __device__ void wg_cholqr(double (*V)[17], int k, int m, double shift, double (*G)[17], double *sh) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     {
         const int q = tid >> 4, c = tid & 15;
-        if (q < m && c <= q) {
-            double s = 0.0;
+        if (c <= q) {
+            double s = q == c ? 1.0 : 0.0;
+            if (q < m) {
+                s = 0.0;
 #pragma unroll 8
-            for (int i = 0; i < k; i++) s = fma(V[i][q], V[i][c], s);
+                for (int i = 0; i < k; i++) s = fma(V[i][q], V[i][c], s);
+            }
             G[q][c] = s;
         }
     }
     __syncthreads();
     if (wave == 0) {
-        const double gd = lane < m ? G[lane][lane] : 0.0;
+        const int r = lane & 15;   // lanes 16 .. 63 repeat rows 0 .. 15 (their results are not stored)
+        const double gd = G[r][r];
         const double sc = gd > 0.0 ? 1.0 / sqrt(gd) : 0.0;
         double g[16];
 #pragma unroll
         for (int c = 0; c < 16; c++) {
             const double scc = read_lane(sc, c);
-            g[c] = (lane < m && c < m && c <= lane) ? G[lane][c] * sc * scc + (c == lane ? shift : 0.0) : 0.0;
+            g[c] = c <= r ? G[r][c] * sc * scc + (c == r ? shift : 0.0) : 0.0;
         }
         double minp = 1e300;
 #pragma unroll
         for (int j = 0; j < 16; j++) {
-            if (j < m) {
-                const double pj = read_lane(g[j], j);
-                minp = fmin(minp, pj);
-                const double dj = sqrt(fmax(pj, 1e-300));
-                const double rj = 1.0 / dj;
-                const double l = (lane == j) ? dj : g[j] * rj;
-                g[j] = l;
+            const double pj = read_lane(g[j], j);
+            minp = j < m ? fmin(minp, pj) : minp;
+            const double dj = sqrt(fmax(pj, 1e-300));
+            const double rj = 1.0 / dj;
+            // column j of L; entries above the diagonal (lanes < j) are never read
+            const double l = (r == j) ? dj : g[j] * rj;
+            g[j] = l;
 #pragma unroll
-                for (int c = j + 1; c < 16; c++) {
-                    if (c < m) {
-                        const double lc = read_lane(l, c);
-                        if (lane >= c) g[c] = fma(-l, lc, g[c]);
-                    }
-                }
-                if (lane == j) sh[j] = rj;
-            }
+            for (int c = j + 1; c < 16; c++) g[c] = fma(-l, read_lane(l, c), g[c]);
+            if (lane == j) sh[j] = rj;
         }
-        if (lane < m) {
+        if (lane < 16) {
 #pragma unroll
             for (int c = 0; c < 16; c++)
                 if (c <= lane) G[lane][c] = g[c];
@@ -310,12 +327,10 @@ __device__ void wg_cholqr(double (*V)[17], int k, int m, double shift, double (*
         double x[16];
 #pragma unroll
         for (int c = 0; c < 16; c++) {
-            if (c < m) {
-                double v = V[tid][c] * sh[16 + c];
+            double v = c < m ? V[tid][c] * sh[16 + c] : 0.0;
 #pragma unroll
-                for (int q = 0; q < c; q++) v = fma(-x[q], G[c][q], v);
-                x[c] = v * sh[c];
-            }
+            for (int q = 0; q < c; q++) v = fma(-x[q], G[c][q], v);
+            x[c] = v * sh[c];
         }
 #pragma unroll
         for (int c = 0; c < 16; c++)
