@@ -207,28 +207,26 @@ void small_orth(const OrthArgs *a, int count, hipStream_t s) {
 // rescaled by a power of two every 4 steps.  A pivot of magnitude below PIV
 // is replaced by -PIV (the LAPACK bisection convention), which also keeps
 // every p_i nonzero and each step's growth within 2^62.
-__device__ __forceinline__ int sturm_count(const double *d, const double *e2, int k, double x) {
+// d is held in registers (KMAX entries; padded past k with d = 4, e^2 = 0,
+// steps that keep the sign, since x lies in [-1.01, 1.01]); e^2 is read from
+// LDS as a broadcast.
+__device__ __forceinline__ int sturm_count_r(const double (&d)[KMAX], const double *e2, double x) {
     constexpr double PIV = 0x1p-60;
     double p = d[0] - x, q = 1.0;
     if (fabs(p) < PIV) p = -PIV;
     int n = p < 0.0;
-    // steps 1 .. k-1 in chunks of 4; the arrays are padded past k with
-    // d = 4, e^2 = 0, steps that keep the sign (x lies in [-1.01, 1.01])
-    for (int i0 = 1; i0 < k; i0 += 4) {
-        double dd[4], ee[4];
 #pragma unroll
-        for (int t = 0; t < 4; t++) { dd[t] = d[i0 + t]; ee[t] = e2[i0 + t - 1]; }
-#pragma unroll
-        for (int t = 0; t < 4; t++) {
-            double tt = fma(dd[t] - x, p, -ee[t] * q);
-            if (fabs(tt) < PIV * fabs(p)) tt = -PIV * p;
-            n += (tt < 0.0) != (p < 0.0);
-            q = p;
-            p = tt;
+    for (int i = 1; i < KMAX; i++) {
+        double tt = fma(d[i] - x, p, -e2[i - 1] * q);
+        if (fabs(tt) < PIV * fabs(p)) tt = -PIV * p;
+        n += (tt < 0.0) != (p < 0.0);
+        q = p;
+        p = tt;
+        if (i % 4 == 0 || i == KMAX - 1) {
+            const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(p), fabs(q)));
+            p = __builtin_amdgcn_ldexp(p, -ex);
+            q = __builtin_amdgcn_ldexp(q, -ex);
         }
-        const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(p), fabs(q)));
-        p = __builtin_amdgcn_ldexp(p, -ex);
-        q = __builtin_amdgcn_ldexp(q, -ex);
     }
     return n;
 }
@@ -275,7 +273,7 @@ __device__ void inv_iter(int c, int k, int nit, const double (*Fd)[17], const do
 // The factorisation always runs on 16 x 16: columns m .. 15 are padded with
 // the identity (their pivots are 1 + shift and they do not touch the leading
 // m x m factor), so the unrolled code has no data-dependent branches.
-__device__ void wg_cholqr(double (*V)[17], int k, int m, double shift, double (*G)[17], double *sh) {
+__device__ __forceinline__ void wg_cholqr(double (*V)[17], int k, int m, double shift, double (*G)[17], double *sh) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     {
         const int q = tid >> 4, c = tid & 15;
@@ -534,10 +532,13 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
         lo -= 1e-12 * w0 + 1e-300;
         hi += 1e-12 * w0 + 1e-300;
         const bool act = g < ne;
+        double dr[KMAX];
+#pragma unroll
+        for (int i = 0; i < KMAX; i++) dr[i] = ds[i];
         for (int round = 0; round < 64; round++) {
             const double h = (hi - lo) / (double)(NG + 1);
             const double x = fma((double)(lg + 1), h, lo);
-            const int cnt = act ? sturm_count(ds, e2s, k, x) : 0;
+            const int cnt = act ? sturm_count_r(dr, e2s, x) : 0;
             const unsigned long long bal = __ballot(act && cnt > g);
             const unsigned long long msk = (bal >> gbase) & gmask;
             if (msk == 0ull) {
