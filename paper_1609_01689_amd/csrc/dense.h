@@ -105,6 +105,15 @@ struct GramJob {
 void gram_batched(const GramJob *jobs, int count, int K1, int K2, int max_parts, hipStream_t s);
 // every table entry passes the shape checks of lincomb()
 void lincomb_batched(const LincombArgs *tab, int count, int64_t max_n, hipStream_t s);
+// W' = lincomb l (one set, one output W') followed by out = g (the Gram
+// [A_0 .. W']^T W', with W' the last A block and the only B block), fused into
+// one pass over the rows when m = 16, else the two calls
+bool lincomb_gram_fusable(const LincombArgs &l, const GramArgs &g);
+int64_t lincomb_gram_rows(int64_t n, int parts);   // rows per workgroup of the fused pass
+void lincomb_gram(const LincombArgs &l, const GramArgs &g, double *out, double *scratch, hipStream_t s);
+// batched fused form (all fusable, K1 = na * 16, GramJob::rpw = lincomb_gram_rows)
+void lincomb_gram_batched(const LincombArgs *lt, const GramJob *gt, int count, int na, int max_parts,
+                          hipStream_t s);
 struct ColsumJob {
     const double *part;
     int64_t nparts;

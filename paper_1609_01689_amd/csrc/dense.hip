@@ -301,6 +301,146 @@ void lincomb(const LincombArgs &a, hipStream_t s) {
 
 int64_t lincomb_norm_parts(int64_t n) { return (n + 63) / 64; }
 
+// ---------------------------------------------------------------------------
+// Linear combination with a Gram epilogue (m = 16): W' = [in] C (one set, one
+// output) and the partial Gram matrices [A_0 .. A_{NA-2} W']^T W' of the rows
+// the workgroup produced, so the Cholesky-QR pass that follows reads neither
+// W' nor the A blocks again.  A workgroup walks rows_per_wg rows (a multiple
+// of 64) in 64-row tiles, 16 rows per wave.  The accumulator of the linear
+// combination holds W'[row lk + 4v][column li], which is exactly the operand
+// layout of v_mfma_f64_16x16x4f64 for the Gram over the rows 4v .. 4v + 3;
+// the A blocks are read again in that layout (rows the wave has just loaded,
+// from cache).  Partials are laid out as those of k_gram_partial.
+// ---------------------------------------------------------------------------
+template <int NA>
+__device__ __forceinline__ void lincomb_gram_body(const LincombArgs &l, const GramArgs &g, double *__restrict__ part,
+                                                  int64_t rows_per_wg, int64_t bx) {
+    __shared__ double red[4][NA * 16][17];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nin = l.nin;
+    // coefficients: loop-invariant MFMA B operands
+    double bv[3][4];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; s4++)
+            bv[i][s4] = i < nin ? l.coef[(i * 16 + 4 * s4 + lk) * l.ldc + li] : 0.0;
+    double4_t G[NA];
+#pragma unroll
+    for (int t = 0; t < NA; t++) G[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    const int64_t r_begin = bx * rows_per_wg;
+    const int64_t r_end = (r_begin + rows_per_wg < l.n) ? r_begin + rows_per_wg : l.n;
+    for (int64_t w0 = r_begin + 16 * wave; w0 < r_end; w0 += 64) {
+        const int64_t ra = w0 + li;
+        const bool rok = ra < r_end;
+        double av[3][4];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int s4 = 0; s4 < 4; s4++)
+                av[i][s4] = (i < nin && rok) ? l.in[i][ra * 16 + 4 * s4 + lk] : 0.0;
+        // the A blocks in the Gram layout (row w0 + lk + 4v, column li)
+        double ax[NA > 1 ? NA - 1 : 1][4];
+#pragma unroll
+        for (int t = 0; t < NA - 1; t++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int64_t r = w0 + lk + 4 * v;
+                ax[t][v] = r < r_end ? g.a[t][r * 16 + li] : 0.0;
+            }
+        double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            if (i >= nin) break;
+#pragma unroll
+            for (int s4 = 0; s4 < 4; s4++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s4], bv[i][s4], acc, 0, 0, 0);
+        }
+        double *dst = l.out[0];
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int64_t r = w0 + lk + 4 * v;
+            if (r < r_end) dst[r * 16 + li] = acc[v];
+        }
+        // rows past r_end carry zero inputs, hence zero acc: they add nothing
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+#pragma unroll
+            for (int t = 0; t < NA - 1; t++) G[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[t][v], acc[v], G[t], 0, 0, 0);
+            G[NA - 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[v], acc[v], G[NA - 1], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NA; t++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) red[wave][16 * t + lk + 4 * v][li] = G[t][v];
+    __syncthreads();
+    double *out = part + bx * (NA * 16) * 16;
+    for (int e = tid; e < NA * 16 * 16; e += 256) {
+        const int i = e >> 4, j = e & 15;
+        out[e] = red[0][i][j] + red[1][i][j] + red[2][i][j] + red[3][i][j];
+    }
+}
+
+template <int NA>
+__global__ __launch_bounds__(256) void k_lincomb_gram(LincombArgs l, GramArgs g, double *__restrict__ part,
+                                                      int64_t rows_per_wg) {
+    lincomb_gram_body<NA>(l, g, part, rows_per_wg, blockIdx.x);
+}
+
+template <int NA>
+__global__ __launch_bounds__(256) void k_lincomb_gram_b(const LincombArgs *__restrict__ lt,
+                                                        const GramJob *__restrict__ gt) {
+    const GramJob j = gt[blockIdx.y];
+    if ((int)blockIdx.x >= j.parts) return;
+    const LincombArgs l = lt[blockIdx.y];
+    lincomb_gram_body<NA>(l, j.g, j.part, j.rpw, blockIdx.x);
+}
+
+bool lincomb_gram_fusable(const LincombArgs &l, const GramArgs &g) {
+    return l.m == 16 && g.m == 16 && l.nsets == 1 && l.nout == 1 && !l.theta && l.nin >= 1 && l.nin <= 3 &&
+           l.ldc == 16 && g.nb == 1 && g.na >= 1 && g.na <= 3 && g.b[0] == l.out[0] && g.a[g.na - 1] == l.out[0] &&
+           l.n == g.n;
+}
+
+int64_t lincomb_gram_rows(int64_t n, int parts) {
+    int64_t rpw = (n + parts - 1) / parts;
+    return (rpw + 63) / 64 * 64;
+}
+
+void lincomb_gram(const LincombArgs &l, const GramArgs &g, double *out, double *scratch, hipStream_t s) {
+    if (!lincomb_gram_fusable(l, g)) {
+        lincomb(l, s);
+        gram(g, out, scratch, s);
+        return;
+    }
+    const int parts = gram_parts(g.n);
+    const int64_t rpw = lincomb_gram_rows(g.n, parts);
+    switch (g.na) {
+        case 1: hipLaunchKernelGGL(k_lincomb_gram<1>, dim3(parts), dim3(256), 0, s, l, g, scratch, rpw); break;
+        case 2: hipLaunchKernelGGL(k_lincomb_gram<2>, dim3(parts), dim3(256), 0, s, l, g, scratch, rpw); break;
+        default: hipLaunchKernelGGL(k_lincomb_gram<3>, dim3(parts), dim3(256), 0, s, l, g, scratch, rpw); break;
+    }
+    HIPCHK(hipGetLastError());
+    const int kk = g.na * 16 * 16;
+    hipLaunchKernelGGL(k_gram_final, dim3((kk + 63) / 64), dim3(1024), 0, s, scratch, parts, kk, out);
+    HIPCHK(hipGetLastError());
+}
+
+void lincomb_gram_batched(const LincombArgs *lt, const GramJob *gt, int count, int na, int max_parts,
+                          hipStream_t s) {
+    const dim3 grid((unsigned)max_parts, (unsigned)count);
+    switch (na) {
+        case 1: hipLaunchKernelGGL(k_lincomb_gram_b<1>, grid, dim3(256), 0, s, lt, gt); break;
+        case 2: hipLaunchKernelGGL(k_lincomb_gram_b<2>, grid, dim3(256), 0, s, lt, gt); break;
+        default: hipLaunchKernelGGL(k_lincomb_gram_b<3>, grid, dim3(256), 0, s, lt, gt); break;
+    }
+    HIPCHK(hipGetLastError());
+    const int kk = na * 16 * 16;
+    hipLaunchKernelGGL(k_gram_final_b, dim3((unsigned)((kk + 63) / 64), (unsigned)count), dim3(1024), 0, s, gt);
+    HIPCHK(hipGetLastError());
+}
+
 // sum of per-workgroup partial column sums: one 1024-thread workgroup per
 // column, strided partial sums combined by a fixed tree (bitwise reproducible)
 __device__ __forceinline__ void colsum_body(const double *__restrict__ part, int64_t nparts, int m,

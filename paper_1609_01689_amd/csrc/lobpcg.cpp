@@ -291,8 +291,7 @@ struct Lobpcg {
         for (int i = 0; i < kb; i++) orth_lc.in[i] = B[i];
         orth_lc.in[kb] = W; orth_lc.out[0] = W; orth_lc.coef = coef; orth_lc.ldc = m; orth_lc.nin = kb + 1;
         orth_lc.nout = 1; orth_lc.nsets = 1; orth_lc.m = m; orth_lc.n = n;
-        lincomb(orth_lc, s);
-        gram(g, gbuf, gram_scr, s);
+        lincomb_gram(orth_lc, g, gbuf, gram_scr, s);   // the update and the next pass's Gram
         oa.stage = 1;
         small_orth(&oa, 1, s);
         HIPCHK(hipMemcpyAsync(&st_h->flags[0], &st_d->flags[0], sizeof(int), hipMemcpyDeviceToHost, s));
@@ -338,10 +337,9 @@ struct Lobpcg {
             return false;
         }
         auto body = [&] {
-            lincomb(orth_lc, s);
             GramArgs g2{};
             g2.a[0] = W; g2.b[0] = W; g2.na = g2.nb = 1; g2.m = m; g2.n = n;
-            gram(g2, gbuf, gram_scr, s);
+            lincomb_gram(orth_lc, g2, gbuf, gram_scr, s);
             // second Cholesky-QR pass: its factor U (W_orth = W U) is not
             // applied to W; the SpMM takes W as it is and the Rayleigh-Ritz
             // step applies U to the Gram matrix and to the W coefficients
@@ -492,7 +490,8 @@ struct BatchPlan {
             j.g.na = na; j.g.nb = nb; j.g.m = L.m; j.g.n = L.n;
             j.parts = gram_parts(L.n);
             int64_t rpw = (L.n + j.parts - 1) / j.parts;
-            j.rpw = (rpw + 3) / 4 * 4;
+            // m = 16: rows per partial shared with the fused update + Gram pass
+            j.rpw = L.m == 16 ? lincomb_gram_rows(L.n, j.parts) : (rpw + 3) / 4 * 4;
             j.part = L.gram_scr;
             j.kk = na * L.m * nb * L.m;
             j.out = L.gbuf;
@@ -581,8 +580,12 @@ struct BatchPlan {
             set_ints(flag_ptr, count, 0, bs);
             gram_batched(gA, count, 3 * m, m, maxpA, bs);
             small_orth(o0.data(), count, bs);
-            lincomb_batched(lcO, count, max_n, bs);
-            gram_batched(gA, count, 3 * m, m, maxpA, bs);
+            if (m == 16) {
+                lincomb_gram_batched(lcO, gA, count, 3, maxpA, bs);
+            } else {
+                lincomb_batched(lcO, count, max_n, bs);
+                gram_batched(gA, count, 3 * m, m, maxpA, bs);
+            }
             small_orth(o1.data(), count, bs);
             gather_words(stat_src, stat_dst, (int)(sizeof(Status) / 4), count, bs);
             Status *hst = (Status *)(pin + ((char *)stat_dst - dev));
@@ -598,8 +601,12 @@ struct BatchPlan {
                 }
             }
             // ---- phase B: second stage, SpMM, Rayleigh-Ritz, update ----
-            lincomb_batched(lcO, count, max_n, bs);
-            gram_batched(gW, count, m, m, maxpW, bs);
+            if (m == 16) {
+                lincomb_gram_batched(lcO, gW, count, 1, maxpW, bs);
+            } else {
+                lincomb_batched(lcO, count, max_n, bs);
+                gram_batched(gW, count, m, m, maxpW, bs);
+            }
             small_orth(o2.data(), count, bs);
             spmm_batched(sp, sp_h.data(), count, m, storage, bs);
             gram_batched(gS, count, 3 * m, 3 * m, maxpS, bs);
