@@ -28,10 +28,18 @@ struct LincombArgs {
     double *norm_part;     // lincomb_norm_parts(n) x m
 };
 void lincomb(const LincombArgs &a, hipStream_t s);
-int64_t lincomb_norm_parts(int64_t n);
+// workgroups of a linear combination over n rows (also its residual-norm
+// partials): at most 1024, each over lincomb_tiles_per_wg(n) tiles of 64 rows
+__host__ __device__ inline int64_t lincomb_tiles_per_wg(int64_t n) {
+    const int64_t nt = (n + 63) / 64;
+    const int64_t wgs = nt < 1024 ? nt : 1024;
+    return wgs > 0 ? (nt + wgs - 1) / wgs : 1;
+}
+__host__ __device__ inline int64_t lincomb_norm_parts(int64_t n) {
+    const int64_t tpw = lincomb_tiles_per_wg(n);
+    return ((n + 63) / 64 + tpw - 1) / tpw;
+}
 void colsum_final(const double *part, int64_t nparts, int m, double *out, hipStream_t s);
-void residual(const double *X, const double *AX, const double *theta, double *R, double *norm_part, int64_t n,
-              int m, hipStream_t s);
 void precond_apply(hsym_matrix *H, int kind, double *W, const double *mu, double delta, int m, hipStream_t s,
                    int fom_iters = 3);
 void to_f32(const double *x, float *y, int64_t cnt, hipStream_t s);

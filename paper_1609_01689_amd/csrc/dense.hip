@@ -185,40 +185,19 @@ void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s) {
 // and its product AX (set 1, output 0), writes it to `res` and accumulates the
 // squared column norms of R per workgroup.
 // ---------------------------------------------------------------------------
-// One workgroup (4 waves) per tile of 64 rows.  The coefficient matrix and
-// the input rows of one set are staged in LDS (rows padded to 17 doubles so
-// the 16 rows an MFMA operand reads fall in distinct banks); each wave forms
-// 16 output rows x 16 columns per v_mfma_f64_16x16x4f64 chain.
-// Each wave computes 16 rows: the MFMA A operands (lane: row li, columns
-// lk, lk+4, ...) are loaded straight from the input blocks and the B operands
-// (coefficients, a few KB read by every wave, cache resident) straight from
-// the coefficient matrix, so the kernel streams with no LDS staging and no
-// barrier until the fixed-order reduction of the residual norms.
+// A workgroup (4 waves) walks lincomb_tiles_per_wg(n) consecutive tiles of 64
+// rows, at most 1024 workgroups in all; each wave computes 16 rows of a tile.
+// The MFMA A operands (lane: row li, columns lk, lk+4, ...) are loaded
+// straight from the input blocks and the B operands (coefficients, a few KB,
+// cache resident) once per workgroup, so the kernel streams with no LDS
+// staging and no barrier until the fixed-order reduction of the residual norms.
 __device__ __forceinline__ void lincomb_body(const LincombArgs &a, int64_t bx) {
     __shared__ double nred[4][4][16];
     const int m = a.m, nin = a.nin, nout = a.nout;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int64_t w0 = bx * 64 + 16 * wave;   // this wave's 16 rows
-    const int64_t ra = w0 + li;                                   // row of this lane's A values
-    const bool rok = ra < a.n;
-    double4_t xkeep = (double4_t){0.0, 0.0, 0.0, 0.0};
-    double nrm = 0.0;
-    // every input value of this wave's 16 rows (both sets) and every
-    // coefficient it needs are loaded before the first store: a wave reads and
-    // writes only its own rows, so outputs may alias inputs, and all the loads
-    // are in flight together
-    double av[2][3][4], bv[2][3][4];
-#pragma unroll
-    for (int set = 0; set < 2; set++)
-#pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int s4 = 0; s4 < 4; s4++) {
-                const int kk = 4 * s4 + lk;
-                av[set][i][s4] =
-                    (set < a.nsets && i < nin && rok && kk < m) ? a.in[set * 3 + i][ra * m + kk] : 0.0;
-            }
+    // every coefficient this lane needs (MFMA B operands), loop-invariant
+    double bv[2][3][4];
 #pragma unroll
     for (int q = 0; q < 2; q++)
 #pragma unroll
@@ -229,41 +208,64 @@ __device__ __forceinline__ void lincomb_body(const LincombArgs &a, int64_t bx) {
                 bv[q][i][s4] = (q < nout && i < nin && kk < m && li < m)
                                    ? a.coef[(i * m + kk) * a.ldc + q * m + li] : 0.0;
             }
+    double nrm = 0.0;
+    const int64_t ntiles = (a.n + 63) / 64, tpw = lincomb_tiles_per_wg(a.n);
+    const int64_t t_end = (bx + 1) * tpw < ntiles ? (bx + 1) * tpw : ntiles;
+    for (int64_t t = bx * tpw; t < t_end; t++) {
+        const int64_t w0 = t * 64 + 16 * wave;   // this wave's 16 rows
+        const int64_t ra = w0 + li;              // row of this lane's A values
+        const bool rok = ra < a.n;
+        double4_t xkeep = (double4_t){0.0, 0.0, 0.0, 0.0};
+        // every input value of this wave's 16 rows (both sets) is loaded
+        // before the first store: a wave reads and writes only its own rows,
+        // so outputs may alias inputs, and all the loads are in flight together
+        double av[2][3][4];
 #pragma unroll
-    for (int set = 0; set < 2; set++) {
-        if (set >= a.nsets) break;
+        for (int set = 0; set < 2; set++)
 #pragma unroll
-        for (int q = 0; q < 2; q++) {
-            if (q >= nout) break;
-            double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int i = 0; i < 3; i++) {
-                if (i >= nin) break;
+            for (int i = 0; i < 3; i++)
 #pragma unroll
                 for (int s4 = 0; s4 < 4; s4++) {
-                    if (4 * s4 >= m) break;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[set][i][s4], bv[q][i][s4], acc, 0, 0, 0);
+                    const int kk = 4 * s4 + lk;
+                    av[set][i][s4] =
+                        (set < a.nsets && i < nin && rok && kk < m) ? a.in[set * 3 + i][ra * m + kk] : 0.0;
                 }
-            }
-            // accumulator register v holds row lk + 4v, column li of this wave's 16 rows
-            double *dst = a.out[set * 2 + q];
 #pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int64_t r = w0 + lk + 4 * v;
-                if (r < a.n && li < m) dst[r * m + li] = acc[v];
-            }
-            if (q == 0 && a.theta) {
-                if (set == 0) {
-                    xkeep = acc;
-                } else {
-                    const double th = li < m ? a.theta[li] : 0.0;
+        for (int set = 0; set < 2; set++) {
+            if (set >= a.nsets) break;
 #pragma unroll
-                    for (int v = 0; v < 4; v++) {
-                        const int64_t r = w0 + lk + 4 * v;
-                        if (r < a.n && li < m) {
-                            const double rv = acc[v] - xkeep[v] * th;
-                            a.res[r * m + li] = rv;
-                            nrm += rv * rv;
+            for (int q = 0; q < 2; q++) {
+                if (q >= nout) break;
+                double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    if (i >= nin) break;
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; s4++) {
+                        if (4 * s4 >= m) break;
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[set][i][s4], bv[q][i][s4], acc, 0, 0, 0);
+                    }
+                }
+                // accumulator register v holds row lk + 4v, column li of this wave's 16 rows
+                double *dst = a.out[set * 2 + q];
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int64_t r = w0 + lk + 4 * v;
+                    if (r < a.n && li < m) dst[r * m + li] = acc[v];
+                }
+                if (q == 0 && a.theta) {
+                    if (set == 0) {
+                        xkeep = acc;
+                    } else {
+                        const double th = li < m ? a.theta[li] : 0.0;
+#pragma unroll
+                        for (int v = 0; v < 4; v++) {
+                            const int64_t r = w0 + lk + 4 * v;
+                            if (r < a.n && li < m) {
+                                const double rv = acc[v] - xkeep[v] * th;
+                                a.res[r * m + li] = rv;
+                                nrm += rv * rv;
+                            }
                         }
                     }
                 }
@@ -271,7 +273,7 @@ __device__ __forceinline__ void lincomb_body(const LincombArgs &a, int64_t bx) {
         }
     }
     if (a.theta) {
-        // squared column norms of R for this workgroup's 64 rows, combined in a fixed order
+        // squared column norms of R for this workgroup's rows, combined in a fixed order
         nred[wave][lk][li] = nrm;
         __syncthreads();
         if (tid < m) {
@@ -287,19 +289,16 @@ __global__ __launch_bounds__(256) void k_lincomb(LincombArgs a) { lincomb_body(a
 
 __global__ __launch_bounds__(256) void k_lincomb_b(const LincombArgs *__restrict__ tab) {
     const LincombArgs a = tab[blockIdx.y];
-    if ((int64_t)blockIdx.x * 64 >= a.n) return;
+    if ((int64_t)blockIdx.x >= lincomb_norm_parts(a.n)) return;
     lincomb_body(a, blockIdx.x);
 }
 
 void lincomb(const LincombArgs &a, hipStream_t s) {
     if (a.nin * a.m > 48 || a.nout * a.m > 32 || a.nout > 2 || a.nin > 3 || a.m > 16)
         fail(HSYM_E_UNSUPPORTED, "lincomb shape");
-    unsigned grid = (unsigned)((a.n + 63) / 64);
-    hipLaunchKernelGGL(k_lincomb, dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_lincomb, dim3((unsigned)lincomb_norm_parts(a.n)), dim3(256), 0, s, a);
     HIPCHK(hipGetLastError());
 }
-
-int64_t lincomb_norm_parts(int64_t n) { return (n + 63) / 64; }
 
 // ---------------------------------------------------------------------------
 // Linear combination with a Gram epilogue (m = 16): W' = [in] C (one set, one
@@ -489,48 +488,6 @@ void colsum_final(const double *part, int64_t nparts, int m, double *out, hipStr
     HIPCHK(hipGetLastError());
 }
 
-// R = AX - X diag(theta) with squared column norms per workgroup
-template <int M>
-__global__ __launch_bounds__(256) void k_residual(const double *__restrict__ X, const double *__restrict__ AX,
-                                                  const double *__restrict__ theta, double *__restrict__ R,
-                                                  double *__restrict__ norm_part, int64_t n, int m) {
-    __shared__ double nred[4][M];
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double rn[M];
-#pragma unroll
-    for (int j = 0; j < M; j++) rn[j] = 0.0;
-    if (r < n) {
-#pragma unroll
-        for (int j = 0; j < M; j++) {
-            if (j < m) {
-                double v = AX[r * m + j] - X[r * m + j] * theta[j];
-                R[r * m + j] = v;
-                rn[j] = v * v;
-            }
-        }
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int j = 0; j < M; j++) {
-        double v = rn[j];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        if (lane == 0) nred[wave][j] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < m) {
-        double s = 0.0;
-        for (int w = 0; w < 4; w++) s += nred[w][threadIdx.x];
-        norm_part[(int64_t)blockIdx.x * m + threadIdx.x] = s;
-    }
-}
-
-void residual(const double *X, const double *AX, const double *theta, double *R, double *norm_part, int64_t n,
-              int m, hipStream_t s) {
-    unsigned grid = (unsigned)((n + 255) / 256);
-    if (m <= 8) hipLaunchKernelGGL(k_residual<8>, dim3(grid), dim3(256), 0, s, X, AX, theta, R, norm_part, n, m);
-    else hipLaunchKernelGGL(k_residual<16>, dim3(grid), dim3(256), 0, s, X, AX, theta, R, norm_part, n, m);
-    HIPCHK(hipGetLastError());
-}
 
 // ---------------------------------------------------------------------------
 // Preconditioners (eq. 11): T_j = Htilde - mu_j I, solved directly.
@@ -752,7 +709,9 @@ void gram_batched(const GramJob *jobs, int count, int K1, int K2, int max_parts,
 }
 
 void lincomb_batched(const LincombArgs *tab, int count, int64_t max_n, hipStream_t s) {
-    hipLaunchKernelGGL(k_lincomb_b, dim3((unsigned)((max_n + 63) / 64), (unsigned)count), dim3(256), 0, s, tab);
+    // every job's workgroup count is at most min(1024, its tiles of 64 rows)
+    const int64_t gx = std::min<int64_t>(1024, (max_n + 63) / 64);
+    hipLaunchKernelGGL(k_lincomb_b, dim3((unsigned)std::max<int64_t>(gx, 1), (unsigned)count), dim3(256), 0, s, tab);
     HIPCHK(hipGetLastError());
 }
 
