@@ -117,9 +117,8 @@ void lincomb_batched(const LincombArgs *tab, int count, int64_t max_n, hipStream
 // [A_0 .. W']^T W', with W' the last A block and the only B block), fused into
 // one pass over the rows when m = 16, else the two calls
 bool lincomb_gram_fusable(const LincombArgs &l, const GramArgs &g);
-int64_t lincomb_gram_rows(int64_t n, int parts);   // rows per workgroup of the fused pass
 void lincomb_gram(const LincombArgs &l, const GramArgs &g, double *out, double *scratch, hipStream_t s);
-// batched fused form (all fusable, K1 = na * 16, GramJob::rpw = lincomb_gram_rows)
+// batched fused form (all fusable, K1 = na * 16, GramJob::rpw = gram_rows)
 void lincomb_gram_batched(const LincombArgs *lt, const GramJob *gt, int count, int na, int max_parts,
                           hipStream_t s);
 struct ColsumJob {
@@ -140,6 +139,12 @@ void jacobi_batched(const JacobiJob *jobs, int count, int m, int64_t max_n, hipS
 void set_ints(int *const *p, int count, int v, hipStream_t s);
 void gather_words(const int *const *src, int *dst, int words, int count, hipStream_t s);
 int gram_parts(int64_t n);
+int64_t gram_rows(int64_t n, int parts);   // rows per partial (a multiple of 64)
+// Jacobi apply W[r][c] /= g(d_r - mu_c) (in place, W = the last A block and the
+// only B block of g, m = 16) followed by out = g, fused into one pass
+bool jacobi_gram_fusable(const GramArgs &g);
+void jacobi_gram(const GramArgs &g, const double *diag, const double *mu, double delta, double *out,
+                 double *scratch, hipStream_t s);
 
 struct OrthWork {
     double *gbuf;       // >= 48*16 doubles, device

@@ -13,6 +13,11 @@ namespace hsym {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
+// guarded shifted denominator: d, or +-delta where |d| < delta
+__device__ __forceinline__ double guard_den(double d, double delta) {
+    return fabs(d) >= delta ? d : (d >= 0.0 ? delta : -delta);
+}
+
 // ---------------------------------------------------------------------------
 // Gram: G = [A_0 .. A_{na-1}]^T [B_0 .. B_{nb-1}], each block n x m (ld m).
 // Stage 1: every workgroup reduces a contiguous row range into a K1 x K2
@@ -159,12 +164,18 @@ static void gram_launch_t(const GramArgs &g, double *part, int parts, int64_t rp
     hipLaunchKernelGGL((k_gram_partial<T1, T2>), dim3(parts), dim3(256), 0, s, g, part, rpw);
 }
 
+// rows per partial: a multiple of 64, shared by every kernel that writes
+// Gram partials, so that all of them cut the rows alike
+int64_t gram_rows(int64_t n, int parts) {
+    int64_t rpw = (n + parts - 1) / parts;
+    return (rpw + 63) / 64 * 64;
+}
+
 void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s) {
     const int K1 = g.na * g.m, K2 = g.nb * g.m;
     const int T1 = (K1 + 15) / 16, T2 = (K2 + 15) / 16;
     const int parts = gram_parts(g.n);
-    int64_t rpw = (g.n + parts - 1) / parts;
-    rpw = (rpw + 3) / 4 * 4;
+    const int64_t rpw = gram_rows(g.n, parts);
 #define GL(a, b) if (T1 == a && T2 == b) { gram_launch_t<a, b>(g, scratch, parts, rpw, s); } else
     GL(1, 1) GL(1, 2) GL(1, 3) GL(2, 1) GL(2, 2) GL(2, 3) GL(3, 1) GL(3, 2) GL(3, 3)
         fail(HSYM_E_UNSUPPORTED, "gram shape");
@@ -402,11 +413,6 @@ bool lincomb_gram_fusable(const LincombArgs &l, const GramArgs &g) {
            l.n == g.n;
 }
 
-int64_t lincomb_gram_rows(int64_t n, int parts) {
-    int64_t rpw = (n + parts - 1) / parts;
-    return (rpw + 63) / 64 * 64;
-}
-
 void lincomb_gram(const LincombArgs &l, const GramArgs &g, double *out, double *scratch, hipStream_t s) {
     if (!lincomb_gram_fusable(l, g)) {
         lincomb(l, s);
@@ -414,7 +420,7 @@ void lincomb_gram(const LincombArgs &l, const GramArgs &g, double *out, double *
         return;
     }
     const int parts = gram_parts(g.n);
-    const int64_t rpw = lincomb_gram_rows(g.n, parts);
+    const int64_t rpw = gram_rows(g.n, parts);
     switch (g.na) {
         case 1: hipLaunchKernelGGL(k_lincomb_gram<1>, dim3(parts), dim3(256), 0, s, l, g, scratch, rpw); break;
         case 2: hipLaunchKernelGGL(k_lincomb_gram<2>, dim3(parts), dim3(256), 0, s, l, g, scratch, rpw); break;
@@ -437,6 +443,83 @@ void lincomb_gram_batched(const LincombArgs *lt, const GramJob *gt, int count, i
     HIPCHK(hipGetLastError());
     const int kk = na * 16 * 16;
     hipLaunchKernelGGL(k_gram_final_b, dim3((unsigned)((kk + 63) / 64), (unsigned)count), dim3(1024), 0, s, gt);
+    HIPCHK(hipGetLastError());
+}
+
+// The Jacobi apply with a Gram epilogue (m = 16): W[r][c] /= g(d_r - mu_c)
+// in place, and the partial Gram matrices [A_0 .. A_{NA-2} W]^T W of the
+// workgroup's rows.  Rows and accumulation order are those of
+// k_gram_partial, so the partials are the ones the two separate passes give.
+template <int NA>
+__global__ __launch_bounds__(256) void k_jacobi_gram(GramArgs g, const double *__restrict__ diag,
+                                                     const double *__restrict__ mu, double delta,
+                                                     double *__restrict__ part, int64_t rows_per_wg) {
+    __shared__ double red[4][NA * 16][17];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    double *W = const_cast<double *>(g.b[0]);
+    const double muc = mu[li];
+    double4_t G[NA];
+#pragma unroll
+    for (int t = 0; t < NA; t++) G[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
+    const int64_t r_end = (r_begin + rows_per_wg < g.n) ? r_begin + rows_per_wg : g.n;
+    constexpr int GU = 4;
+    for (int64_t r0 = r_begin + 4 * wave; r0 < r_end; r0 += 16 * GU) {
+        double ax[GU][NA > 1 ? NA - 1 : 1], wv[GU], dg[GU];
+#pragma unroll
+        for (int u = 0; u < GU; u++) {
+            const int64_t r = r0 + 16 * u + lk;
+            const bool ok = r < r_end;
+#pragma unroll
+            for (int t = 0; t < NA - 1; t++) ax[u][t] = ok ? g.a[t][r * 16 + li] : 0.0;
+            wv[u] = ok ? W[r * 16 + li] : 0.0;
+            dg[u] = ok ? diag[r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < GU; u++) {
+            const int64_t r = r0 + 16 * u + lk;
+            if (r < r_end) {
+                wv[u] = wv[u] / guard_den(dg[u] - muc, delta);
+                W[r * 16 + li] = wv[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GU; u++) {
+#pragma unroll
+            for (int t = 0; t < NA - 1; t++) G[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[u][t], wv[u], G[t], 0, 0, 0);
+            G[NA - 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[u], wv[u], G[NA - 1], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NA; t++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) red[wave][16 * t + lk + 4 * v][li] = G[t][v];
+    __syncthreads();
+    double *out = part + (int64_t)blockIdx.x * (NA * 16) * 16;
+    for (int e = tid; e < NA * 16 * 16; e += 256) {
+        const int i = e >> 4, j = e & 15;
+        out[e] = red[0][i][j] + red[1][i][j] + red[2][i][j] + red[3][i][j];
+    }
+}
+
+bool jacobi_gram_fusable(const GramArgs &g) {
+    return g.m == 16 && g.nb == 1 && g.na >= 1 && g.na <= 3 && g.b[0] == g.a[g.na - 1];
+}
+
+void jacobi_gram(const GramArgs &g, const double *diag, const double *mu, double delta, double *out,
+                 double *scratch, hipStream_t s) {
+    if (!jacobi_gram_fusable(g)) fail(HSYM_E_UNSUPPORTED, "jacobi_gram shape");
+    const int parts = gram_parts(g.n);
+    const int64_t rpw = gram_rows(g.n, parts);
+    switch (g.na) {
+        case 1: hipLaunchKernelGGL(k_jacobi_gram<1>, dim3(parts), dim3(256), 0, s, g, diag, mu, delta, scratch, rpw); break;
+        case 2: hipLaunchKernelGGL(k_jacobi_gram<2>, dim3(parts), dim3(256), 0, s, g, diag, mu, delta, scratch, rpw); break;
+        default: hipLaunchKernelGGL(k_jacobi_gram<3>, dim3(parts), dim3(256), 0, s, g, diag, mu, delta, scratch, rpw); break;
+    }
+    HIPCHK(hipGetLastError());
+    const int kk = g.na * 16 * 16;
+    hipLaunchKernelGGL(k_gram_final, dim3((kk + 63) / 64), dim3(1024), 0, s, scratch, parts, kk, out);
     HIPCHK(hipGetLastError());
 }
 
@@ -493,9 +576,6 @@ void colsum_final(const double *part, int64_t nparts, int m, double *out, hipStr
 // Preconditioners (eq. 11): T_j = Htilde - mu_j I, solved directly.
 // The shifted denominators are kept at least delta away from zero.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double guard_den(double d, double delta) {
-    return fabs(d) >= delta ? d : (d >= 0.0 ? delta : -delta);
-}
 
 // Elementwise over the row-major n x M block (coalesced): W[r][j] /= g(d_r - mu_j).
 template <int M>

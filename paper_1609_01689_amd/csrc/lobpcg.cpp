@@ -277,14 +277,21 @@ struct Lobpcg {
 
     // advance_a: step 6 (W = T^-1 R) and the first Cholesky-QR stage of step 7,
     // ending with the copy of the rank-deficiency flag
-    void orth_part1() {
+    GramArgs orth_gram() const {
         const double *B[2] = {X, P};
         const int kb = have_p ? 2 : 1;
-        set_int(&st_d->flags[0], 0, s);
         GramArgs g{};
         for (int i = 0; i < kb; i++) g.a[i] = B[i];
         g.a[kb] = W; g.b[0] = W; g.na = kb + 1; g.nb = 1; g.m = m; g.n = n;
-        gram(g, gbuf, gram_scr, s);
+        return g;
+    }
+    // gram_done: gbuf already holds [X P W]^T W (computed with the preconditioner)
+    void orth_part1(bool gram_done = false) {
+        const double *B[2] = {X, P};
+        const int kb = have_p ? 2 : 1;
+        set_int(&st_d->flags[0], 0, s);
+        const GramArgs g = orth_gram();
+        if (!gram_done) gram(g, gbuf, gram_scr, s);
         OrthArgs oa{gbuf, coef, &st_d->flags[0], kb, m, 0};
         small_orth(&oa, 1, s);
         orth_lc = LincombArgs{};
@@ -304,11 +311,19 @@ struct Lobpcg {
         const bool pre = shifts(rho_, rnorm_, st_h->theta);
         orth_attempt = 0;
         auto body = [&] {
+            bool gram_done = false;
             if (pre) {
                 HIPCHK(hipMemcpyAsync(mu, mu_h, sizeof(double) * m, hipMemcpyHostToDevice, s));
-                precond_apply(H, precond, W, mu, o.guard * H->norm1, m, s, o.fom_iters);
+                const GramArgs g = orth_gram();
+                if (precond == HSYM_PRECOND_JACOBI && jacobi_gram_fusable(g)) {
+                    // the Jacobi apply and the first Gram in one pass over the rows
+                    jacobi_gram(g, H->diag64, mu, o.guard * H->norm1, gbuf, gram_scr, s);
+                    gram_done = true;
+                } else {
+                    precond_apply(H, precond, W, mu, o.guard * H->norm1, m, s, o.fom_iters);
+                }
             }
-            orth_part1();
+            orth_part1(gram_done);
         };
         if (o.graph && have_p) graphed(graph_a[pre ? 1 : 0], body);
         else body();
@@ -489,9 +504,7 @@ struct BatchPlan {
             j.g.a[0] = a0; j.g.a[1] = a1; j.g.a[2] = a2; j.g.b[0] = b0; j.g.b[1] = b1; j.g.b[2] = b2;
             j.g.na = na; j.g.nb = nb; j.g.m = L.m; j.g.n = L.n;
             j.parts = gram_parts(L.n);
-            int64_t rpw = (L.n + j.parts - 1) / j.parts;
-            // m = 16: rows per partial shared with the fused update + Gram pass
-            j.rpw = L.m == 16 ? lincomb_gram_rows(L.n, j.parts) : (rpw + 3) / 4 * 4;
+            j.rpw = gram_rows(L.n, j.parts);
             j.part = L.gram_scr;
             j.kk = na * L.m * nb * L.m;
             j.out = L.gbuf;
