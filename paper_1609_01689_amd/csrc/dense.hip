@@ -8,6 +8,7 @@
 //   - the preconditioner applies of eq. 11 (diagonal and 64x64 blocks).
 #include "hsym_internal.h"
 #include "dense.h"
+#include "wave.h"
 
 namespace hsym {
 
@@ -650,12 +651,6 @@ __global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W,
 // ---------------------------------------------------------------------------
 constexpr int FOM_KMAX = 4;
 
-__device__ __forceinline__ double wave_allsum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 __global__ __launch_bounds__(1024) void k_precond_fom(double *__restrict__ W, const int64_t *__restrict__ gstart,
                                                       const int64_t *__restrict__ goff,
                                                       const double *__restrict__ gdense,
@@ -667,9 +662,19 @@ __global__ __launch_bounds__(1024) void k_precond_fom(double *__restrict__ W, co
     const int64_t a = gstart[t];
     const int s = (int)(gstart[t + 1] - a);
     const double *D = gdense + goff[t];
-    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-        const int r = e >> 6, c = e & 63;
-        Ht[r][c] = (r < s && c < s) ? D[r * s + c] : 0.0;
+    // the tile, zero-padded to 64 x 64: four loads per thread in flight at once
+    for (int e0 = threadIdx.x; e0 < 64 * 64; e0 += 4 * blockDim.x) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = e0 + u * blockDim.x, r = e >> 6, c = e & 63;
+            v[u] = (e < 64 * 64 && r < s && c < s) ? D[r * s + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = e0 + u * blockDim.x;
+            if (e < 64 * 64) Ht[e >> 6][e & 63] = v[u];
+        }
     }
     __syncthreads();
     // from here on the waves (columns) are independent: no further barrier
@@ -678,7 +683,7 @@ __global__ __launch_bounds__(1024) void k_precond_fom(double *__restrict__ W, co
     const bool in = lane < s;
     const double shift = mu[j];
     const double b = in ? W[(a + lane) * m + j] : 0.0;
-    const double beta = sqrt(wave_allsum(b * b));
+    const double beta = sqrt(wave_sum(b * b));
     if (beta == 0.0) {
         if (in) W[(a + lane) * m + j] = 0.0;
         return;
@@ -698,17 +703,24 @@ __global__ __launch_bounds__(1024) void k_precond_fom(double *__restrict__ W, co
         if (i >= iters) break;
         vs[j][lane] = V[i];
         __builtin_amdgcn_wave_barrier();
-        double w = 0.0;
-        for (int c = 0; c < 64; c++) w = fma(Ht[lane][c], vs[j][c], w);
+        // (T v)_lane over the s columns of the tile (zero past s), four chains
+        double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+        for (int c = 0; c < s; c += 4) {
+            w0 = fma(Ht[lane][c], vs[j][c], w0);
+            w1 = fma(Ht[lane][c + 1], vs[j][c + 1], w1);
+            w2 = fma(Ht[lane][c + 2], vs[j][c + 2], w2);
+            w3 = fma(Ht[lane][c + 3], vs[j][c + 3], w3);
+        }
+        double w = (w0 + w1) + (w2 + w3);
         __builtin_amdgcn_wave_barrier();
         w = in ? w - shift * V[i] : 0.0;
 #pragma unroll
         for (int l = 0; l <= i; l++) {
-            const double h = wave_allsum(w * V[l]);
+            const double h = wave_sum(w * V[l]);
             Hh[l][i] = h;
             w -= h * V[l];
         }
-        const double hn = sqrt(wave_allsum(w * w));
+        const double hn = sqrt(wave_sum(w * w));
         Hh[i + 1][i] = hn;
         const bool live = hn > 1e-14 * beta;
         if (live) V[i + 1] = w / hn;
