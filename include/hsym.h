@@ -211,7 +211,8 @@ typedef struct {
                                threads of the process: use it where one thread
                                creates and steps the contexts (hsym_serve, whose
                                loader thread builds requests meanwhile, leaves it
-                               off)                                             */
+                               off).  Needs a non-null stream: on the null stream
+                               the solve runs without graphs                    */
     int fom_iters;          /* FOM steps of HSYM_PRECOND_FOM, 1..4; default 3 (the
                                paper performs up to three)                       */
 } lobpcg_opts;

@@ -194,6 +194,10 @@ struct Lobpcg {
         }
     }
 
+    // graphs need a stream that can be captured: the null stream cannot, so
+    // a solve on it runs eagerly
+    bool use_graph() const { return o.graph && have_p && s != nullptr; }
+
     // Run f's launches on s; with opts.graph, record them once into ge (a
     // graph of the stream's work) and replay ge from then on.  The launches
     // of a steady-state phase take the same arguments every iteration: the
@@ -325,7 +329,7 @@ struct Lobpcg {
             }
             orth_part1(gram_done);
         };
-        if (o.graph && have_p) graphed(graph_a[pre ? 1 : 0], body);
+        if (use_graph()) graphed(graph_a[pre ? 1 : 0], body);
         else body();
     }
 
@@ -376,7 +380,7 @@ struct Lobpcg {
             colsum_final(norm_part, lincomb_norm_parts(n), m, st_d->norms, s);
             post_status();
         };
-        if (o.graph && have_p) graphed(graph_b, body);
+        if (use_graph()) graphed(graph_b, body);
         else body();
         rep.spmm_calls++;
         have_p = true;

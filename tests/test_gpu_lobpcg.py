@@ -144,3 +144,23 @@ def test_lobpcg_invalid_args(c1):
     with pytest.raises(hs.HsymError):
         hs.lobpcg_solve(M.h, 5, 8, 1e-8, precond="block64")   # factors not built
     M.close()
+
+
+def test_lobpcg_graph_on_null_and_own_stream(c1):
+    """opts.graph replays the steady-state phases as HIP graphs on a stream
+    the caller owns, and runs eagerly on the null stream (which cannot be
+    captured); all three solves converge to the same pairs."""
+    A, lam = c1
+    M = hs.Matrix(A, geom_m=8)
+    out = []
+    st_own = torch.cuda.Stream()
+    for graph, stream in ((0, None), (1, None), (1, st_own)):
+        opts = hs.default_lobpcg_opts(seed=3, graph=graph)
+        s, ev, rep = hs.lobpcg_solve(M.h, 5, 8, 1e-8, opts=opts, stream=stream)
+        torch.cuda.synchronize()
+        assert s == hs.HSYM_OK
+        assert np.max(np.abs(ev - lam[:5]) / np.abs(lam[:5])) <= 1e-8
+        out.append(rep.iters)
+    M.close()
+    print("iterations (eager, graph on the null stream, graph on an own stream):", out)
+    assert max(out) - min(out) <= 2
