@@ -268,6 +268,7 @@ struct Builder {
     DevVec<double> v64;
     DevVec<float> v32;
     std::vector<int64_t> panel_tile_ptr{0};
+    std::vector<int64_t> panel_weight;  // per panel: padded entries + a per-tile cost, in entry units
     std::vector<int32_t> slot_chunk;   // chunk of every slot
     std::vector<double> diag;          // n
     std::vector<double> abssum;        // n: row+column absolute sums
@@ -317,6 +318,13 @@ struct Builder {
                 pq.insert(pq.end(), o.preq.begin(), o.preq.end());
                 pl.insert(pl.end(), o.prelam.begin(), o.prelam.end());
                 panel_tile_ptr.push_back(panel_tile_ptr.back() + (int64_t)o.tiles.size());
+                {
+                    // a tile's fixed cost (staging its X chunk, barriers, writing its sums)
+                    // is about that of 1,200 entries at m = 16
+                    int64_t wgt = 1200 * (int64_t)o.tiles.size();
+                    for (const auto &td : o.tiles) wgt += (int64_t)td.len * G;
+                    panel_weight.push_back(wgt);
+                }
                 for (size_t w = 0; w < o.colsum.size(); w++) abssum[(size_t)r0 + w] += o.colsum[w];
                 nnz += o.nnz;
                 PanelOut().tiles.swap(o.tiles);
@@ -480,6 +488,28 @@ void builder_finish(hsym_matrix *H) {
     HIPCHK(hipMemcpy(dt.panel_tile_ptr, b->panel_tile_ptr.data(), sizeof(int64_t) * b->panel_tile_ptr.size(),
                      hipMemcpyHostToDevice));
     dt.bytes += (int64_t)(sizeof(int64_t) * b->panel_tile_ptr.size());
+    // workgroup -> panel.  The dispatcher deals workgroups round-robin to the
+    // 8 XCDs (workgroup b to XCD b mod 8).  XCD x gets a contiguous run of
+    // panels, so the X chunks that neighbouring panels share stay in its L2,
+    // and takes them heaviest first, so that its CUs end on light panels
+    // (list scheduling; the panels' loads differ by up to 2x).
+    {
+        const int64_t P = dt.npanels, q = P >> 3, rem = P & 7;
+        std::vector<int32_t> order((size_t)P);
+        for (int64_t x = 0; x < 8; x++) {
+            const int64_t lo = x * q + std::min<int64_t>(x, rem), cnt = q + (x < rem ? 1 : 0);
+            std::vector<int32_t> ps((size_t)cnt);
+            for (int64_t i = 0; i < cnt; i++) ps[(size_t)i] = (int32_t)(lo + i);
+            std::stable_sort(ps.begin(), ps.end(), [&](int32_t u, int32_t v) {
+                return b->panel_weight[(size_t)u] > b->panel_weight[(size_t)v];
+            });
+            for (int64_t i = 0; i < cnt; i++) order[(size_t)(8 * i + x)] = ps[(size_t)i];
+        }
+        HIPCHK(hipMalloc(&dt.panel_order, sizeof(int32_t) * std::max<size_t>(1, order.size())));
+        if (!order.empty())
+            HIPCHK(hipMemcpy(dt.panel_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice));
+        dt.bytes += (int64_t)(sizeof(int32_t) * order.size());
+    }
     // reduction lists: slots per output chunk in panel order
     std::vector<int64_t> rptr((size_t)dt.nchunks + 1, 0);
     for (int32_t g : b->slot_chunk) rptr[(size_t)g + 1]++;
@@ -521,7 +551,7 @@ void builder_finish(hsym_matrix *H) {
 }
 
 void free_tiles(DeviceTiles *dt) {
-    void *ptrs[] = {dt->panel_tile_ptr, dt->tiles, dt->idx, dt->vals,
+    void *ptrs[] = {dt->panel_tile_ptr, dt->panel_order, dt->tiles, dt->idx, dt->vals,
                     dt->red_ptr, dt->red_slot, dt->red_chunks};
     for (void *p : ptrs) if (p) (void)hipFree(p);
     *dt = DeviceTiles();

@@ -52,6 +52,7 @@ struct DeviceTiles {
     int64_t npanels = 0, nchunks = 0, ntiles = 0, nentries = 0, nslots = 0;
     int64_t nred_chunks = 0;
     int64_t *panel_tile_ptr = nullptr;
+    int32_t *panel_order = nullptr;   // panel of workgroup b (see build.cpp: per-XCD, heaviest first)
     TileDesc *tiles = nullptr;
     void *idx = nullptr;          // uint16_t codes when idx_bytes == 2, else uint32_t
     int idx_bytes = 4;
@@ -126,6 +127,7 @@ size_t spmm_partial_bytes(hsym_matrix *H, int m, int yprec = T_F64);
 // one matrix of a batched SpMM (fp64 blocks with leading dimension m)
 struct SpmmJob {
     const int64_t *ptp;
+    const int32_t *porder;
     const TileDesc *tiles;
     const void *idx;
     int idx_bytes, idx_shift;

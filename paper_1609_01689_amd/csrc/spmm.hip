@@ -56,13 +56,6 @@ size_t spmm_lds_bytes(int storage, int m, int R, int C) {
     return (size_t)(R + C) * M * (8 + es);
 }
 
-__device__ __forceinline__ int64_t xcd_panel(int64_t b, int64_t P) {
-    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a run of
-    // consecutive panels so the X chunks they share stay in that XCD's L2.
-    const int64_t x = b & 7, i = b >> 3;
-    const int64_t q = P >> 3, rem = P & 7;
-    return x * q + (x < rem ? x : rem) + i;
-}
 
 __device__ __forceinline__ void lds_add(double *p, double v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -111,7 +104,8 @@ __device__ __forceinline__ void read_row(const T *rowp, int r, int k0, double *o
 // IT: uint16_t or uint32_t index codes, local row << cs | local column
 template <int M, typename T, typename XIN, typename YT, typename IT>
 __device__ __forceinline__ void spmm_panel_body(
-    const int64_t *__restrict__ ptp, const TileDesc *__restrict__ tiles, const IT *__restrict__ idx, int cs,
+    const int64_t *__restrict__ ptp, const int32_t *__restrict__ porder, const TileDesc *__restrict__ tiles,
+    const IT *__restrict__ idx, int cs,
     const T *__restrict__ vals, const T *__restrict__ diag, const XIN *__restrict__ X, int64_t ldx,
     YT *__restrict__ Y, int64_t ldy, double *__restrict__ partials, int64_t n, int R, int C, int G,
     int64_t npanels, int m, int64_t blk, unsigned char *smem_raw) {
@@ -124,7 +118,7 @@ __device__ __forceinline__ void spmm_panel_body(
     T *xs = xp + (size_t)R * M;
     const int tid = threadIdx.x, g = tid / LPE, q = tid % LPE, k0 = q * MW;
     const uint32_t cmask = (1u << cs) - 1u;   // 16-bit codes: local row << cs | local column
-    const int64_t p = xcd_panel(blk, npanels);
+    const int64_t p = porder[blk];
     const int64_t row0 = p * (int64_t)R;
     const int nrow = (int)((n - row0) < R ? (n - row0) : R);
 
@@ -254,12 +248,13 @@ __device__ __forceinline__ void spmm_panel_body(
 
 template <int M, typename T, typename XIN, typename YT, typename IT>
 __global__ __launch_bounds__(1024) void k_spmm_panel(
-    const int64_t *__restrict__ ptp, const TileDesc *__restrict__ tiles, const IT *__restrict__ idx, int cs,
+    const int64_t *__restrict__ ptp, const int32_t *__restrict__ porder, const TileDesc *__restrict__ tiles,
+    const IT *__restrict__ idx, int cs,
     const T *__restrict__ vals, const T *__restrict__ diag, const XIN *__restrict__ X, int64_t ldx,
     YT *__restrict__ Y, int64_t ldy, double *__restrict__ partials, int64_t n, int R, int C, int G,
     int64_t npanels, int m) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    spmm_panel_body<M, T, XIN, YT, IT>(ptp, tiles, idx, cs, vals, diag, X, ldx, Y, ldy, partials, n, R, C, G,
+    spmm_panel_body<M, T, XIN, YT, IT>(ptp, porder, tiles, idx, cs, vals, diag, X, ldx, Y, ldy, partials, n, R, C, G,
                                        npanels, m, blockIdx.x, smem_raw);
 }
 
@@ -271,12 +266,12 @@ __global__ __launch_bounds__(1024) void k_spmm_panel_b(const SpmmJob *__restrict
     if ((int64_t)blockIdx.x >= J.npanels) return;
     // the index width is a property of each job's handle (uniform per workgroup)
     if (J.idx_bytes == 2)
-        spmm_panel_body<M, T, double, double, uint16_t>(J.ptp, J.tiles, (const uint16_t *)J.idx, J.idx_shift,
+        spmm_panel_body<M, T, double, double, uint16_t>(J.ptp, J.porder, J.tiles, (const uint16_t *)J.idx, J.idx_shift,
                                                         (const T *)J.vals, (const T *)J.diag, J.X, J.ldx, J.Y, J.ldy,
                                                         J.partials, J.n, J.R, J.C, J.G, J.npanels, J.m, blockIdx.x,
                                                         smem_raw);
     else
-        spmm_panel_body<M, T, double, double, uint32_t>(J.ptp, J.tiles, (const uint32_t *)J.idx, J.idx_shift,
+        spmm_panel_body<M, T, double, double, uint32_t>(J.ptp, J.porder, J.tiles, (const uint32_t *)J.idx, J.idx_shift,
                                                         (const T *)J.vals, (const T *)J.diag, J.X, J.ldx, J.Y, J.ldy,
                                                         J.partials, J.n, J.R, J.C, J.G, J.npanels, J.m, blockIdx.x,
                                                         smem_raw);
@@ -359,7 +354,7 @@ static void launch_typed(hsym_matrix *H, int m, const void *X, int64_t ldx, void
     const T *diag = (const T *)(H->storage == HSYM_FP64 ? (const void *)H->diag64 : (const void *)H->diag32);
     constexpr bool atomic_out = sizeof(YT) == 8;
     if (atomic_out) zero_rows((double *)Y, H->n, m, ldy, s);
-    hipLaunchKernelGGL(kp, dim3((unsigned)dt.npanels), dim3(1024), lds, s, dt.panel_tile_ptr, dt.tiles,
+    hipLaunchKernelGGL(kp, dim3((unsigned)dt.npanels), dim3(1024), lds, s, dt.panel_tile_ptr, dt.panel_order, dt.tiles,
                        (const IT *)dt.idx, dt.idx_shift, (const T *)dt.vals, diag, (const XIN *)X, ldx, (YT *)Y, ldy, (double *)partials, H->n, dt.R,
                        dt.C, dt.G, dt.npanels, m);
     HIPCHK(hipGetLastError());
@@ -393,7 +388,7 @@ static void launch_m(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y,
 SpmmJob spmm_job(hsym_matrix *H, int m, const double *X, double *Y, double *partials) {
     const DeviceTiles &dt = H->tiles;
     SpmmJob J{};
-    J.ptp = dt.panel_tile_ptr; J.tiles = dt.tiles; J.idx = dt.idx; J.vals = dt.vals;
+    J.ptp = dt.panel_tile_ptr; J.porder = dt.panel_order; J.tiles = dt.tiles; J.idx = dt.idx; J.vals = dt.vals;
     J.idx_bytes = dt.idx_bytes; J.idx_shift = dt.idx_shift;
     J.diag = H->storage == HSYM_FP64 ? (const void *)H->diag64 : (const void *)H->diag32;
     J.X = X; J.ldx = m; J.Y = Y; J.ldy = m; J.partials = partials;
