@@ -490,19 +490,22 @@ void builder_finish(hsym_matrix *H) {
     dt.bytes += (int64_t)(sizeof(int64_t) * b->panel_tile_ptr.size());
     // workgroup -> panel.  The dispatcher deals workgroups round-robin to the
     // 8 XCDs (workgroup b to XCD b mod 8).  XCD x gets a contiguous run of
-    // panels, so the X chunks that neighbouring panels share stay in its L2,
-    // and takes them heaviest first, so that its CUs end on light panels
-    // (list scheduling; the panels' loads differ by up to 2x).
+    // panels, so the X chunks that neighbouring panels share stay in its L2.
+    // With few panels per CU it takes them heaviest first, so that its CUs
+    // end on light panels (list scheduling; the panels' loads differ by up to
+    // 2x); with many, in row order, which keeps more chunk reuse in L2.
     {
         const int64_t P = dt.npanels, q = P >> 3, rem = P & 7;
+        const bool heavy_first = P < 16 * 256;
         std::vector<int32_t> order((size_t)P);
         for (int64_t x = 0; x < 8; x++) {
             const int64_t lo = x * q + std::min<int64_t>(x, rem), cnt = q + (x < rem ? 1 : 0);
             std::vector<int32_t> ps((size_t)cnt);
             for (int64_t i = 0; i < cnt; i++) ps[(size_t)i] = (int32_t)(lo + i);
-            std::stable_sort(ps.begin(), ps.end(), [&](int32_t u, int32_t v) {
-                return b->panel_weight[(size_t)u] > b->panel_weight[(size_t)v];
-            });
+            if (heavy_first)
+                std::stable_sort(ps.begin(), ps.end(), [&](int32_t u, int32_t v) {
+                    return b->panel_weight[(size_t)u] > b->panel_weight[(size_t)v];
+                });
             for (int64_t i = 0; i < cnt; i++) order[(size_t)(8 * i + x)] = ps[(size_t)i];
         }
         HIPCHK(hipMalloc(&dt.panel_order, sizeof(int32_t) * std::max<size_t>(1, order.size())));
