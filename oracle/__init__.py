@@ -44,6 +44,10 @@ _lib = None
 NEAR = 1e-1          # Section 4.3 rule 2 threshold; also "nearly converged" (rules 3-4)
 GUARD = 1e-4         # shifted-denominator guard, as a fraction of ||H||_1
 DEFICIENT = 1e-10    # rank test on the R factor of a column-normalised block
+# P is orthonormalised through its QR factor and AP follows by the same
+# (updated, not recomputed) transformation: a pivot r amplifies the rounding
+# of both by 1 / r, so P is dropped for the iteration below this pivot
+P_DEFICIENT = 1e-4
 NO_PRECOND_ITERS = 3 # Section 4.3 rule 1
 
 
@@ -457,7 +461,7 @@ def lobpcg(A: SymMatrix, nev, m, tol, X0=None, precond="jacobi", maxit=1000, see
                 P = P / nrm
                 AP = AP / nrm
                 Qp, Rp = np.linalg.qr(P)
-                if np.min(np.abs(np.diag(Rp))) < DEFICIENT:
+                if np.min(np.abs(np.diag(Rp))) < P_DEFICIENT:
                     P = AP = None
                     res.p_dropped += 1
                 else:

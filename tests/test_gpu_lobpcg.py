@@ -164,3 +164,18 @@ def test_lobpcg_graph_on_null_and_own_stream(c1):
     M.close()
     print("iterations (eager, graph on the null stream, graph on an own stream):", out)
     assert max(out) - min(out) <= 2
+
+
+@pytest.mark.parametrize("n", [48, 50, 70, 130])
+def test_lobpcg_m16_tiny_n(n):
+    """Block width 16 on n = 3m and barely above: one partial per Gram,
+    ragged 64-row tiles in the fused update + Gram and Jacobi + Gram passes,
+    and (n = 48, 50) a basis that fills the space, where W columns are
+    replaced and the coefficient-space P keeps the basis orthonormal."""
+    A = hsymgen.generate(n, 20, 40 + n)
+    lam = np.linalg.eigvalsh(dense_of(A))
+    X0 = hsymgen.gauss_block(7, n, 16)
+    st, evals, vecs, rep, _ = solve(A, 4, 16, 1e-9, X0=X0, maxit=500)
+    assert st == hs.HSYM_OK
+    assert np.max(np.abs(evals - lam[:4]) / np.abs(lam[:4])) <= 1e-8
+    certify(A, evals, vecs, 2e-9)

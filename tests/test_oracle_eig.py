@@ -132,3 +132,22 @@ def test_lobpcg_vs_lanczos_iteration_claim(c1):
     la = oracle.lanczos(H, 5, 1e-8, v0=hsymgen.gauss_vector(1, A.n))
     assert lo.iters < la.iters
     assert 8 * lo.iters > la.iters
+
+
+def test_ritz_values_bounded_when_the_basis_nearly_fills_the_space():
+    """n = 50 with m = 16: [X W P] spans 48 of 50 dimensions and P turns
+    nearly dependent.  Rayleigh-Ritz on an orthonormal basis gives Ritz values
+    theta_j >= lambda_j (Cauchy interlacing); a P orthonormalised through a
+    tiny QR pivot (with its updated AP) breaks that bound and the iteration
+    diverges (Ritz values below -1e3 within 10 iterations).  The bound is
+    checked to 1e-7 ||H||_1: W columns are kept down to pivots of 1e-10, whose
+    rounding can leave the basis orthonormal to about that level only."""
+    n = 50
+    A = hsymgen.generate(n, 20, 90)
+    H = oracle.SymMatrix.from_csr(A)
+    lam = np.linalg.eigvalsh(H.dense())
+    r = oracle.lobpcg(H, 4, 16, 1e-9, X0=hsymgen.gauss_block(7, n, 16), maxit=60, keep_history=True)
+    slack = 1e-7 * H.norm1()
+    for theta, _ in r.history:
+        assert np.all(theta[:16] >= lam[:16] - slack)
+    assert np.max(np.abs(r.evals - lam[:4]) / np.abs(lam[:4])) <= 1e-9
