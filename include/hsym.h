@@ -61,6 +61,9 @@ enum hsym_precond { HSYM_PRECOND_NONE = 0, HSYM_PRECOND_JACOBI = 1, HSYM_PRECOND
 
 /* hsym_create flags */
 #define HSYM_HOST_PTRS     0x0   /* rowptr/colind/values are host memory (default)   */
+#define HSYM_DEVICE_PTRS   0x1   /* hsym_create only: rowptr/colind/values are device
+                                    memory (copied to the host, where the tiles are
+                                    built; the copy is synchronous)                 */
 #define HSYM_BUILD_BLOCK64 0x2   /* also build the 64x64 block preconditioner factors */
 /* Store the tile-local index codes (local row and column packed together) in
  * 16 bits instead of 32 when the chunk width C is a power of two and
@@ -103,15 +106,16 @@ typedef struct {
  * Build a device-resident handle from the upper triangle of H in CSR form
  * (Section 4.1 stores one triangle; this ABI takes the upper one, which is
  * the transpose of the paper's lower triangle).
- *   rowptr  host int64[n+1], rowptr[0]=0, non-decreasing, rowptr[n]=nnz;
- *   colind  host int32[nnz], row i holds columns >= i, strictly increasing;
+ *   rowptr  host (or device, see flags) int64[n+1], rowptr[0]=0,
+ *           non-decreasing, rowptr[n]=nnz;
+ *   colind  int32[nnz], row i holds columns >= i, strictly increasing;
  *           a missing diagonal entry means H_ii = 0;
- *   values  host, fp64 (values_prec=HSYM_FP64) or fp32 (HSYM_FP32), finite;
+ *   values  fp64 (values_prec=HSYM_FP64) or fp32 (HSYM_FP32), finite;
  *   storage precision of the device copy: HSYM_FP64 (plain form) or HSYM_FP32
  *           (mixed form, Section 4.4 footnote 5: H stored and multiplied in
  *           single precision); fp64 input is rounded to nearest once;
- *   flags   HSYM_HOST_PTRS | optional HSYM_BUILD_BLOCK64, HSYM_INDEX16,
- *           HSYM_GEOM_M, HSYM_GEOM_PANEL.
+ *   flags   HSYM_HOST_PTRS or HSYM_DEVICE_PTRS, optional HSYM_BUILD_BLOCK64,
+ *           HSYM_INDEX16, HSYM_GEOM_M, HSYM_GEOM_PANEL.
  * The call copies: the caller may free its arrays on return.  Synchronous.
  * Errors: HSYM_E_INVALID_ARG for any CSR violation listed above or n < 1 or
  * n >= 2^31; HSYM_E_OUT_OF_MEMORY; HSYM_E_DEVICE.  *H is NULL on error.

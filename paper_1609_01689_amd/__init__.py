@@ -29,6 +29,7 @@ HSYM_FP64, HSYM_FP32 = 0, 1
 PRECOND = {"none": 0, "jacobi": 1, "block64": 2, "fom": 3}
 HSYM_BUILD_BLOCK64 = 0x2
 HSYM_INDEX16 = 0x4
+HSYM_DEVICE_PTRS = 0x1
 MAX_BLOCK = 16
 MAX_HISTORY = 4096
 
@@ -215,6 +216,16 @@ def hsym_create(n, rowptr, colind, values, storage=HSYM_FP64, flags=0, stream=No
     h = ctypes.c_void_p()
     _check(lib().hsym_create(ctypes.byref(h), int(n), _hptr(rowptr), _hptr(colind), _hptr(values), vp,
                              storage, flags, _stream(stream)))
+    return h
+
+
+def hsym_create_device(n, rowptr, colind, values, storage=HSYM_FP64, flags=0, stream=None):
+    """Device handle from upper-triangle CSR held in device tensors (int64, int32, fp64/fp32)."""
+    vp = {"torch.float64": HSYM_FP64, "torch.float32": HSYM_FP32}[str(values.dtype)]
+    h = ctypes.c_void_p()
+    _check(lib().hsym_create(ctypes.byref(h), int(n), ctypes.c_void_p(rowptr.data_ptr()),
+                             ctypes.c_void_p(colind.data_ptr()), ctypes.c_void_p(values.data_ptr()), vp,
+                             storage, flags | HSYM_DEVICE_PTRS, _stream(stream)))
     return h
 
 

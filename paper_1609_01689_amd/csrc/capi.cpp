@@ -3,6 +3,8 @@
 #include <cstring>
 #include <mutex>
 
+#include <vector>
+
 #include "hsym_internal.h"
 
 namespace hsym {
@@ -90,6 +92,7 @@ int hsym_create_begin(hsym_t *out, int64_t n, int storage, int flags, void *stre
     if (out) *out = nullptr;
     hsym_matrix *H = nullptr;
     API_BEGIN
+    if (flags & HSYM_DEVICE_PTRS) fail(HSYM_E_INVALID_ARG, "the streaming create takes host arrays");
     if (!out) fail(HSYM_E_INVALID_ARG, "NULL handle pointer");
     if (n < 1 || n >= ((int64_t)1 << 31)) fail(HSYM_E_INVALID_ARG, "n must be in [1, 2^31)");
     if (storage != HSYM_FP64 && storage != HSYM_FP32) fail(HSYM_E_INVALID_ARG, "storage must be HSYM_FP64 or HSYM_FP32");
@@ -146,8 +149,36 @@ int hsym_create(hsym_t *out, int64_t n, const int64_t *rowptr, const int32_t *co
     if (!out) fail(HSYM_E_INVALID_ARG, "NULL handle pointer");
     if (!rowptr) fail(HSYM_E_INVALID_ARG, "NULL rowptr");
     if (n < 1 || n >= ((int64_t)1 << 31)) fail(HSYM_E_INVALID_ARG, "n must be in [1, 2^31)");
-    if (rowptr[0] != 0) fail(HSYM_E_INVALID_ARG, "rowptr[0] != 0");
     if (values_prec != HSYM_FP64 && values_prec != HSYM_FP32) fail(HSYM_E_INVALID_ARG, "bad values precision");
+    // device-resident CSR: staged to the host, where the tiles are built
+    std::vector<int64_t> rp_h;
+    std::vector<int32_t> ci_h;
+    std::vector<char> v_h;
+    if (flags & HSYM_DEVICE_PTRS) {
+        rp_h.resize((size_t)n + 1);
+        if (hipMemcpy(rp_h.data(), rowptr, sizeof(int64_t) * rp_h.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(HSYM_E_INVALID_ARG, "rowptr is not readable device memory");
+        }
+        const int64_t nnz = rp_h[(size_t)n];
+        if (rp_h[0] != 0 || nnz < 0) fail(HSYM_E_INVALID_ARG, "rowptr[0] != 0 or rowptr[n] < 0");
+        if (nnz > 0) {
+            if (!colind || !values) fail(HSYM_E_INVALID_ARG, "NULL CSR array");
+            const size_t vs = values_prec == HSYM_FP64 ? 8 : 4;
+            ci_h.resize((size_t)nnz);
+            v_h.resize((size_t)nnz * vs);
+            if (hipMemcpy(ci_h.data(), colind, sizeof(int32_t) * ci_h.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(v_h.data(), values, v_h.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+                (void)hipGetLastError();
+                fail(HSYM_E_INVALID_ARG, "colind or values is not readable device memory");
+            }
+        }
+        rowptr = rp_h.data();
+        colind = ci_h.data();
+        values = v_h.data();
+        flags &= ~HSYM_DEVICE_PTRS;
+    }
+    if (rowptr[0] != 0) fail(HSYM_E_INVALID_ARG, "rowptr[0] != 0");
     hsym_t H = nullptr;
     int st = hsym_create_begin(&H, n, storage, flags, stream);
     if (st) return st;

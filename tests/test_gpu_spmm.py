@@ -211,3 +211,28 @@ def test_index_code_widths(storage):
     assert i16["padded_entries"] == i32["padded_entries"]
     assert i16["device_bytes"] <= i32["device_bytes"] - 2 * i32["padded_entries"] + 4096
     assert np.linalg.norm(y16 - y32) <= 1e-13 * np.linalg.norm(y32)
+
+
+def test_create_from_device_csr():
+    """HSYM_DEVICE_PTRS: the same handle from CSR arrays held in device memory."""
+    dev = _dev()
+    A = hsymgen.generate(7001, 120, 33)
+    X = hsymgen.gauss_block(5, A.n, 16)
+    Yh, ih = _run(A, X)
+    rp = torch.from_numpy(np.ascontiguousarray(A.rowptr, np.int64)).to(dev)
+    ci = torch.from_numpy(np.ascontiguousarray(A.colind, np.int32)).to(dev)
+    va = torch.from_numpy(np.ascontiguousarray(A.values, np.float64)).to(dev)
+    h = hs.hsym_create_device(A.n, rp, ci, va, flags=hs.HSYM_GEOM_M(16))
+    info = hs.hsym_info(h)
+    Xd = torch.from_numpy(X).to(dev)
+    Yd = torch.empty_like(Xd)
+    hs.spmm_sym(h, Xd, Yd)
+    torch.cuda.synchronize()
+    hs.hsym_destroy(h)
+    for k in ("nnz_stored", "norm1", "npanels", "ntiles", "padded_entries", "device_bytes"):
+        assert info[k] == ih[k], k
+    assert np.linalg.norm(Yd.cpu().numpy() - Yh) <= 1e-15 * np.linalg.norm(Yh)
+    # the streaming create takes host arrays only
+    with pytest.raises(hs.HsymError) as e:
+        hs.hsym_create_begin(A.n, hs.HSYM_FP64, hs.HSYM_DEVICE_PTRS)
+    assert e.value.status == hs.HSYM_E_INVALID_ARG
