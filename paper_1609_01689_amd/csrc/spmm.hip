@@ -28,6 +28,8 @@
 // LDS rows are stored in 16-byte chunks permuted by an XOR with the row index,
 // so the lane groups of one wave, which touch different rows, spread their
 // 16-byte reads and their atomics over the banks.
+#include <mutex>
+
 #include "hsym_internal.h"
 
 namespace hsym {
@@ -346,11 +348,10 @@ static void launch_typed(hsym_matrix *H, int m, const void *X, int64_t ldx, void
     const DeviceTiles &dt = H->tiles;
     size_t lds = (size_t)(dt.R + dt.C) * M * (sizeof(double) + sizeof(T));
     auto kp = k_spmm_panel<M, T, XIN, YT, IT>;
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::once_flag attr_once;   // the 160 KB LDS limit, set once (threads may launch concurrently)
+    std::call_once(attr_once, [&] {
         HIPCHK(hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        attr_set = true;
-    }
+    });
     const T *diag = (const T *)(H->storage == HSYM_FP64 ? (const void *)H->diag64 : (const void *)H->diag32);
     constexpr bool atomic_out = sizeof(YT) == 8;
     if (atomic_out) zero_rows((double *)Y, H->n, m, ldy, s);
@@ -408,11 +409,10 @@ static void batched_typed(const SpmmJob *jobs, const SpmmJob *host, int count, h
     }
     if (lds > 160 * 1024) fail(HSYM_E_UNSUPPORTED, "block width too large for a handle's panel geometry");
     auto kp = k_spmm_panel_b<M, T>;
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::once_flag attr_once;   // the 160 KB LDS limit, set once (threads may launch concurrently)
+    std::call_once(attr_once, [&] {
         HIPCHK(hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        attr_set = true;
-    }
+    });
     int64_t maxn = 0;
     for (int i = 0; i < count; i++) maxn = std::max(maxn, host[i].n * host[i].m);
     (void)maxr;
