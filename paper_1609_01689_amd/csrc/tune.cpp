@@ -44,6 +44,11 @@ struct DevBuf {
     ~DevBuf() { if (p) (void)hipFree(p); }
 };
 
+struct Handle {
+    hsym_t h = nullptr;
+    ~Handle() { if (h) (void)hsym_destroy(h); }
+};
+
 struct Stream {
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -111,8 +116,9 @@ extern "C" int hsym_autotune_geometry(int64_t n, const int64_t *rowptr, const in
             if (spmm_lds_bytes(storage, m, R, C) > 160 * 1024) continue;
             const int flags = HSYM_GEOM_M(m) | HSYM_GEOM_PANEL(lr, lc);
             double ms = -1.0;
-            hsym_t H = nullptr;
-            int rc = hsym_create(&H, k, S.rp.data(), S.ci.data(), sv, values_prec, storage, flags, st.s);
+            Handle hg;   // destroyed on every path, errors included
+            int rc = hsym_create(&hg.h, k, S.rp.data(), S.ci.data(), sv, values_prec, storage, flags, st.s);
+            hsym_t H = hg.h;
             if (rc == HSYM_OK) {
                 for (int w = 0; w < 3 && rc == HSYM_OK; w++)
                     rc = spmm_sym(H, m, (const double *)X.p, m, (double *)Y.p, m, st.s);
@@ -126,7 +132,6 @@ extern "C" int hsym_autotune_geometry(int64_t n, const int64_t *rowptr, const in
                     HIPCHK(hipEventElapsedTime(&f, st.e0, st.e1));
                     if (rc == HSYM_OK) ms = f / 5.0;
                 }
-                hsym_destroy(H);
             }
             // a geometry the device cannot hold (memory) is skipped, not fatal
             if (rc == HSYM_E_DEVICE) fail(rc, std::string("autotune: ") + hsym_last_error());
