@@ -26,6 +26,7 @@ struct LincombArgs {
     const double *theta;   // optional: residual of (set1 out0) - (set0 out0) diag(theta)
     double *res;
     double *norm_part;     // lincomb_norm_parts(n) x m
+    const int *skip;       // optional device flag: nonzero -> the launch writes nothing
 };
 void lincomb(const LincombArgs &a, hipStream_t s);
 // workgroups of a linear combination over n rows (also its residual-norm

@@ -205,6 +205,7 @@ void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s) {
 // staging and no barrier until the fixed-order reduction of the residual norms.
 __device__ __forceinline__ void lincomb_body(const LincombArgs &a, int64_t bx) {
     __shared__ double nred[4][4][16];
+    if (a.skip && *a.skip) return;   // uniform: the flag was written by an earlier launch
     const int m = a.m, nin = a.nin, nout = a.nout;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
@@ -327,6 +328,7 @@ template <int NA>
 __device__ __forceinline__ void lincomb_gram_body(const LincombArgs &l, const GramArgs &g, double *__restrict__ part,
                                                   int64_t rows_per_wg, int64_t bx) {
     __shared__ double red[4][NA * 16][17];
+    if (l.skip && *l.skip) return;   // uniform: the flag was written by an earlier launch
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int nin = l.nin;

@@ -238,7 +238,7 @@ struct Lobpcg {
         small_rr(&r, 1, s);
     }
 
-    // ---- phases of one iteration (the two host synchronisation points) ----
+    // ---- phases of one iteration (A: up to the rank flag; B: the rest) ----
     // post_status: enqueue the copy of the status block (norms, Ritz values)
     void post_status() { HIPCHK(hipMemcpyAsync(st_h, st_d, sizeof(Status), hipMemcpyDeviceToHost, s)); }
 
@@ -333,10 +333,6 @@ struct Lobpcg {
         else body();
     }
 
-    // advance_b (flag copy complete): repair a deficient W, or finish step 7,
-    // apply H (the one SpMM of the iteration), Rayleigh-Ritz (steps 7-9), the
-    // update of X, P, AX, AP (step 10) fused with the next residual, and post
-    // the status copy.  Returns false when the flag copy must be awaited again.
     // a deficient W (flag copy complete): replace the flagged columns and redo
     // the first Cholesky-QR stage, ending with a new flag copy
     void repair_once() {
@@ -350,15 +346,19 @@ struct Lobpcg {
         orth_part1();
     }
 
-    bool advance_b() {
-        if (st_h->flags[0]) {
-            repair_once();
-            return false;
-        }
+    // Phase B: the second Cholesky-QR pass, the SpMM, Rayleigh-Ritz (steps
+    // 7-9) and the update of X, P, AX, AP (step 10) fused with the next
+    // residual, then the status copy.  It is enqueued right behind phase A,
+    // before the rank flag is known: the two launches that overwrite the
+    // basis (the second update of W and the update of X, P, AX, AP) write
+    // nothing when the flag is set, so that a repair can start from them.
+    void phase_b() {
         auto body = [&] {
+            LincombArgs lc2 = orth_lc;
+            lc2.skip = &st_d->flags[0];
             GramArgs g2{};
             g2.a[0] = W; g2.b[0] = W; g2.na = g2.nb = 1; g2.m = m; g2.n = n;
-            lincomb_gram(orth_lc, g2, gbuf, gram_scr, s);
+            lincomb_gram(lc2, g2, gbuf, gram_scr, s);
             // second Cholesky-QR pass: its factor U (W_orth = W U) is not
             // applied to W; the SpMM takes W as it is and the Rayleigh-Ritz
             // step applies U to the Gram matrix and to the W coefficients
@@ -375,7 +375,7 @@ struct Lobpcg {
             u.in[0] = X; u.in[1] = W; u.in[2] = P; u.in[3] = AX; u.in[4] = AW; u.in[5] = AP;
             u.out[0] = X; u.out[1] = P; u.out[2] = AX; u.out[3] = AP;
             u.coef = rrcoef; u.ldc = 2 * m; u.nin = nblk; u.nout = 2; u.nsets = 2; u.m = m; u.n = n;
-            u.theta = st_d->theta; u.res = W; u.norm_part = norm_part;
+            u.theta = st_d->theta; u.res = W; u.norm_part = norm_part; u.skip = &st_d->flags[0];
             lincomb(u, s);
             colsum_final(norm_part, lincomb_norm_parts(n), m, st_d->norms, s);
             post_status();
@@ -384,7 +384,36 @@ struct Lobpcg {
         else body();
         rep.spmm_calls++;
         have_p = true;
-        return true;
+    }
+
+    // One iteration with one host wait: phases A and B and the status copy
+    // are enqueued together (begin), then the status is checked (complete).
+    Status prev_st{};
+    bool prev_have_p = false;
+    void begin_iteration() {
+        prev_st = *st_h;
+        prev_have_p = have_p;
+        advance_a();
+        phase_b();
+    }
+    // A set rank flag (from Cholesky-QR stage 0, 1 or 2) means phase B left
+    // X, P, AX, AP and W as they were: restore the status and P of before the
+    // iteration, repair the flagged columns of W until the first stage is
+    // clean, and run phase B again.
+    void complete_iteration() {
+        for (;;) {
+            sync();
+            const int flag = st_h->flags[0];
+            if (!flag) return;
+            *st_h = prev_st;
+            st_h->flags[0] = flag;
+            have_p = prev_have_p;
+            do {
+                repair_once();
+                sync();
+            } while (st_h->flags[0]);
+            phase_b();
+        }
     }
 
     void sync() {
@@ -403,8 +432,8 @@ struct Lobpcg {
         for (;;) {
             sync();
             if (evaluate()) return;
-            advance_a();
-            do { sync(); } while (!advance_b());
+            begin_iteration();
+            complete_iteration();
         }
     }
 
@@ -423,7 +452,7 @@ struct Lobpcg {
 // for all of them (argument tables in device memory, one problem per
 // blockIdx.y), on one stream, with the two host synchronisation points of
 // the iteration shared.  The arithmetic of each problem is that of
-// Lobpcg::advance_a / advance_b; only the launches are merged.
+// Lobpcg::advance_a / phase_b; only the launches are merged.
 // ---------------------------------------------------------------------------
 constexpr int64_t BATCH_MAX_N = (int64_t)1 << 18;   // larger problems fill the GPU alone
 constexpr int BATCH_CAP = 256;
@@ -782,7 +811,7 @@ int lobpcg_ctx_step(lobpcg_ctx_t *ctxs, int count, int iters) {
     return ctx_guard([&] {
         if ((!ctxs && count) || count < 0 || iters < 0) fail(HSYM_E_INVALID_ARG, "bad step arguments");
         for (int i = 0; i < count; i++) if (!ctxs[i]) fail(HSYM_E_INVALID_ARG, "NULL context");
-        std::vector<Lobpcg *> act, pend;
+        std::vector<Lobpcg *> act;
         for (int k = 0; k < iters; k++) {
             act.clear();
             for (int i = 0; i < count; i++) {
@@ -812,18 +841,10 @@ int lobpcg_ctx_step(lobpcg_ctx_t *ctxs, int count, int iters) {
             }
             for (auto &g : groups)
                 if (g.size() < 2) solo.push_back(g[0]);
-            for (Lobpcg *L : solo) L->advance_a();
+            for (Lobpcg *L : solo) L->begin_iteration();
             for (auto &g : groups)
                 if (g.size() >= 2) step_batched(g);
-            pend = solo;
-            while (!pend.empty()) {
-                std::vector<Lobpcg *> next;
-                for (Lobpcg *L : pend) {
-                    L->sync();
-                    if (!L->advance_b()) next.push_back(L);
-                }
-                pend.swap(next);
-            }
+            for (Lobpcg *L : solo) L->complete_iteration();
         }
         return (int)HSYM_OK;
     });
