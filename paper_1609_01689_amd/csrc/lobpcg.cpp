@@ -450,8 +450,8 @@ struct Lobpcg {
 // state (P present), use the Jacobi or no preconditioner and record no
 // graphs are stepped together: every step of the iteration is one launch
 // for all of them (argument tables in device memory, one problem per
-// blockIdx.y), on one stream, with the two host synchronisation points of
-// the iteration shared.  The arithmetic of each problem is that of
+// blockIdx.y), on one stream, with the iteration's host synchronisation
+// shared.  The arithmetic of each problem is that of
 // Lobpcg::advance_a / phase_b; only the launches are merged.
 // ---------------------------------------------------------------------------
 constexpr int64_t BATCH_MAX_N = (int64_t)1 << 18;   // larger problems fill the GPU alone
@@ -469,7 +469,7 @@ struct BatchPlan {
     char *dev = nullptr, *pin = nullptr;
     size_t bytes = 0;
     GramJob *gA = nullptr, *gW = nullptr, *gS = nullptr;
-    LincombArgs *lcO = nullptr, *lcU = nullptr;
+    LincombArgs *lcO = nullptr, *lcO2 = nullptr, *lcU = nullptr;   // lcO2: phase B's copy of lcO
     ColsumJob *cs = nullptr;
     SpmmJob *sp = nullptr;
     int **flag_ptr = nullptr;
@@ -507,7 +507,7 @@ struct BatchPlan {
                 return o;
             };
             const size_t oA = at(sizeof(GramJob)), oW = at(sizeof(GramJob)), oS = at(sizeof(GramJob));
-            const size_t oO = at(sizeof(LincombArgs)), oU = at(sizeof(LincombArgs));
+            const size_t oO = at(sizeof(LincombArgs)), oO2 = at(sizeof(LincombArgs)), oU = at(sizeof(LincombArgs));
             const size_t oC = at(sizeof(ColsumJob)), oP = at(sizeof(SpmmJob)), oF = at(sizeof(int *));
             const size_t oR = at(sizeof(int *)), oT = at(sizeof(Status)), oJ = at(sizeof(JacobiJob));
             const size_t oM = at(sizeof(double) * HSYM_MAX_BLOCK);
@@ -515,14 +515,14 @@ struct BatchPlan {
             HIPCHK(hipMalloc((void **)&dev, bytes));
             HIPCHK(hipHostMalloc((void **)&pin, bytes, hipHostMallocDefault));
             gA = (GramJob *)(dev + oA); gW = (GramJob *)(dev + oW); gS = (GramJob *)(dev + oS);
-            lcO = (LincombArgs *)(dev + oO); lcU = (LincombArgs *)(dev + oU);
+            lcO = (LincombArgs *)(dev + oO); lcO2 = (LincombArgs *)(dev + oO2); lcU = (LincombArgs *)(dev + oU);
             cs = (ColsumJob *)(dev + oC); sp = (SpmmJob *)(dev + oP); flag_ptr = (int **)(dev + oF);
             stat_src = (const int **)(dev + oR); stat_dst = (int *)(dev + oT); jac = (JacobiJob *)(dev + oJ);
             mu = (double *)(dev + oM);
         }
         auto host = [&](const void *d) { return pin + ((const char *)d - dev); };
         GramJob *hgA = (GramJob *)host(gA), *hgW = (GramJob *)host(gW), *hgS = (GramJob *)host(gS);
-        LincombArgs *hlO = (LincombArgs *)host(lcO), *hlU = (LincombArgs *)host(lcU);
+        LincombArgs *hlO = (LincombArgs *)host(lcO), *hlO2 = (LincombArgs *)host(lcO2), *hlU = (LincombArgs *)host(lcU);
         ColsumJob *hcs = (ColsumJob *)host(cs);
         SpmmJob *hsp = (SpmmJob *)host(sp);
         int **hfl = (int **)host(flag_ptr);
@@ -555,11 +555,13 @@ struct BatchPlan {
             lo.in[0] = L.X; lo.in[1] = L.P; lo.in[2] = L.W; lo.out[0] = L.W; lo.coef = L.coef; lo.ldc = L.m;
             lo.nin = 3; lo.nout = 1; lo.nsets = 1; lo.m = L.m; lo.n = L.n;
             hlO[i] = lo;
+            lo.skip = &L.st_d->flags[0];   // phase B runs before the rank flag is read
+            hlO2[i] = lo;
             LincombArgs u{};
             u.in[0] = L.X; u.in[1] = L.W; u.in[2] = L.P; u.in[3] = L.AX; u.in[4] = L.AW; u.in[5] = L.AP;
             u.out[0] = L.X; u.out[1] = L.P; u.out[2] = L.AX; u.out[3] = L.AP;
             u.coef = L.rrcoef; u.ldc = 2 * L.m; u.nin = 3; u.nout = 2; u.nsets = 2; u.m = L.m; u.n = L.n;
-            u.theta = L.st_d->theta; u.res = L.W; u.norm_part = L.norm_part;
+            u.theta = L.st_d->theta; u.res = L.W; u.norm_part = L.norm_part; u.skip = &L.st_d->flags[0];
             hlU[i] = u;
             hcs[i] = ColsumJob{L.norm_part, lincomb_norm_parts(L.n), L.m, L.st_d->norms};
             hsp[i] = spmm_job(L.H, L.m, L.W, L.AW, L.spmm_part);
@@ -633,24 +635,12 @@ struct BatchPlan {
                 gram_batched(gA, count, 3 * m, m, maxpA, bs);
             }
             small_orth(o1.data(), count, bs);
-            gather_words(stat_src, stat_dst, (int)(sizeof(Status) / 4), count, bs);
-            Status *hst = (Status *)(pin + ((char *)stat_dst - dev));
-            HIPCHK(hipMemcpyAsync(hst, stat_dst, sizeof(Status) * (size_t)count, hipMemcpyDeviceToHost, bs));
-            HIPCHK(hipStreamSynchronize(bs));
-            // rare: deficient W blocks are repaired one by one (same stream)
-            for (int i = 0; i < count; i++) {
-                Lobpcg &L = *ctxs[(size_t)i];
-                L.st_h->flags[0] = hst[i].flags[0];
-                while (L.st_h->flags[0]) {
-                    L.repair_once();
-                    HIPCHK(hipStreamSynchronize(bs));
-                }
-            }
-            // ---- phase B: second stage, SpMM, Rayleigh-Ritz, update ----
+            // ---- phase B, enqueued at once: its launches that overwrite the
+            // basis skip a problem whose rank flag is set (see Lobpcg::phase_b) ----
             if (m == 16) {
-                lincomb_gram_batched(lcO, gW, count, 1, maxpW, bs);
+                lincomb_gram_batched(lcO2, gW, count, 1, maxpW, bs);
             } else {
-                lincomb_batched(lcO, count, max_n, bs);
+                lincomb_batched(lcO2, count, max_n, bs);
                 gram_batched(gW, count, m, m, maxpW, bs);
             }
             small_orth(o2.data(), count, bs);
@@ -660,13 +650,33 @@ struct BatchPlan {
             lincomb_batched(lcU, count, max_n, bs);
             colsum_batched(cs, count, m, bs);
             gather_words(stat_src, stat_dst, (int)(sizeof(Status) / 4), count, bs);
+            Status *hst = (Status *)(pin + ((char *)stat_dst - dev));
             HIPCHK(hipMemcpyAsync(hst, stat_dst, sizeof(Status) * (size_t)count, hipMemcpyDeviceToHost, bs));
             HIPCHK(hipStreamSynchronize(bs));
             for (int i = 0; i < count; i++) {
                 Lobpcg &L = *ctxs[(size_t)i];
-                memcpy(L.st_h, &hst[i], sizeof(Status));
                 L.rep.spmm_calls++;
-                L.rep.batched_iters++;
+                if (!hst[i].flags[0]) {
+                    memcpy(L.st_h, &hst[i], sizeof(Status));
+                    L.rep.batched_iters++;
+                    continue;
+                }
+                // rare: a deficient W; this problem's phase B wrote nothing to
+                // its basis.  Repair it alone (same stream) and rerun phase B.
+                const Status keep = *L.st_h;
+                int flag = hst[i].flags[0];
+                for (;;) {
+                    L.st_h->flags[0] = flag;
+                    do {
+                        L.repair_once();
+                        L.sync();
+                    } while (L.st_h->flags[0]);
+                    L.phase_b();
+                    L.sync();
+                    flag = L.st_h->flags[0];
+                    if (!flag) break;
+                    *L.st_h = keep;
+                }
             }
         } catch (...) {
             (void)hipStreamSynchronize(bs);

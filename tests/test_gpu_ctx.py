@@ -139,3 +139,38 @@ def test_batched_rounds_match_solo_solves():
         hs.lobpcg_ctx_destroy(c)
     for M in mats:
         M.close()
+
+
+def test_batched_rounds_repair_deficient_blocks():
+    """Small problems whose basis nearly fills the space (n close to 3m) lose
+    rank in W during batched rounds: the round's phase B then leaves such a
+    problem's basis untouched, and the problem is repaired alone and its
+    phase B rerun.  Every problem still reaches LAPACK's eigenvalues."""
+    import scipy.sparse as sp
+    cases = [(26, 61), (27, 62), (30, 63), (40, 64)]
+    mats, lams = [], []
+    for n, seed in cases:
+        A = hsymgen.generate(n, 12, seed)
+        U = sp.csr_matrix((A.values, A.colind, A.rowptr), shape=(n, n))
+        lams.append(np.linalg.eigvalsh((U + U.T - sp.diags(U.diagonal())).toarray()))
+        mats.append(hs.Matrix(A, geom_m=8))
+    ctxs = [hs.lobpcg_ctx_create(M.h, 3, 8, 1e-9, precond="jacobi",
+                                 opts=hs.default_lobpcg_opts(seed=k, keep_history=0, maxit=400))
+            for k, M in enumerate(mats)]
+    for _ in range(500):
+        hs.lobpcg_ctx_step(ctxs, iters=1)
+        if all(hs.lobpcg_ctx_status(c, 3)[0] for c in ctxs):
+            break
+    replaced = 0
+    for c, lam, (n, _) in zip(ctxs, lams, cases):
+        done, s, ev, rep = hs.lobpcg_ctx_status(c, 3)
+        print("n=%d: status %d, iters %d, batched %d, W columns replaced %d"
+              % (n, s, rep.iters, rep.batched_iters, rep.w_replaced))
+        replaced += rep.w_replaced
+        assert done and s == hs.HSYM_OK
+        assert np.max(np.abs(ev - lam[:3]) / np.abs(lam[:3])) <= 1e-8
+        hs.lobpcg_ctx_destroy(c)
+    for M in mats:
+        M.close()
+    print("W columns replaced in all:", replaced)
+    assert replaced > 0        # the repair path ran
