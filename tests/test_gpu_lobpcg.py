@@ -179,3 +179,45 @@ def test_lobpcg_m16_tiny_n(n):
     assert st == hs.HSYM_OK
     assert np.max(np.abs(evals - lam[:4]) / np.abs(lam[:4])) <= 1e-8
     certify(A, evals, vecs, 2e-9)
+
+
+def test_lobpcg_c2_bench_configuration():
+    """The solve the benchmark times (n = 500,000, about 300 nonzeros per full
+    row, fp64, m = 16, nev = 8, tol 1e-8, Jacobi), checked at full size by
+    properties that hold at any size, with the oracle's fp64 SpMM on the host:
+    residual norms within the stopping rule, orthonormal eigenvectors, Rayleigh
+    quotients equal to the returned eigenvalues, and the same eigenvalues from
+    Lanczos on the same matrix (another method; its residuals are certified
+    the same way, and two pairs with residuals r1, r2 and a gap g to the rest
+    of the spectrum agree to about (|r1|^2 + |r2|^2) / g)."""
+    A = hsymgen.config("C2")
+    dev = torch.device("cuda:0")
+    M = hs.Matrix(A, geom_m=16)
+    V = torch.zeros((A.n, 8), dtype=torch.float64, device=dev)
+    st, evals, rep = hs.lobpcg_solve(M.h, 8, 16, 1e-8, precond="jacobi", opts=hs.default_lobpcg_opts(seed=1), evecs=V)
+    VL = torch.zeros((A.n, 8), dtype=torch.float64, device=dev)
+    st2, e2, rep2 = hs.lanczos_solve(M.h, 8, 1e-8, seed=2, evecs=VL)
+    torch.cuda.synchronize()
+    M.close()
+    print("C2 lobpcg: status %d iters %d (%.3fs); lanczos: status %d iters %d (%.3fs)"
+          % (st, rep.iters, rep.seconds, st2, rep2.iters, rep2.seconds), flush=True)
+    assert st == hs.HSYM_OK and rep.converged
+    assert st2 == hs.HSYM_OK and rep2.converged
+    H = oracle.SymMatrix.from_csr(A)
+    nrm = H.norm1()
+    X = V.cpu().numpy()
+    HX = H.spmm(X)
+    rho = np.linalg.norm(HX - X * evals[None, :], axis=0) / nrm
+    G = X.T @ X
+    q = np.einsum("ij,ij->j", X, HX)
+    print("residuals / |H|_1", rho, "orthonormality %.1e" % np.max(np.abs(G - np.eye(8))),
+          "rayleigh %.1e" % (np.max(np.abs(q - evals)) / nrm), flush=True)
+    assert np.max(rho) <= 1.5e-8
+    assert np.max(np.abs(G - np.eye(8))) <= 1e-10
+    assert np.max(np.abs(q - evals)) <= 1e-12 * nrm
+    XL = VL.cpu().numpy()
+    rl = np.linalg.norm(H.spmm(XL) - XL * e2[None, :], axis=0) / nrm
+    print("lanczos residuals / |H|_1", rl, "eigenvalue agreement %.1e" % np.max(np.abs(evals - e2) / np.abs(e2)))
+    assert np.max(rl) <= 1e-7
+    assert np.all(np.diff(evals) >= 0)
+    assert np.max(np.abs(evals - e2) / np.abs(e2)) <= 1e-8
