@@ -114,7 +114,11 @@ def serving(hs, torch, count, seed=5):
     ns = np.round(10 ** rng.uniform(3, np.log10(2e6), count)).astype(np.int64)
     nevs = rng.integers(1, 9, count)
     t = time.perf_counter()
-    mats = [hsymgen.generate(int(n), 40, 1000 + r) for r, n in enumerate(ns)]
+    mats = []
+    for r, n in enumerate(ns):
+        mats.append(hsymgen.generate(int(n), 40, 1000 + r))
+        if (r + 1) % 250 == 0 and r + 1 < count:
+            log("serving: generated %d of %d requests" % (r + 1, count))
     log("serving: generated %d requests (%.0fM stored entries) in %.1fs" %
         (count, sum(A.nnz for A in mats) / 1e6, time.perf_counter() - t))
     svc = []
@@ -127,6 +131,8 @@ def serving(hs, torch, count, seed=5):
         M.close()
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - t)
+        if (r + 1) % 250 == 0 and r + 1 < count:
+            log("serving: sequential fp64 baseline, %d of %d solved" % (r + 1, count))
     svc = np.array(svc)
     rate = 2.0 * count / svc.sum()
     arr = np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, count))
