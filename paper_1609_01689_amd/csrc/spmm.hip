@@ -53,9 +53,9 @@ int spmm_lanes_per_entry(int storage, int m) {
 }
 
 size_t spmm_lds_bytes(int storage, int m, int R, int C) {
+    (void)storage;   // X is staged in fp64 for both storage precisions
     int M = round_m(m);
-    size_t es = storage == HSYM_FP64 ? 8 : 4;
-    return (size_t)(R + C) * M * (8 + es);
+    return (size_t)(R + C) * M * (8 + 8);
 }
 
 
@@ -100,9 +100,10 @@ __device__ __forceinline__ void read_row(const T *rowp, int r, int k0, double *o
     }
 }
 
-// T: stored values and staged X; products and sums are fp64 for both storage
-// precisions (a product of two fp32 numbers is exact in fp64, and the LDS fp64
-// atomic add is several times cheaper than the fp32 one on gfx950)
+// T: stored values.  X is staged in LDS as fp64 and products and sums are
+// fp64 for both storage precisions: an fp32 value is converted once per entry,
+// the X rows once per staging (the LDS fp64 atomic add is also several times
+// cheaper than the fp32 one on gfx950)
 // IT: uint16_t or uint32_t index codes, local row << cs | local column
 template <int M, typename T, typename XIN, typename YT, typename IT>
 __device__ __forceinline__ void spmm_panel_body(
@@ -111,13 +112,13 @@ __device__ __forceinline__ void spmm_panel_body(
     const T *__restrict__ vals, const T *__restrict__ diag, const XIN *__restrict__ X, int64_t ldx,
     YT *__restrict__ Y, int64_t ldy, double *__restrict__ partials, int64_t n, int R, int C, int G,
     int64_t npanels, int m, int64_t blk, unsigned char *smem_raw) {
-    using XL = RowLay<M, T, false>;
+    using XL = RowLay<M, double, false>;
     using AL = RowLay<M, double, true>;
     constexpr int NT = 1024, MW = mw_of(M), LPE = M / MW, GK = NT / LPE;
     double *acc = reinterpret_cast<double *>(smem_raw);
     double *ts = acc + (size_t)R * M;
-    T *xp = reinterpret_cast<T *>(ts + (size_t)C * M);
-    T *xs = xp + (size_t)R * M;
+    double *xp = ts + (size_t)C * M;
+    double *xs = xp + (size_t)R * M;
     const int tid = threadIdx.x, g = tid / LPE, q = tid % LPE, k0 = q * MW;
     const uint32_t cmask = (1u << cs) - 1u;   // 16-bit codes: local row << cs | local column
     const int64_t p = porder[blk];
@@ -126,8 +127,8 @@ __device__ __forceinline__ void spmm_panel_body(
 
     for (int i = tid; i < R * M; i += NT) {
         const int r = i / M, k = i - r * M;
-        T v = T(0);
-        if (r < nrow && k < m) v = (T)X[(row0 + r) * ldx + k];
+        double v = 0.0;
+        if (r < nrow && k < m) v = (double)X[(row0 + r) * ldx + k];
         xp[r * M + XL::phys(r, k)] = v;
         acc[i] = 0.0;
     }
@@ -141,8 +142,8 @@ __device__ __forceinline__ void spmm_panel_body(
             const int ncol = (int)((n - col0) < C ? (n - col0) : C);
             for (int i = tid; i < C * M; i += NT) {
                 const int r = i / M, k = i - r * M;
-                T v = T(0);
-                if (r < ncol && k < m) v = (T)X[(col0 + r) * ldx + k];
+                double v = 0.0;
+                if (r < ncol && k < m) v = (double)X[(col0 + r) * ldx + k];
                 xs[r * M + XL::phys(r, k)] = v;
                 ts[i] = 0.0;
             }
@@ -151,7 +152,7 @@ __device__ __forceinline__ void spmm_panel_body(
         // own tiles read and update the panel's rows directly; col0 - row0 is a
         // multiple of C (itself a multiple of 8), so a chunk row has the
         // swizzle of its panel row
-        const T *xsrc = ext ? xs : xp + (col0 - row0) * M;
+        const double *xsrc = ext ? xs : xp + (col0 - row0) * M;
         double *tgt = ext ? ts : acc + (col0 - row0) * M;
         const int len = td.len;
         for (int seg = g; seg < G; seg += GK) {
@@ -191,10 +192,10 @@ __device__ __forceinline__ void spmm_panel_body(
                             }
                         }
                         cur = r;
-                        read_row<M, T>(xp + r * M, r, k0, xr);
+                        read_row<M, double>(xp + r * M, r, k0, xr);
                     }
                     double xc[MW];
-                    read_row<M, T>(xsrc + c * M, c, k0, xc);
+                    read_row<M, double>(xsrc + c * M, c, k0, xc);
                     const double av = (double)a[u];
                     double *trow = tgt + c * M;
                     if constexpr (MW == 2 && AL::CPR >= 1) {
@@ -241,7 +242,7 @@ __device__ __forceinline__ void spmm_panel_body(
         const int r = i / M, k = i - r * M;
         if (k < m) {
             const int64_t row = row0 + r;
-            const double v = acc[r * M + AL::phys(r, k)] + (double)diag[row] * (double)xp[r * M + XL::phys(r, k)];
+            const double v = acc[r * M + AL::phys(r, k)] + (double)diag[row] * xp[r * M + XL::phys(r, k)];
             if constexpr (sizeof(YT) == 8) unsafeAtomicAdd(&Y[row * ldy + k], v);
             else Y[row * ldy + k] = (YT)v;
         }
@@ -346,7 +347,7 @@ template <int M, typename T, typename XIN, typename YT, typename IT>
 static void launch_typed(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y, int64_t ldy,
                          void *partials, hipStream_t s) {
     const DeviceTiles &dt = H->tiles;
-    size_t lds = (size_t)(dt.R + dt.C) * M * (sizeof(double) + sizeof(T));
+    size_t lds = spmm_lds_bytes(H->storage, m, dt.R, dt.C);
     auto kp = k_spmm_panel<M, T, XIN, YT, IT>;
     static std::once_flag attr_once;   // the 160 KB LDS limit, set once (threads may launch concurrently)
     std::call_once(attr_once, [&] {
@@ -403,7 +404,7 @@ static void batched_typed(const SpmmJob *jobs, const SpmmJob *host, int count, h
     size_t lds = 0;
     int64_t maxp = 0, maxr = 0;
     for (int i = 0; i < count; i++) {
-        lds = std::max(lds, (size_t)(host[i].R + host[i].C) * M * (sizeof(double) + sizeof(T)));
+        lds = std::max(lds, spmm_lds_bytes(HSYM_FP64, M, host[i].R, host[i].C));
         maxp = std::max(maxp, host[i].npanels);
         maxr = std::max(maxr, host[i].nred);
     }

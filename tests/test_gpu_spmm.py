@@ -196,8 +196,9 @@ def test_index_code_widths(storage):
         M = hs.Matrix(A, storage=storage, flags=flags)
         info = M.info
         assert info["index_bytes"] == width, (flags, info)
-        es = 8 if storage == hs.HSYM_FP64 else 4
-        m = 16 if (info["panel_rows"] + info["chunk_cols"]) * 16 * (8 + es) <= 160 * 1024 else 8
+        # LDS per row of the panel and of the chunk: an fp64 accumulator and
+        # the fp64-staged X row, for both storage precisions
+        m = 16 if (info["panel_rows"] + info["chunk_cols"]) * 16 * 16 <= 160 * 1024 else 8
         Xd = torch.from_numpy(X[:, :m].copy()).to(_dev())
         Yd = torch.empty_like(Xd)
         hs.spmm_sym(M.h, Xd, Yd)
