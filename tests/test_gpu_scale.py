@@ -3,7 +3,8 @@ nonzeros per full row (1.0e9 stored entries), built by streaming create.
 
 Checks (sampled where the full product is not formed on the host):
   - rows of H X at the start, middle and end of the matrix against the
-    oracle, for fp32 storage (fp64 and fp32 blocks) and fp64 storage;
+    oracle, for fp32 storage (fp64 blocks taken as they are, fp32 blocks) and
+    fp64 storage;
   - LOBPCG in the mixed form (fp32 storage) against the fp64 form, nev = 10,
     m = 16, tol 1e-6, Jacobi: both converge, and every eigenvalue of the
     mixed form is within 1e-6 relative of the fp64 one.
@@ -60,13 +61,14 @@ def test_c3_scale_mixed_vs_fp64():
     X = hsymgen.gauss_block(31, g.n, 16)
     Xd = torch.from_numpy(X).to(dev)
     X32 = X.astype(np.float32).astype(np.float64)
-    ref32 = reference_rows(g, X32, np.float32)
+    ref32 = reference_rows(g, X32, np.float32)         # fp32 values, X rounded to fp32
 
     h32 = stream(g, hs.HSYM_FP32, np.float32)
     Yd = torch.empty_like(Xd)
     hs.spmm_sym(h32, Xd, Yd)
     torch.cuda.synchronize()
-    check_rows(Yd.cpu().numpy(), ref32, 1e-12)        # fp32 operands, exact products, fp64 sums
+    # fp32 values, the fp64 block as it is, fp64 products and sums
+    check_rows(Yd.cpu().numpy(), reference_rows(g, X, np.float32), 1e-12)
     Yf = torch.empty((g.n, 16), dtype=torch.float32, device=dev)
     hs.spmm_sym_f32(h32, Xd.float(), Yf)
     torch.cuda.synchronize()
