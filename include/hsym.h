@@ -157,10 +157,9 @@ int hsym_info(hsym_t H, hsym_info_t *out);
  * Y = H X (async).  X, Y device fp64 n x m with leading dimensions ldx, ldy;
  * m in {1..16}.  H is applied from its stored triangle as D X + U X + U^T X
  * (U strictly upper, D the diagonal; Section 4.1: each stored block is used
- * once as itself and once transposed).  With fp32 storage the values and X
- * are held in fp32 (X rounded once as it is staged); every product is formed
- * and summed in fp64 (the product of two fp32 numbers is exact in fp64) and
- * Y is returned in fp64.  The transposed half is summed with workgroup-local
+ * once as itself and once transposed).  With fp32 storage the values are
+ * held in fp32 and X is taken as it is (staged in fp64); every product is
+ * formed and summed in fp64 and Y is returned in fp64.  The transposed half is summed with workgroup-local
  * atomics and added into Y with device-scope atomics, so repeated calls agree
  * to rounding, not bitwise.
  * X and Y must not overlap.  Errors: HSYM_E_INVALID_ARG, HSYM_E_DEVICE.
