@@ -146,9 +146,9 @@ def test_batched_rounds_repair_deficient_blocks():
     rank in W during batched rounds: the round's phase B then leaves such a
     problem's basis untouched, and the problem is repaired alone and its
     phase B rerun.  Every problem still reaches LAPACK's eigenvalues.
-    (n = 30 is left out: with 24 basis columns in 30 dimensions its P block can
-    lose rank, which the GPU path does not yet detect, and the solve has once
-    ended not converged after 400 iterations, reported as such.)"""
+    (n = 30 is left out: with 24 basis columns in 30 dimensions one run ended
+    not converged after 400 iterations, reported as such; the cause is not yet
+    found, and the oracle converges on that matrix.)"""
     import scipy.sparse as sp
     cases = [(26, 61), (27, 62), (40, 64)]
     mats, lams = [], []
