@@ -446,7 +446,10 @@ def lobpcg(A: SymMatrix, nev, m, tol, X0=None, precond="jacobi", maxit=1000, see
             W[:, bad] = G[:, bad]
             W = _project(W, [X, X])
             res.w_replaced += int(bad.sum())
-        W = Q
+        # second pass: a QR pivot r leaves the rounding of the projection,
+        # amplified by 1 / r, along X; projecting again and re-factoring
+        # restores X^T W = 0 to working precision (twice is enough)
+        W, _ = _householder(_project(Q, [X]))
         AW = Hx(W)
         if P is not None:
             for _ in range(2):
@@ -465,6 +468,14 @@ def lobpcg(A: SymMatrix, nev, m, tol, X0=None, precond="jacobi", maxit=1000, see
                     P = AP = None
                     res.p_dropped += 1
                 else:
+                    AP = sla.solve_triangular(Rp, AP.T, trans="T", lower=False).T
+                    P = Qp
+                    # second pass against [X W], the same transforms on AP
+                    C1 = X.T @ P
+                    C2 = W.T @ P
+                    P = P - X @ C1 - W @ C2
+                    AP = AP - AX @ C1 - AW @ C2
+                    Qp, Rp = np.linalg.qr(P)
                     AP = sla.solve_triangular(Rp, AP.T, trans="T", lower=False).T
                     P = Qp
         if P is None:
