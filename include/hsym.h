@@ -65,23 +65,24 @@ enum hsym_precond { HSYM_PRECOND_NONE = 0, HSYM_PRECOND_JACOBI = 1, HSYM_PRECOND
                                     memory (copied to the host, where the tiles are
                                     built; the copy is synchronous)                 */
 #define HSYM_BUILD_BLOCK64 0x2   /* also build the 64x64 block preconditioner factors */
-/* Store the tile-local index codes (local row and column packed together) in
- * 16 bits instead of 32 when the chunk width C is a power of two and
- * R * C <= 2^16 (Section 4.2: indices local to a block need only 16 bits):
- * 2 bytes less per stored entry, for a slightly slower SpMM.  Other
- * geometries keep 32-bit codes; hsym_info reports the width in use. */
+/* Accepted for compatibility: tile-local index codes (local row and column
+ * packed together, Section 4.2: indices local to a block need only 16 bits)
+ * are 16-bit whenever R * C <= 2^16, which the default geometries satisfy at
+ * block widths of 4 and more; hsym_info reports the width in use. */
 #define HSYM_INDEX16       0x4
 /* Tile geometry hint: the block width (1..16) the panel sizes are chosen for,
- * in bits 8..15 (0 = 16).  Any block width whose LDS footprint fits the chosen
- * geometry can be used with the handle; a narrower hint gives taller panels. */
+ * in bits 8..15 (0 = 16).  The tile streams are laid out for the lane groups
+ * of that width; other widths whose LDS footprint fits the geometry can be
+ * used with the handle, at lower efficiency. */
 #define HSYM_GEOM_M(m) (((m) & 0xff) << 8)
-/* Explicit panel geometry: R = 2^lr panel rows (6 <= lr <= 15) and C = 2^lc
- * chunk columns (3 <= lc <= lr), in bits 16..23 (0 = chosen from the block
- * width hint and n).  hsym_create fails with HSYM_E_INVALID_ARG when C does
- * not divide R, and spmm_sym with HSYM_E_UNSUPPORTED when the geometry does
- * not fit the LDS at the requested block width.  hsym_autotune_geometry
+/* Explicit panel geometry: R = 64 * r64 panel rows (1 <= r64 <= 255) and
+ * C = 2^lc chunk columns (3 <= lc <= 12, C dividing R), in bits 16..27
+ * (0 = chosen from the block width hint and n).  hsym_create fails with
+ * HSYM_E_INVALID_ARG when C does not divide R or the geometry does not fit
+ * the LDS at the hinted block width; spmm_sym fails with HSYM_E_UNSUPPORTED
+ * when it does not fit at the requested width.  hsym_autotune_geometry
  * returns such flags. */
-#define HSYM_GEOM_PANEL(lr, lc) ((((lr) & 0xf) << 16) | (((lc) & 0xf) << 20))
+#define HSYM_GEOM_PANEL(r64, lc) ((((r64) & 0xff) << 16) | (((lc) & 0xf) << 24))
 
 typedef struct hsym_matrix *hsym_t;
 typedef struct lobpcg_ctx *lobpcg_ctx_t;
@@ -96,10 +97,12 @@ typedef struct {
     int64_t npanels;
     int64_t ntiles;
     int64_t nslots;             /* tiles whose transposed half leaves the panel       */
-    int64_t padded_entries;     /* stored off-diagonal entries after slice padding    */
+    int64_t padded_entries;     /* stored off-diagonal entries after segment padding  */
     int64_t device_bytes;       /* device memory held by the handle                   */
     int has_block64;
     int index_bytes;            /* bytes of one tile-local index code: 2 or 4         */
+    int64_t npieces;            /* tiles after cutting them into pieces               */
+    int piece_entries;          /* entries per piece at most                          */
 } hsym_info_t;
 
 /*

@@ -16,9 +16,10 @@ extern "C" {
 
 /*
  * Block inner product G = [A_0 .. A_{na-1}]^T [B_0 .. B_{nb-1}] (Section 4.4,
- * "block inner product"): A and B are host arrays of na, nb (1..3) device
+ * "block inner product"): A and B are host arrays of na (1..3), nb (1..6) device
  * pointers to n x m blocks; G is device (na*m) x (nb*m) row-major.  Reduced
  * in a fixed order (bitwise reproducible).  Scratch is allocated per call.
+ * nb may be up to 6 (the Rayleigh-Ritz Gram of [X W P] against [X W P AX AW AP]).
  */
 int hsym_kernel_gram(int64_t n, int m, int na, const double *const *A, int nb, const double *const *B,
                      double *G, void *stream);
@@ -33,18 +34,28 @@ int hsym_kernel_lincomb(int64_t n, int m, int nin, const double *const *In, int 
                         const double *C, int ldc, void *stream);
 
 /*
- * Rayleigh-Ritz of eq. 9 on an orthonormal basis of nblk (1..3) blocks:
- * A is device k x k (k = nblk*m), symmetrised on input.  Eigenvalues by
- * bisection on Sturm counts of the Householder tridiagonal form, eigenvectors
- * by inverse iteration (accuracy: eigenvalues and residuals within a small
- * multiple of k * eps * ||A||).  Writes theta (device,
- * m lowest eigenvalues ascending), evals (device, all k), and coef (device
- * k x 2m): columns 0..m-1 the m lowest eigenvectors C_X, columns m..2m-1 an
- * orthonormal basis of the rows m..k-1 of C_X made orthogonal to C_X (the
- * coefficients of the next search direction; zero when nblk = 1).
+ * Rayleigh-Ritz of eq. 9 on a basis S of nblk (1..3) blocks of m columns
+ * (Algorithm 1, steps 7-9), k = nblk*m: G is device k x 2k row-major,
+ * [S^T S | S^T A S], each half symmetrised on input.  The basis is made
+ * orthonormal in coefficient space from S^T S: its Cholesky factor in the
+ * block order [X W P] is Gram-Schmidt of W against X and of P against X and
+ * W (a second factorisation follows when a pivot is below 1e-4); the third
+ * block is dropped when a pivot of its column-normalised projection is below
+ * 1e-4 or one of its columns makes an angle with a sine below 1e-5 with the
+ * span of the columns before it, reported in *p_dropped (host int, may be
+ * NULL).  Eigenvalues of the
+ * projected matrix by bisection on Sturm counts of the Householder
+ * tridiagonal form, eigenvectors by inverse iteration (accuracy: eigenvalues
+ * and residuals within a small multiple of k * eps * ||A|| when S^T S = I).
+ * Writes theta (device, m lowest eigenvalues ascending), evals (device, all
+ * eigenvalues of the kept basis), and coef (device k x 2m, for S as given):
+ * columns 0..m-1 the Ritz vectors C_X, columns m..2m-1 the coefficients of
+ * the next search direction: a basis of the components of S C_X outside the
+ * first block, orthonormal and orthogonal to S C_X (zero when nblk = 1);
+ * rows of a dropped block are zero.
  */
-int hsym_kernel_rayleigh_ritz(int nblk, int m, const double *A, double *theta, double *evals, double *coef,
-                              void *stream);
+int hsym_kernel_rayleigh_ritz(int nblk, int m, const double *G, double *theta, double *evals, double *coef,
+                              int *p_dropped, void *stream);
 
 /*
  * Preconditioner apply of eq. 11 in place on W (device n x m):

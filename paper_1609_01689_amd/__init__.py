@@ -38,9 +38,9 @@ def HSYM_GEOM_M(m: int) -> int:
     return (int(m) & 0xFF) << 8
 
 
-def HSYM_GEOM_PANEL(lr: int, lc: int) -> int:
-    """Explicit panel geometry: 2**lr panel rows, 2**lc chunk columns."""
-    return ((int(lr) & 0xF) << 16) | ((int(lc) & 0xF) << 20)
+def HSYM_GEOM_PANEL(r64: int, lc: int) -> int:
+    """Explicit panel geometry: 64 * r64 panel rows, 2**lc chunk columns."""
+    return ((int(r64) & 0xFF) << 16) | ((int(lc) & 0xF) << 24)
 
 
 class HsymError(RuntimeError):
@@ -58,7 +58,8 @@ class hsym_info_t(ctypes.Structure):
                 ("storage", ctypes.c_int), ("panel_rows", ctypes.c_int), ("chunk_cols", ctypes.c_int),
                 ("npanels", ctypes.c_int64), ("ntiles", ctypes.c_int64), ("nslots", ctypes.c_int64),
                 ("padded_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("has_block64", ctypes.c_int), ("index_bytes", ctypes.c_int)]
+                ("has_block64", ctypes.c_int), ("index_bytes", ctypes.c_int),
+                ("npieces", ctypes.c_int64), ("piece_entries", ctypes.c_int)]
 
 
 class lobpcg_opts(ctypes.Structure):
@@ -145,7 +146,7 @@ _SIGS = {
     # step-level entry points (include/hsym_kernels.h)
     "hsym_kernel_gram": [_i64, _int, _int, _vp, _int, _vp, _vp, _vp],
     "hsym_kernel_lincomb": [_i64, _int, _int, _vp, _int, _vp, _vp, _int, _vp],
-    "hsym_kernel_rayleigh_ritz": [_int, _int, _vp, _vp, _vp, _vp, _vp],
+    "hsym_kernel_rayleigh_ritz": [_int, _int, _vp, _vp, _vp, _vp, ctypes.POINTER(_int), _vp],
     "hsym_kernel_precond": [_vp, _int, _int, _vp, _vp, _dbl, _vp],
     "hsym_kernel_orthonormalize": [_i64, _int, _vp, _int, _vp, ctypes.c_uint64, ctypes.POINTER(_int), _vp],
 }
@@ -396,9 +397,13 @@ def hsym_kernel_lincomb(In, Out, C, stream=None):
                                             C.stride(0), _stream(stream)))
 
 
-def hsym_kernel_rayleigh_ritz(nblk, m, A, theta, evals, coef, stream=None):
-    return _check(lib().hsym_kernel_rayleigh_ritz(nblk, m, _dptr(A), _dptr(theta), _dptr(evals), _dptr(coef),
-                                                  _stream(stream)))
+def hsym_kernel_rayleigh_ritz(nblk, m, G, theta, evals, coef, stream=None):
+    """Rayleigh-Ritz on a basis S given G = [S^T S | S^T A S] (k x 2k device
+    fp64); returns 1 when the third block was dropped, else 0."""
+    dropped = _int(0)
+    _check(lib().hsym_kernel_rayleigh_ritz(nblk, m, _dptr(G), _dptr(theta), _dptr(evals), _dptr(coef),
+                                           ctypes.byref(dropped), _stream(stream)))
+    return dropped.value
 
 
 def hsym_kernel_precond(h, kind, W, mu, delta, stream=None):

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <thread>
 
@@ -53,46 +54,89 @@ void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, in
     if (errst) fail(errst, err);
 }
 
-void geometry_for(int storage, int m, int64_t n, int lr, int lc, int *R, int *C, int *G) {
-    // Panel rows R and chunk columns C = R/4: the largest power-of-two R for
-    // which the panel accumulator, the panel's X rows, the staged X chunk and
-    // the chunk's transposed accumulator fit the 160 KB LDS of a gfx950 CU.
+// LDS of the SpMM at block width m (spmm.hip): fp64 accumulators for the
+// panel rows and the chunk rows, the panel's and the chunk's X rows in the
+// arithmetic precision (that of the storage), and the staged codes, perm and
+// values of one piece.
+size_t spmm_lds_bytes(int storage, int m, const Geom &g) {
+    const size_t M = (size_t)round_m(m), sa = storage == HSYM_FP64 ? 8 : 4;
+    auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
+    return (size_t)(g.R + g.C) * M * (8 + sa) + r16((size_t)g.maxe * g.idx_bytes) + r16((size_t)g.maxe * 2) +
+           r16((size_t)g.maxe * sa);
+}
+
+// Lane groups of the 1024-thread SpMM workgroup at block width M: a group
+// holds one 16-byte piece of an X row per lane (the whole row when it is
+// shorter), so the number of groups (segments per piece) is 1024 divided by
+// the lanes one row needs.
+static int segments_for(int storage, int M) {
+    const int sa = storage == HSYM_FP64 ? 8 : 4;
+    const int mw = M * sa >= 16 ? 16 / sa : M;
+    return 1024 / (M / mw);
+}
+
+Geom geometry_for(int storage, int m, int64_t n, int r64, int lc) {
+    const int M = round_m(m);
     const size_t budget = 160 * 1024;
-    int r = 65536;
-    while (r > 64 && spmm_lds_bytes(storage, m, r, r / 4) > budget) r /= 2;
-    // keep at least one panel per CU (256 CUs) when n allows
-    while (r > 256 && (int64_t)r * 256 > n) r /= 2;
-    int c = r / 4;
-    if (lr > 0) {
+    const int sa = storage == HSYM_FP64 ? 8 : 4;
+    Geom g;
+    g.G = segments_for(storage, M);
+    auto fill = [&](int R, int C) -> bool {
+        g.R = R;
+        g.C = C;
+        g.cb = 0;
+        while ((1 << g.cb) < C) g.cb++;
+        g.idx_bytes = (int64_t)R * C <= 65536 ? 2 : 4;
+        g.maxe = 0;
+        const size_t fixed = spmm_lds_bytes(storage, M, g);
+        if (fixed + 64 > budget) return false;
+        // entries per piece: what is left of the LDS, a multiple of 8, and the
+        // perm codes of a piece index at most 2^16 positions
+        const size_t eb = (size_t)g.idx_bytes + 2 + sa;
+        int64_t e = (int64_t)((budget - fixed - 64) / eb);
+        // a piece is staged through registers: at most 4 units of 16 bytes per
+        // thread of the workgroup, three streams each rounded up to 16 bytes
+        e = std::min<int64_t>(e, ((int64_t)4 * 1024 - 3) * 16 / (int64_t)eb);
+        e = std::min<int64_t>(e, 16384) & ~(int64_t)7;
+        g.maxe = (int)e;
+        return spmm_lds_bytes(storage, M, g) <= budget;
+    };
+    if (r64 > 0) {
         // explicit geometry (hsym_create flags, e.g. from the autotuner)
-        if (lr > 16 || lc < 3 || lc > 16) fail(HSYM_E_INVALID_ARG, "panel geometry exponents out of range");
-        r = 1 << lr;
-        c = 1 << lc;
-    } else {
-        const char *er = getenv("HSYM_PANEL_ROWS");
-        const char *ec = getenv("HSYM_CHUNK_COLS");
-        if (er) r = atoi(er);
-        if (ec) c = atoi(ec);
+        const int R = 64 * r64, C = 1 << lc;
+        if (lc < 3 || lc > 12 || C > R || R % C || (int64_t)C * M > 4096)
+            fail(HSYM_E_INVALID_ARG, "panel geometry must have C = 2^lc (3 <= lc <= 12) dividing R = 64 * r64");
+        if (!fill(R, C) || g.maxe < 256)
+            fail(HSYM_E_INVALID_ARG, "panel geometry does not fit the LDS at the geometry block width");
+        return g;
     }
-    // the SpMM relies on chunks tiling panels and on chunk rows sharing the
-    // LDS swizzle of their panel rows (a multiple of 8)
-    if (r < 64 || r > 65536 || c < 8 || c % 8 || r % c)
-        fail(HSYM_E_INVALID_ARG, "panel geometry must have 64 <= R <= 65536, C a multiple of 8 dividing R");
-    *R = r;
-    *C = c;
-    // one segment per lane group of the 1024-thread workgroup at this width
-    *G = 1024 / spmm_lanes_per_entry(storage, m);
+    // Tallest panels first (fewer panels share each chunk's transposed sums),
+    // at least one panel per CU (256) when n allows; chunks of 128 or 64
+    // columns (64 or more keeps the per-piece barriers rare); 16-bit codes at
+    // block widths of 4 and more; at least 2048 entries per piece.
+    const int64_t rmax = std::max<int64_t>(64, std::min<int64_t>(4096, (n / 256) / 64 * 64));
+    for (int64_t R = rmax; R >= 64; R -= 64) {
+        for (int C : {128, 64}) {
+            if (C > R || R % C) continue;
+            if (M >= 4 && R * C > 65536) continue;
+            if ((int64_t)C * M > 4096) continue;
+            if (fill((int)R, C) && g.maxe >= 2048) return g;
+        }
+    }
+    if (!fill(64, 64) || g.maxe < 256) fail(HSYM_E_UNSUPPORTED, "no panel geometry fits the LDS at this block width");
+    return g;
 }
 
 // ---------------------------------------------------------------------------
 // one panel
 // ---------------------------------------------------------------------------
 struct PanelOut {
-    std::vector<TileDesc> tiles;      // base relative to the panel
-    std::vector<uint32_t> idx;
+    std::vector<TileDesc> tiles;      // pieces, base relative to the panel
+    std::vector<uint32_t> idx;        // codes (narrowed to 16 bits on upload when the geometry allows)
+    std::vector<uint16_t> perm;
     std::vector<double> v64;
     std::vector<float> v32;
-    std::vector<int32_t> ext_chunks;  // chunk of every external tile, in order
+    int64_t next = 0;                 // external tiles
     std::vector<double> colsum;       // |a| summed per column, window [r0, r0 + size)
     double rowsum_max = 0.0;
     int64_t nnz = 0;                  // stored entries incl. diagonal
@@ -129,7 +173,7 @@ static void block64_factor(int64_t c0, int sz, int64_t slab_row0, const int64_t 
 
 // Rows [r0, r1) of the matrix; rp/ci/v index the caller's slab whose first row
 // is slab_row0.  dg receives the diagonal of the panel rows.
-static void build_panel(int64_t n, int64_t r0, int64_t r1, int R, int C, int G, int cs, int storage, bool b64,
+static void build_panel(int64_t n, int64_t r0, int64_t r1, const Geom &geo, int storage, bool b64,
                         int64_t slab_row0, const int64_t *rp, const int32_t *ci,
                         const double *vin64, const float *vin32, double *dg, PanelOut &out) {
     const int nr = (int)(r1 - r0);
@@ -173,47 +217,88 @@ static void build_panel(int64_t n, int64_t r0, int64_t r1, int R, int C, int G, 
         for (int64_t c0 = r0; c0 < r1; c0 += 64)
             block64_factor(c0, (int)std::min<int64_t>(64, r1 - c0), slab_row0, rp, ci, vin64, vin32, out);
 
+    const int C = geo.C, G = geo.G, cb = geo.cb;
     const int64_t gmin = r0 / C, gmax = maxcol / C;
     std::vector<int> cnt(nr);
+    std::vector<int32_t> tr, tc;      // one tile's entries: local row, local column
+    std::vector<int64_t> tp;          // and their positions in the slab
+    std::vector<int32_t> colcnt((size_t)C + 1), order;
     for (int64_t g = gmin; g <= gmax; g++) {
         const int64_t cend = (g + 1) * (int64_t)C;
-        int64_t nnz = 0;
-        int last = -1;
+        tr.clear(); tc.clear(); tp.clear();
         for (int i = 0; i < nr; i++) {
             int64_t p = cur[i];
-            while (p < end[i] && ci[p] < cend) p++;
-            cnt[i] = (int)(p - cur[i]);
-            nnz += cnt[i];
-            if (cnt[i]) last = i;
-        }
-        if (!nnz) continue;
-        TileDesc td;
-        td.base = (int64_t)out.idx.size();
-        td.len = (int32_t)((nnz + G - 1) / G);
-        td.chunk = (int32_t)g;
-        bool ext = g * (int64_t)C >= r0 + R;
-        td.slot = ext ? (int32_t)out.ext_chunks.size() : -1;
-        td.pad = 0;
-        if (ext) out.ext_chunks.push_back((int32_t)g);
-        out.tiles.push_back(td);
-        const size_t sz = (size_t)td.len * G;
-        const size_t b0 = out.idx.size();
-        // padding: zero values on the last row (keeps a segment's row run unbroken)
-        out.idx.resize(b0 + sz, (uint32_t)last << cs);
-        if (storage == HSYM_FP64) out.v64.resize(b0 + sz, 0.0);
-        else out.v32.resize(b0 + sz, 0.0f);
-        int64_t logical = 0;
-        for (int i = 0; i < nr; i++) {
-            for (int e = 0; e < cnt[i]; e++, logical++) {
-                int64_t p = cur[i] + e;
-                const int64_t seg = logical / td.len, pos = logical - seg * td.len;
-                const size_t at = b0 + (size_t)pos * G + (size_t)seg;
-                out.idx[at] = ((uint32_t)i << cs) | (uint32_t)(ci[p] - g * (int64_t)C);
-                if (storage == HSYM_FP64) out.v64[at] = vin64 ? vin64[p] : (double)vin32[p];
-                else out.v32[at] = vin64 ? (float)vin64[p] : vin32[p];
+            for (; p < end[i] && ci[p] < cend; p++) {
+                tr.push_back(i);
+                tc.push_back((int32_t)(ci[p] - g * (int64_t)C));
+                tp.push_back(p);
             }
+            cnt[i] = (int)(p - cur[i]);
         }
         for (int i = 0; i < nr; i++) cur[i] += cnt[i];
+        const int64_t tcnt = (int64_t)tr.size();
+        if (!tcnt) continue;
+        const bool ext = g * (int64_t)C >= r0 + geo.R;
+        if (ext) out.next++;
+        // pieces of consecutive row-major entries, at most maxe positions
+        // after padding to a whole number of steps of G segments
+        const int64_t cut = (int64_t)(geo.maxe / G) * G;
+        if (cut < 1) fail(HSYM_E_INVALID_ARG, "panel geometry leaves no room for a piece");
+        for (int64_t q0 = 0; q0 < tcnt; q0 += cut) {
+            const int pc = (int)std::min<int64_t>(cut, tcnt - q0);
+            const int len = (pc + G - 1) / G;
+            const int64_t E = (int64_t)G * len;
+            const int64_t base = ((int64_t)out.idx.size() + 7) & ~(int64_t)7;
+            const int64_t last = q0 + pc - 1;
+            const uint32_t lastcode = ((uint32_t)tr[last] << cb) | (uint32_t)tc[last];
+            out.idx.resize((size_t)(base + E), lastcode);
+            out.perm.resize((size_t)(base + E), 0);
+            if (storage == HSYM_FP64) out.v64.resize((size_t)(base + E), 0.0);
+            else out.v32.resize((size_t)(base + E), 0.0f);
+            // the alignment gap before base repeats a code with value 0 too
+            for (int64_t q = 0; q < pc; q++) {
+                const int64_t at = base + (q % len) * G + q / len;
+                const int64_t k = q0 + q, p = tp[(size_t)k];
+                out.idx[(size_t)at] = ((uint32_t)tr[(size_t)k] << cb) | (uint32_t)tc[(size_t)k];
+                if (storage == HSYM_FP64) out.v64[(size_t)at] = vin64 ? vin64[p] : (double)vin32[p];
+                else out.v32[(size_t)at] = vin64 ? (float)vin64[p] : vin32[p];
+            }
+            // column-major order of the piece (a stable counting sort by
+            // column keeps rows ascending within a column)
+            std::fill(colcnt.begin(), colcnt.end(), 0);
+            for (int q = 0; q < pc; q++) colcnt[(size_t)tc[(size_t)(q0 + q)] + 1]++;
+            for (int c = 0; c < C; c++) colcnt[(size_t)c + 1] += colcnt[(size_t)c];
+            order.assign((size_t)pc, 0);
+            for (int q = 0; q < pc; q++) order[(size_t)colcnt[(size_t)tc[(size_t)(q0 + q)]]++] = q;
+            // padding positions of the column order point at a padding
+            // position of the row order (value 0), which exists when E > pc
+            const int64_t padpos = E > pc ? ((int64_t)pc % len) * G + pc / len : 0;
+            for (int64_t q = 0; q < E; q++) {
+                const int64_t at = base + (q % len) * G + q / len;
+                int64_t src = padpos;
+                if (q < pc) {
+                    const int64_t o = order[(size_t)q];
+                    src = (o % len) * G + o / len;
+                }
+                out.perm[(size_t)at] = (uint16_t)src;
+            }
+            TileDesc td;
+            td.base = base;
+            td.len = len;
+            td.chunk = (int32_t)g;
+            td.ext = ext ? 1 : 0;
+            td.flags = (q0 == 0 ? TILE_FIRST : 0) | (q0 + pc == tcnt ? TILE_LAST : 0);
+            out.tiles.push_back(td);
+        }
+    }
+    // a whole number of 8-entry groups per panel keeps every base aligned
+    const size_t tot = (out.idx.size() + 7) & ~(size_t)7;
+    if (tot != out.idx.size()) {
+        const uint32_t lc = out.idx.empty() ? 0u : out.idx.back();
+        out.idx.resize(tot, lc);
+        out.perm.resize(tot, 0);
+        if (storage == HSYM_FP64) out.v64.resize(tot, 0.0);
+        else out.v32.resize(tot, 0.0f);
     }
 }
 
@@ -246,9 +331,8 @@ struct DevVec {
 };
 
 struct Builder {
-    int R = 0, C = 0, G = 256;
-    bool idx16 = false;             // 16-bit index codes (shift log2 C)
-    int cs = 16;                    // code shift: local row << cs | local column
+    Geom geo;
+    int R = 0;
     int storage = HSYM_FP64;
     bool b64 = false;
     DevVec<double> preq, prelam;
@@ -265,18 +349,18 @@ struct Builder {
     DevVec<TileDesc> tiles;
     DevVec<uint32_t> idx;
     DevVec<uint16_t> idx16v;
+    DevVec<uint16_t> perm;
     DevVec<double> v64;
     DevVec<float> v32;
     std::vector<int64_t> panel_tile_ptr{0};
-    std::vector<int64_t> panel_weight;  // per panel: padded entries + a per-tile cost, in entry units
-    std::vector<int32_t> slot_chunk;   // chunk of every slot
+    std::vector<int64_t> panel_weight;  // per panel: padded entries + a per-piece cost, in entry units
     std::vector<double> diag;          // n
     std::vector<double> abssum;        // n: row+column absolute sums
     double norm1 = 0.0;
-    int64_t nentries = 0, ntiles = 0;
+    int64_t nentries = 0, npieces = 0, ntiles = 0, next = 0;
 
     void release() {
-        tiles.release(); idx.release(); idx16v.release(); v64.release(); v32.release();
+        tiles.release(); idx.release(); idx16v.release(); perm.release(); v64.release(); v32.release();
         preq.release(); prelam.release();
     }
 
@@ -291,13 +375,14 @@ struct Builder {
                 for (int64_t k = a; k < b; k++) {
                     int64_t p = b0 + k;
                     int64_t r0 = p * R, r1 = std::min(n, r0 + R);
-                    build_panel(n, r0, r1, R, C, G, cs, storage, b64, slab_row0, rp, ci, vin64, vin32,
+                    build_panel(n, r0, r1, geo, storage, b64, slab_row0, rp, ci, vin64, vin32,
                                 diag.data() + r0, outs[(size_t)k]);
                 }
             });
             // concatenate in panel order
             std::vector<TileDesc> t;
             std::vector<uint32_t> c;
+            std::vector<uint16_t> pm;
             std::vector<double> d64;
             std::vector<float> d32;
             std::vector<double> pq, pl;
@@ -305,24 +390,24 @@ struct Builder {
                 PanelOut &o = outs[(size_t)k];
                 int64_t r0 = (b0 + k) * R;
                 int64_t entry_off = nentries + (int64_t)c.size();
-                int32_t slot_off = (int32_t)slot_chunk.size();
                 for (auto td : o.tiles) {
                     td.base += entry_off;
-                    if (td.slot >= 0) td.slot += slot_off;
                     t.push_back(td);
+                    if (td.flags & TILE_FIRST) ntiles++;
                 }
                 c.insert(c.end(), o.idx.begin(), o.idx.end());
+                pm.insert(pm.end(), o.perm.begin(), o.perm.end());
                 d64.insert(d64.end(), o.v64.begin(), o.v64.end());
                 d32.insert(d32.end(), o.v32.begin(), o.v32.end());
-                for (int32_t g : o.ext_chunks) slot_chunk.push_back(g);
+                next += o.next;
                 pq.insert(pq.end(), o.preq.begin(), o.preq.end());
                 pl.insert(pl.end(), o.prelam.begin(), o.prelam.end());
                 panel_tile_ptr.push_back(panel_tile_ptr.back() + (int64_t)o.tiles.size());
                 {
-                    // a tile's fixed cost (staging its X chunk, barriers, writing its sums)
-                    // is about that of 1,200 entries at m = 16
-                    int64_t wgt = 1200 * (int64_t)o.tiles.size();
-                    for (const auto &td : o.tiles) wgt += (int64_t)td.len * G;
+                    // a piece's fixed cost (two barriers, staging, the transposed
+                    // sums of an external tile) is about that of 600 entries
+                    int64_t wgt = 600 * (int64_t)o.tiles.size();
+                    for (const auto &td : o.tiles) wgt += (int64_t)td.len * geo.G;
                     panel_weight.push_back(wgt);
                 }
                 for (size_t w = 0; w < o.colsum.size(); w++) abssum[(size_t)r0 + w] += o.colsum[w];
@@ -330,16 +415,17 @@ struct Builder {
                 PanelOut().tiles.swap(o.tiles);
             }
             tiles.append(t.data(), (int64_t)t.size());
-            if (idx16) {
+            if (geo.idx_bytes == 2) {
                 std::vector<uint16_t> c16(c.begin(), c.end());
                 idx16v.append(c16.data(), (int64_t)c16.size());
             } else {
                 idx.append(c.data(), (int64_t)c.size());
             }
+            perm.append(pm.data(), (int64_t)pm.size());
             if (storage == HSYM_FP64) v64.append(d64.data(), (int64_t)d64.size());
             else v32.append(d32.data(), (int64_t)d32.size());
             if (b64) { preq.append(pq.data(), (int64_t)pq.size()); prelam.append(pl.data(), (int64_t)pl.size()); }
-            ntiles += (int64_t)t.size();
+            npieces += (int64_t)t.size();
             nentries += (int64_t)c.size();
             npanels_done = b1;
         }
@@ -418,29 +504,23 @@ static Builder *builder_of(hsym_matrix *H) {
 namespace hsym {
 
 void builder_begin(hsym_matrix *H, int64_t nnz_hint) {
-    Builder *b = new Builder();
+    const Geom geo = geometry_for(H->storage, H->geom_m, H->n, H->geom_r64, H->geom_lc);
+    std::unique_ptr<Builder> b(new Builder());
     b->n = H->n;
     b->storage = H->storage;
     b->b64 = (H->flags & HSYM_BUILD_BLOCK64) != 0;
-    geometry_for(H->storage, H->geom_m, H->n, H->geom_lr, H->geom_lc, &b->R, &b->C, &b->G);
-    if (b->G < 1) fail(HSYM_E_INVALID_ARG, "bad segment count");
-    if (b->R % b->C != 0 || b->C > 65536 || b->R > 65535)
-        fail(HSYM_E_INVALID_ARG, "panel rows must be a multiple of chunk columns (<= 65535)");
-    // 16-bit codes on request, when a tile's local row and column fit in 16 bits together
-    if ((H->flags & HSYM_INDEX16) && (b->C & (b->C - 1)) == 0 && (int64_t)b->R * b->C <= 65536) {
-        b->idx16 = true;
-        b->cs = 0;
-        while ((1 << b->cs) < b->C) b->cs++;
-    }
+    b->geo = geo;
+    b->R = geo.R;
     b->diag.assign((size_t)H->n, 0.0);
     b->abssum.assign((size_t)H->n, 0.0);
     if (nnz_hint > 0) {
         int64_t est = nnz_hint + nnz_hint / 8 + 4096;
-        if (b->idx16) b->idx16v.reserve(est); else b->idx.reserve(est);
+        if (geo.idx_bytes == 2) b->idx16v.reserve(est); else b->idx.reserve(est);
+        b->perm.reserve(est);
         if (H->storage == HSYM_FP64) b->v64.reserve(est); else b->v32.reserve(est);
     }
     std::lock_guard<std::mutex> g(g_builders_mu);
-    g_builders.push_back({H, b});
+    g_builders.push_back({H, b.release()});
 }
 
 void builder_append(hsym_matrix *H, int64_t nrows, const int64_t *rp, const int32_t *ci,
@@ -467,21 +547,30 @@ void builder_finish(hsym_matrix *H) {
     if (b->next_row != H->n || b->carry_rp.size() != 1)
         fail(HSYM_E_INVALID_ARG, "streaming create finished before all n rows were appended");
     DeviceTiles &dt = H->tiles;
-    dt.R = b->R; dt.C = b->C; dt.G = b->G;
+    // 16 more positions at the end of every stream: the SpMM stages a piece
+    // in whole 16-byte loads, which may read past its last position
+    {
+        std::vector<uint32_t> z32(16, 0);
+        std::vector<uint16_t> z16(16, 0);
+        std::vector<double> zd(16, 0.0);
+        std::vector<float> zf(16, 0.0f);
+        if (b->geo.idx_bytes == 2) b->idx16v.append(z16.data(), 16); else b->idx.append(z32.data(), 16);
+        b->perm.append(z16.data(), 16);
+        if (H->storage == HSYM_FP64) b->v64.append(zd.data(), 16); else b->v32.append(zf.data(), 16);
+    }
+    dt.g = b->geo;
     dt.npanels = (H->n + b->R - 1) / b->R;
-    dt.nchunks = (H->n + b->C - 1) / b->C;
-    dt.ntiles = b->ntiles; dt.nentries = b->nentries;
-    dt.nslots = (int64_t)b->slot_chunk.size();
+    dt.nchunks = (H->n + b->geo.C - 1) / b->geo.C;
+    dt.ntiles = b->ntiles; dt.npieces = b->npieces; dt.nentries = b->nentries; dt.next = b->next;
     dt.tiles = b->tiles.p;
-    dt.idx = b->idx16 ? (void *)b->idx16v.p : (void *)b->idx.p;
-    dt.idx_bytes = b->idx16 ? 2 : 4;
-    dt.idx_shift = b->cs;
+    dt.idx = b->geo.idx_bytes == 2 ? (void *)b->idx16v.p : (void *)b->idx.p;
+    dt.perm = b->perm.p;
     dt.vals = H->storage == HSYM_FP64 ? (void *)b->v64.p : (void *)b->v32.p;
-    const int64_t idx_cap_bytes = b->idx16 ? b->idx16v.cap * 2 : b->idx.cap * 4;
-    b->tiles.p = nullptr; b->idx.p = nullptr; b->idx16v.p = nullptr;
+    const int64_t idx_cap_bytes = b->geo.idx_bytes == 2 ? b->idx16v.cap * 2 : b->idx.cap * 4;
+    b->tiles.p = nullptr; b->idx.p = nullptr; b->idx16v.p = nullptr; b->perm.p = nullptr;
     b->v64.p = nullptr; b->v32.p = nullptr;
     int vs = H->storage == HSYM_FP64 ? 8 : 4;
-    dt.bytes = b->tiles.cap * (int64_t)sizeof(TileDesc) + idx_cap_bytes +
+    dt.bytes = b->tiles.cap * (int64_t)sizeof(TileDesc) + idx_cap_bytes + b->perm.cap * 2 +
                (H->storage == HSYM_FP64 ? b->v64.cap : b->v32.cap) * vs;
     // panel pointers
     HIPCHK(hipMalloc(&dt.panel_tile_ptr, sizeof(int64_t) * b->panel_tile_ptr.size()));
@@ -490,10 +579,10 @@ void builder_finish(hsym_matrix *H) {
     dt.bytes += (int64_t)(sizeof(int64_t) * b->panel_tile_ptr.size());
     // workgroup -> panel.  The dispatcher deals workgroups round-robin to the
     // 8 XCDs (workgroup b to XCD b mod 8).  XCD x gets a contiguous run of
-    // panels, so the X chunks that neighbouring panels share stay in its L2.
-    // With few panels per CU it takes them heaviest first, so that its CUs
-    // end on light panels (list scheduling; the panels' loads differ by up to
-    // 2x); with many, in row order, which keeps more chunk reuse in L2.
+    // panels, so the X chunks and the rows of Y that neighbouring panels share
+    // stay in its L2.  With few panels per CU it takes them heaviest first, so
+    // that its CUs end on light panels (list scheduling; the panels' loads
+    // differ by up to 2x); with many, in row order, which keeps more reuse in L2.
     {
         const int64_t P = dt.npanels, q = P >> 3, rem = P & 7;
         const bool heavy_first = P < 16 * 256;
@@ -513,23 +602,6 @@ void builder_finish(hsym_matrix *H) {
             HIPCHK(hipMemcpy(dt.panel_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice));
         dt.bytes += (int64_t)(sizeof(int32_t) * order.size());
     }
-    // reduction lists: slots per output chunk in panel order
-    std::vector<int64_t> rptr((size_t)dt.nchunks + 1, 0);
-    for (int32_t g : b->slot_chunk) rptr[(size_t)g + 1]++;
-    for (int64_t g = 0; g < dt.nchunks; g++) rptr[(size_t)g + 1] += rptr[(size_t)g];
-    std::vector<int32_t> rs(b->slot_chunk.size());
-    std::vector<int64_t> fill(rptr.begin(), rptr.end() - 1);
-    for (size_t s = 0; s < b->slot_chunk.size(); s++) rs[(size_t)fill[(size_t)b->slot_chunk[s]]++] = (int32_t)s;
-    std::vector<int32_t> rc;
-    for (int64_t g = 0; g < dt.nchunks; g++) if (rptr[(size_t)g + 1] > rptr[(size_t)g]) rc.push_back((int32_t)g);
-    dt.nred_chunks = (int64_t)rc.size();
-    HIPCHK(hipMalloc(&dt.red_ptr, sizeof(int64_t) * rptr.size()));
-    HIPCHK(hipMemcpy(dt.red_ptr, rptr.data(), sizeof(int64_t) * rptr.size(), hipMemcpyHostToDevice));
-    HIPCHK(hipMalloc(&dt.red_slot, sizeof(int32_t) * std::max<size_t>(1, rs.size())));
-    if (!rs.empty()) HIPCHK(hipMemcpy(dt.red_slot, rs.data(), sizeof(int32_t) * rs.size(), hipMemcpyHostToDevice));
-    HIPCHK(hipMalloc(&dt.red_chunks, sizeof(int32_t) * std::max<size_t>(1, rc.size())));
-    if (!rc.empty()) HIPCHK(hipMemcpy(dt.red_chunks, rc.data(), sizeof(int32_t) * rc.size(), hipMemcpyHostToDevice));
-    dt.bytes += (int64_t)(sizeof(int64_t) * rptr.size() + 4 * rs.size() + 4 * rc.size());
     // diagonal in both precisions and ||H||_1
     H->d_host = b->diag;
     std::vector<float> d32(b->diag.size());
@@ -554,8 +626,7 @@ void builder_finish(hsym_matrix *H) {
 }
 
 void free_tiles(DeviceTiles *dt) {
-    void *ptrs[] = {dt->panel_tile_ptr, dt->panel_order, dt->tiles, dt->idx, dt->vals,
-                    dt->red_ptr, dt->red_slot, dt->red_chunks};
+    void *ptrs[] = {dt->panel_tile_ptr, dt->panel_order, dt->tiles, dt->idx, dt->perm, dt->vals};
     for (void *p : ptrs) if (p) (void)hipFree(p);
     *dt = DeviceTiles();
 }

@@ -101,9 +101,9 @@ int hsym_create_begin(hsym_t *out, int64_t n, int storage, int flags, void *stre
     H->storage = storage;
     H->flags = flags;
     H->geom_m = geom_from_flags(flags);
-    H->geom_lr = (flags >> 16) & 0xf;
-    H->geom_lc = (flags >> 20) & 0xf;
-    if (H->geom_lr && !H->geom_lc) H->geom_lc = H->geom_lr - 2;
+    H->geom_r64 = (flags >> 16) & 0xff;
+    H->geom_lc = (flags >> 24) & 0xf;
+    if (H->geom_r64 && !H->geom_lc) fail(HSYM_E_INVALID_ARG, "explicit panel geometry needs the chunk exponent");
     H->stream = (hipStream_t)stream;
     HIPCHK(hipGetDevice(&H->device));
     try {
@@ -282,15 +282,17 @@ int hsym_info(hsym_t H, hsym_info_t *o) {
     o->nnz_stored = H->nnz;
     o->norm1 = H->norm1;
     o->storage = H->storage;
-    o->panel_rows = H->tiles.R;
-    o->chunk_cols = H->tiles.C;
+    o->panel_rows = H->tiles.g.R;
+    o->chunk_cols = H->tiles.g.C;
     o->npanels = H->tiles.npanels;
     o->ntiles = H->tiles.ntiles;
-    o->nslots = H->tiles.nslots;
+    o->nslots = H->tiles.next;
     o->padded_entries = H->tiles.nentries;
     o->device_bytes = H->bytes;
     o->has_block64 = H->pre_q != nullptr;
-    o->index_bytes = H->tiles.idx_bytes;
+    o->index_bytes = H->tiles.g.idx_bytes;
+    o->npieces = H->tiles.npieces;
+    o->piece_entries = H->tiles.g.maxe;
     API_END
 }
 
@@ -304,16 +306,7 @@ static void check_block(hsym_t H, int m, const void *X, int64_t ldx, const void 
 int spmm_sym(hsym_t H, int m, const double *X, int64_t ldx, double *Y, int64_t ldy, void *stream) {
     API_BEGIN
     check_block(H, m, X, ldx, Y, ldy);
-    hipStream_t s = (hipStream_t)stream;
-    void *pp = nullptr;
-    HIPCHK(hipMallocAsync(&pp, spmm_partial_bytes(H, m), s));
-    try {
-        spmm_launch(H, m, X, T_F64, ldx, Y, T_F64, ldy, pp, s);
-    } catch (...) {
-        (void)hipFreeAsync(pp, s);
-        throw;
-    }
-    HIPCHK(hipFreeAsync(pp, s));
+    spmm_launch(H, m, X, T_F64, ldx, Y, T_F64, ldy, (hipStream_t)stream);
     API_END
 }
 
@@ -321,16 +314,7 @@ int spmm_sym_f32(hsym_t H, int m, const float *X, int64_t ldx, float *Y, int64_t
     API_BEGIN
     check_block(H, m, X, ldx, Y, ldy);
     if (H->storage != HSYM_FP32) fail(HSYM_E_INVALID_ARG, "spmm_sym_f32 needs fp32 storage");
-    hipStream_t s = (hipStream_t)stream;
-    void *pp = nullptr;
-    HIPCHK(hipMallocAsync(&pp, spmm_partial_bytes(H, m, T_F32), s));
-    try {
-        spmm_launch(H, m, X, T_F32, ldx, Y, T_F32, ldy, pp, s);
-    } catch (...) {
-        (void)hipFreeAsync(pp, s);
-        throw;
-    }
-    HIPCHK(hipFreeAsync(pp, s));
+    spmm_launch(H, m, X, T_F32, ldx, Y, T_F32, ldy, (hipStream_t)stream);
     API_END
 }
 

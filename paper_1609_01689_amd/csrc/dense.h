@@ -7,7 +7,7 @@ namespace hsym {
 
 struct GramArgs {
     const double *a[3];
-    const double *b[3];
+    const double *b[6];
     int na, nb;       // number of n x m blocks on each side
     int m;
     int64_t n;
@@ -86,17 +86,14 @@ void small_orth(const OrthArgs *a, int count, hipStream_t s);
 // (k x 2m): C_X = the m lowest Ritz vectors, C_P an orthonormal basis of the
 // W,P-components of C_X made orthogonal to C_X; theta[0..m).
 struct RRArgs {
-    const double *gram;   // k x k
-    double *coef;         // k x 2m
+    // k x 2k (k = nblk*m): [S^T S | S^T A S] for the basis S of nblk blocks
+    const double *gram;
+    double *coef;         // k x 2m: C_X and C_P for the stored basis
     double *theta;        // m
     double *evals_all;    // k (diagnostics), or null: then only the m lowest are computed
-    int *flag;            // 1 + multisection rounds used (>0), or -1 on failure
+    int *flag;            // [0]: 1 + multisection rounds used (>0), or -1 on failure;
+                          // [1]: 1 when the P block was dropped, else 0
     int nblk, m;
-    // optional (nblk >= 2): the W block of the basis is W' U with U (m x m,
-    // row-major) applied implicitly: gram holds [X W' P]^T A [X W' P], the
-    // eigenproblem is solved for T^T gram T with T = diag(I, U, I), and the W
-    // rows of coef are returned for W' (premultiplied by U)
-    const double *wtrans;
 };
 void small_rr(const RRArgs *a, int count, hipStream_t s);
 void set_int(int *p, int v, hipStream_t s);

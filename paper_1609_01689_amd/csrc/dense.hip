@@ -29,7 +29,9 @@ __device__ __forceinline__ double guard_den(double d, double delta) {
 template <int T1, int T2>
 __device__ __forceinline__ void gram_partial_body(const GramArgs &g, double *__restrict__ part, int64_t rows_per_wg,
                                                   int64_t bx) {
-    __shared__ double red[4][T1 * 16][T2 * 16 + 1];
+    // the four waves' partial sums meet in LDS, at most 3 column tiles at a time
+    constexpr int TC = T2 < 3 ? T2 : 3;
+    __shared__ double red[4][T1 * 16][TC * 16 + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = g.m;
     const int K1 = g.na * m, K2 = g.nb * m;
@@ -82,17 +84,23 @@ __device__ __forceinline__ void gram_partial_body(const GramArgs &g, double *__r
                 for (int j = 0; j < T2; j++)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i], bv[u][j], acc[i][j], 0, 0, 0);
     }
-#pragma unroll
-    for (int i = 0; i < T1; i++)
-#pragma unroll
-        for (int j = 0; j < T2; j++)
-#pragma unroll
-            for (int v = 0; v < 4; v++) red[wave][16 * i + lk + 4 * v][16 * j + li] = acc[i][j][v];
-    __syncthreads();
     double *out = part + bx * K1 * K2;
-    for (int e = tid; e < K1 * K2; e += 256) {
-        int i = e / K2, j = e - (e / K2) * K2;
-        out[e] = red[0][i][j] + red[1][i][j] + red[2][i][j] + red[3][i][j];
+#pragma unroll
+    for (int j0 = 0; j0 < T2; j0 += TC) {
+        if (j0) __syncthreads();
+#pragma unroll
+        for (int i = 0; i < T1; i++)
+#pragma unroll
+            for (int j = 0; j < TC; j++)
+                if (j0 + j < T2)
+#pragma unroll
+                    for (int v = 0; v < 4; v++) red[wave][16 * i + lk + 4 * v][16 * j + li] = acc[i][j0 + j][v];
+        __syncthreads();
+        const int c0 = 16 * j0, cw = (K2 - c0) < 16 * TC ? (K2 - c0) : 16 * TC;
+        for (int e = tid; e < K1 * cw; e += 256) {
+            const int i = e / cw, j = e - (e / cw) * cw;
+            out[i * K2 + c0 + j] = red[0][i][j] + red[1][i][j] + red[2][i][j] + red[3][i][j];
+        }
     }
 }
 
@@ -179,6 +187,7 @@ void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s) {
     const int64_t rpw = gram_rows(g.n, parts);
 #define GL(a, b) if (T1 == a && T2 == b) { gram_launch_t<a, b>(g, scratch, parts, rpw, s); } else
     GL(1, 1) GL(1, 2) GL(1, 3) GL(2, 1) GL(2, 2) GL(2, 3) GL(3, 1) GL(3, 2) GL(3, 3)
+    GL(1, 4) GL(1, 6) GL(2, 4) GL(2, 5) GL(2, 6) GL(3, 4) GL(3, 5) GL(3, 6)
         fail(HSYM_E_UNSUPPORTED, "gram shape");
 #undef GL
     HIPCHK(hipGetLastError());
@@ -795,6 +804,7 @@ void gram_batched(const GramJob *jobs, int count, int K1, int K2, int max_parts,
     const dim3 grid((unsigned)max_parts, (unsigned)count);
 #define GB(a, b) if (T1 == a && T2 == b) { hipLaunchKernelGGL((k_gram_partial_b<a, b>), grid, dim3(256), 0, s, jobs); } else
     GB(1, 1) GB(1, 2) GB(1, 3) GB(2, 1) GB(2, 2) GB(2, 3) GB(3, 1) GB(3, 2) GB(3, 3)
+    GB(1, 4) GB(1, 6) GB(2, 4) GB(2, 5) GB(2, 6) GB(3, 4) GB(3, 5) GB(3, 6)
         fail(HSYM_E_UNSUPPORTED, "gram shape");
 #undef GB
     HIPCHK(hipGetLastError());

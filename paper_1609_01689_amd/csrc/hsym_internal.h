@@ -11,6 +11,9 @@
 
 namespace hsym {
 
+// block widths are rounded up to the next of 1, 2, 4, 8, 16 for the kernels
+inline int round_m(int m) { return m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : m <= 8 ? 8 : 16; }
+
 // ---------------------------------------------------------------------------
 // Errors: every entry point converts failures into a status and a message.
 // ---------------------------------------------------------------------------
@@ -25,42 +28,52 @@ void check_hip(hipError_t e, const char *what);
 
 // ---------------------------------------------------------------------------
 // Tile format of the stored upper triangle (compressed sparse blocks,
-// Section 4.2: independently addressable blocks, each holding its entries in
-// coordinate form with 16-bit local row and column offsets).  Rows are cut
-// into panels of R rows and columns into chunks of C columns (R a multiple of
-// C).  The strictly-upper entries of one panel that fall into one chunk form a
-// tile, stored row-major as index codes (local row << shift | local column)
-// plus values: 32-bit codes with shift = 16, or, on request (HSYM_INDEX16),
-// 16-bit codes with shift = log2 C when C is a power of two and R * C <= 2^16
-// (Section 4.2: indices local to a block need only 16 bits).  A tile's entries are cut into G equal segments (the last one padded
-// with zero values) stored interleaved: entry e of segment s sits at
-// base + e*G + s, so G lane groups stream a tile with coalesced loads and equal
-// work.  A tile is "own" when its chunk lies inside the panel (its transposed
-// half lands in the panel's rows) and "external" otherwise; every external tile
-// owns one partial-sum slot of C rows (used when the output is fp32).
+// Section 4.2: independently addressable blocks whose entries carry indices
+// local to the block).  Rows are cut into panels of R rows and columns into
+// chunks of C columns (C a power of two dividing R).  The strictly-upper
+// entries of one panel that fall into one chunk form a tile; a tile with more
+// than MAXE entries is cut into pieces of consecutive entries.  A piece of cnt
+// entries is padded to E = G * len and stored as three arrays:
+//   - codes: local row << cb | local column (cb = log2 C), 16-bit when
+//     R * C <= 2^16, else 32-bit, in row-major order (rows ascending, columns
+//     ascending within a row), cut into G equal segments: entry q of the
+//     row-major order is segment q / len, step q % len, and sits at
+//     base + step * G + segment;
+//   - values (T), in the same positions;
+//   - perm (16-bit): the column-major order of the same entries, cut into G
+//     segments the same way; each position holds the staged position of the
+//     entry (its index within the piece's codes/values).
+// Padding positions repeat the code of the piece's last entry with value 0.
+// A tile is "own" when its chunk lies inside the panel (its transposed half
+// lands in the panel's rows) and "external" otherwise.
 // ---------------------------------------------------------------------------
 struct TileDesc {
-    int64_t base;          // first stored entry
-    int32_t len;           // entries per segment (after padding)
+    int64_t base;          // first stored position (a multiple of 8)
+    int32_t len;           // steps per segment
     int32_t chunk;         // global chunk index g: columns [g*C, g*C+C)
-    int32_t slot;          // partial slot, -1 for an own tile
-    int32_t pad;
+    int32_t ext;           // 1 for an external tile, 0 for an own tile
+    int32_t flags;         // TILE_FIRST: first piece of its tile; TILE_LAST: last piece
+};
+enum { TILE_FIRST = 1, TILE_LAST = 2 };
+
+// panel geometry of a handle
+struct Geom {
+    int R = 0, C = 0;      // panel rows, chunk columns
+    int cb = 0;            // log2 C
+    int G = 0;             // segments per piece
+    int maxe = 0;          // entries per piece at most (a multiple of 8)
+    int idx_bytes = 2;     // code width
 };
 
 struct DeviceTiles {
-    int R = 0, C = 0, G = 0;
-    int64_t npanels = 0, nchunks = 0, ntiles = 0, nentries = 0, nslots = 0;
-    int64_t nred_chunks = 0;
-    int64_t *panel_tile_ptr = nullptr;
-    int32_t *panel_order = nullptr;   // panel of workgroup b (see build.cpp: per-XCD, heaviest first)
+    Geom g;
+    int64_t npanels = 0, nchunks = 0, ntiles = 0, npieces = 0, nentries = 0, next = 0;
+    int64_t *panel_tile_ptr = nullptr;   // pieces of panel p: [ptp[p], ptp[p+1])
+    int32_t *panel_order = nullptr;      // panel of workgroup b (see build.cpp: per-XCD runs)
     TileDesc *tiles = nullptr;
-    void *idx = nullptr;          // uint16_t codes when idx_bytes == 2, else uint32_t
-    int idx_bytes = 4;
-    int idx_shift = 16;           // local row << idx_shift | local column
+    void *idx = nullptr;                 // codes (uint16_t or uint32_t)
+    uint16_t *perm = nullptr;
     void *vals = nullptr;
-    int64_t *red_ptr = nullptr;
-    int32_t *red_slot = nullptr;
-    int32_t *red_chunks = nullptr;
     int64_t bytes = 0;
 };
 
@@ -78,7 +91,7 @@ struct hsym_matrix {
     // tile format of the strictly-upper part (one panel geometry per handle)
     hsym::DeviceTiles tiles;
     int geom_m = 16;              // block width the geometry is sized for
-    int geom_lr = 0, geom_lc = 0; // explicit log2 panel rows / chunk columns (0: automatic)
+    int geom_r64 = 0, geom_lc = 0; // explicit panel rows / 64 and log2 chunk columns (0: automatic)
     std::vector<double> d_host;   // diagonal, fp64, host copy
     std::vector<double> colsum;   // absolute column sums (streaming create)
     // block-64 preconditioner: per 64-row chunk Q (64x64, row-major) and lambda
@@ -102,10 +115,11 @@ struct hsym_matrix {
 
 namespace hsym {
 
-// geometry: (R, C) for a block width and storage precision
-void geometry_for(int storage, int m, int64_t n, int lr, int lc, int *R, int *C, int *G);
-int spmm_lanes_per_entry(int storage, int m);
-size_t spmm_lds_bytes(int storage, int m, int R, int C);
+// geometry for a storage precision and block width (explicit rows/64 and log2 C
+// when r64 > 0)
+Geom geometry_for(int storage, int m, int64_t n, int r64, int lc);
+// LDS bytes the SpMM needs at block width m on geometry g (160 KB available)
+size_t spmm_lds_bytes(int storage, int m, const Geom &g);
 void free_tiles(DeviceTiles *dt);
 
 // device scratch (per call)
@@ -116,13 +130,11 @@ struct Scratch {
     void *get(size_t b);
 };
 
-// SpMM launch: X (n x m, ld ldx) -> Y; XIN/YOUT precision flags
+// SpMM launch: X (n x m, ld ldx) -> Y; XIN/YOUT precision flags.  Y is
+// cleared and receives every contribution by device-scope atomic adds.
 enum { T_F64 = 0, T_F32 = 1 };
 void spmm_launch(hsym_matrix *H, int m, const void *X, int xprec, int64_t ldx, void *Y, int yprec,
-                 int64_t ldy, void *partials, hipStream_t s);
-// partial-slot scratch of one SpMM call: fp32 outputs sum the transposed half
-// of external tiles through slots and a reduction; fp64 outputs add it into Y
-size_t spmm_partial_bytes(hsym_matrix *H, int m, int yprec = T_F64);
+                 int64_t ldy, hipStream_t s);
 
 // one matrix of a batched SpMM (fp64 blocks with leading dimension m)
 struct SpmmJob {
@@ -130,24 +142,19 @@ struct SpmmJob {
     const int32_t *porder;
     const TileDesc *tiles;
     const void *idx;
-    int idx_bytes, idx_shift;
+    const uint16_t *perm;
     const void *vals;
     const void *diag;
     const double *X;
     int64_t ldx;
     double *Y;
     int64_t ldy;
-    double *partials;
     int64_t n;
-    int R, C, G;
     int64_t npanels;
+    Geom g;
     int m;
-    const int32_t *red_chunks;
-    const int64_t *red_ptr;
-    const int32_t *red_slot;
-    int64_t nred;
 };
-SpmmJob spmm_job(hsym_matrix *H, int m, const double *X, double *Y, double *partials);
+SpmmJob spmm_job(hsym_matrix *H, int m, const double *X, double *Y);
 // jobs: device table; host: the same table on the host (for the launch shape).
 // Every matrix has the given storage; m is the same for all.
 void spmm_batched(const SpmmJob *jobs, const SpmmJob *host, int count, int m, int storage, hipStream_t s);

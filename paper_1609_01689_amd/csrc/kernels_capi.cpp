@@ -48,7 +48,7 @@ int hsym_kernel_gram(int64_t n, int m, int na, const double *const *A, int nb, c
                      void *stream) {
     return guarded([&] {
         check_nm(n, m);
-        if (na < 1 || na > 3 || nb < 1 || nb > 3 || !A || !B || !G) fail(HSYM_E_INVALID_ARG, "bad gram arguments");
+        if (na < 1 || na > 3 || nb < 1 || nb > 6 || !A || !B || !G) fail(HSYM_E_INVALID_ARG, "bad gram arguments");
         hipStream_t s = (hipStream_t)stream;
         GramArgs g{};
         for (int i = 0; i < na; i++) g.a[i] = A[i];
@@ -74,21 +74,22 @@ int hsym_kernel_lincomb(int64_t n, int m, int nin, const double *const *In, int 
     });
 }
 
-int hsym_kernel_rayleigh_ritz(int nblk, int m, const double *A, double *theta, double *evals, double *coef,
-                              void *stream) {
+int hsym_kernel_rayleigh_ritz(int nblk, int m, const double *G, double *theta, double *evals, double *coef,
+                              int *p_dropped, void *stream) {
     return guarded([&] {
-        if (nblk < 1 || nblk > 3 || m < 1 || m > HSYM_MAX_BLOCK || !A || !theta || !evals || !coef)
+        if (nblk < 1 || nblk > 3 || m < 1 || m > HSYM_MAX_BLOCK || !G || !theta || !evals || !coef)
             fail(HSYM_E_INVALID_ARG, "bad Rayleigh-Ritz arguments");
         hipStream_t s = (hipStream_t)stream;
-        DevBuf flag(sizeof(int));
+        DevBuf flag(2 * sizeof(int));
         RRArgs r{};
-        r.gram = A; r.coef = coef; r.theta = theta; r.evals_all = evals; r.flag = (int *)flag.p;
+        r.gram = G; r.coef = coef; r.theta = theta; r.evals_all = evals; r.flag = (int *)flag.p;
         r.nblk = nblk; r.m = m;
         small_rr(&r, 1, s);
-        int f = 0;
-        HIPCHK(hipMemcpyAsync(&f, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        int f[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(f, flag.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        if (f < 0) fail(HSYM_E_NUMERIC, "Rayleigh-Ritz eigensolver broke down (non-finite inverse iterate)");
+        if (f[0] < 0) fail(HSYM_E_NUMERIC, "Rayleigh-Ritz eigensolver broke down (non-finite inverse iterate)");
+        if (p_dropped) *p_dropped = f[1];
     });
 }
 

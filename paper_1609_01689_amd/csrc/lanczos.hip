@@ -139,7 +139,6 @@ extern "C" int lanczos_solve(hsym_t H, int nev, double tol, const double *v0, co
         double *alpha = (double *)dal(sizeof(double) * (kmax + 1));
         double *beta2 = (double *)dal(sizeof(double) * (kmax + 1));   // squared norms
         double *beta = (double *)dal(sizeof(double) * (kmax + 1));
-        double *part = (double *)dal(spmm_partial_bytes(H, 1));
         const unsigned gb = (unsigned)((n + 255) / 256);
         auto t0 = std::chrono::steady_clock::now();
         // v_1 = v0 / ||v0||
@@ -164,7 +163,7 @@ extern "C" int lanczos_solve(hsym_t H, int nev, double tol, const double *v0, co
         for (j = 1; j <= kmax; j++) {
             double *vj = V + (int64_t)(j - 1) * n;
             if (nev_rec < NEV) HIPCHK(hipEventRecord(evs[2 * nev_rec], s));
-            spmm_launch(H, 1, vj, T_F64, 1, w, T_F64, 1, part, s);
+            spmm_launch(H, 1, vj, T_F64, 1, w, T_F64, 1, s);
             if (nev_rec < NEV) { HIPCHK(hipEventRecord(evs[2 * nev_rec + 1], s)); nev_rec++; }
             if (j > 1) {
                 hipLaunchKernelGGL(k_axpy_dev, dim3(gb), dim3(256), 0, s, w, vj - n, beta + (j - 2), n);

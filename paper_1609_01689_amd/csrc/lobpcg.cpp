@@ -3,15 +3,18 @@
 // reads back one small status block per iteration (residual norms, Ritz
 // values) to run the convergence test and the shift rules.
 //
-// Basis handling: S = [X W P] is kept orthonormal.  W is orthonormalised
-// against [X P] and itself by Cholesky-QR passes driven by Gram matrices; the
-// factor U of the last pass is not applied to W (the basis holds W U, with U
-// folded into the Rayleigh-Ritz problem and its W coefficients), which saves
-// a full pass over W;
-// after Rayleigh-Ritz the new P is built in coefficient space as an
-// orthonormal basis of the W,P-components of the new X made orthogonal to the
-// new X, so span{X_new, P_new} equals span{X_new, (I - X X^T) X_new} of step 10
-// and no full-size pass is needed to orthogonalise P.
+// Basis handling (Algorithm 1, step 7): W is orthonormalised against [X P]
+// and itself by Cholesky-QR passes driven by Gram matrices.  The Rayleigh-
+// Ritz step then measures the basis: one pass over S = [X W P] and AS forms
+// both S^T S and S^T A S, and the small kernel orthonormalises S in
+// coefficient space (Cholesky of S^T S in the order X, W, P: Gram-Schmidt of
+// P against X and W, and of W against X), dropping P for the iteration when
+// one of its pivots is small.  After Rayleigh-Ritz the new P is built in
+// coefficient space from the W,P-components of the new X made orthogonal to
+// it, so span{X_new, P_new} equals span{X_new, (I - X X^T) X_new} of step 10
+// and no full-size pass is needed to orthogonalise P.  The rounding of X and
+// P away from orthonormality does not accumulate: every iteration's
+// Rayleigh-Ritz takes the basis as measured.
 #include <atomic>
 #include <memory>
 #include <chrono>
@@ -85,7 +88,7 @@ struct Lobpcg {
     lobpcg_opts o{};
     // device blocks
     double *X = nullptr, *AX = nullptr, *W = nullptr, *AW = nullptr, *P = nullptr, *AP = nullptr;
-    double *spmm_part = nullptr, *gram_scr = nullptr, *gbuf = nullptr, *coef = nullptr, *rrcoef = nullptr;
+    double *gram_scr = nullptr, *gbuf = nullptr, *coef = nullptr, *rrcoef = nullptr;
     double *mu = nullptr, *norm_part = nullptr;
     Status *st_d = nullptr;
     Status *st_h = nullptr;      // pinned
@@ -147,10 +150,9 @@ struct Lobpcg {
         size_t nm = (size_t)n * m;
         X = dalloc<double>(nm); AX = dalloc<double>(nm); W = dalloc<double>(nm);
         AW = dalloc<double>(nm); P = dalloc<double>(nm); AP = dalloc<double>(nm);
-        spmm_part = (double *)dalloc<char>(spmm_partial_bytes(H, m));
-        gram_scr = (double *)dalloc<char>(std::max(gram_scratch_bytes(n, 3 * m, 3 * m),
+        gram_scr = (double *)dalloc<char>(std::max(gram_scratch_bytes(n, 3 * m, 6 * m),
                                                    sign_fix_scratch_bytes(n, m)));
-        gbuf = dalloc<double>(48 * 48);
+        gbuf = dalloc<double>(48 * 96);
         coef = dalloc<double>(48 * 32);
         rrcoef = dalloc<double>(48 * 32);
         mu = dalloc<double>(HSYM_MAX_BLOCK);
@@ -170,7 +172,7 @@ struct Lobpcg {
         spmm(X, AX);
         rep.spmm_calls++;
         GramArgs g{};
-        g.a[0] = X; g.b[0] = AX; g.na = g.nb = 1; g.m = m; g.n = n;
+        g.a[0] = X; g.b[0] = X; g.b[1] = AX; g.na = 1; g.nb = 2; g.m = m; g.n = n;
         gram(g, gbuf, gram_scr, s);
         rayleigh_ritz(1);
         LincombArgs u{};
@@ -187,7 +189,7 @@ struct Lobpcg {
     // phase_ms[0] at the next synchronisation
     void spmm(const double *V, double *AV) {
         if (!capturing) HIPCHK(hipEventRecord(ev_spmm[0], s));
-        spmm_launch(H, m, V, T_F64, m, AV, T_F64, m, spmm_part, s);
+        spmm_launch(H, m, V, T_F64, m, AV, T_F64, m, s);
         if (!capturing) {
             HIPCHK(hipEventRecord(ev_spmm[1], s));
             spmm_pending = true;
@@ -229,12 +231,11 @@ struct Lobpcg {
         HIPCHK(hipGraphLaunch(ge, s));
     }
 
-    // wtrans: the second Cholesky-QR factor of W (coef), applied inside the
-    // Rayleigh-Ritz step instead of to W itself
-    void rayleigh_ritz(int nblk, const double *wtrans = nullptr) {
+    // gbuf holds [S^T S | S^T A S] for the nblk blocks of S
+    void rayleigh_ritz(int nblk) {
         RRArgs r{};
         r.gram = gbuf; r.coef = rrcoef; r.theta = st_d->theta; r.evals_all = nullptr;   // only the m lowest are needed
-        r.flag = &st_d->flags[1]; r.nblk = nblk; r.m = m; r.wtrans = wtrans;
+        r.flag = &st_d->flags[1]; r.nblk = nblk; r.m = m;
         small_rr(&r, 1, s);
     }
 
@@ -271,6 +272,7 @@ struct Lobpcg {
         }
         if (st_h->flags[1] < 0) fail(HSYM_E_NUMERIC, "Rayleigh-Ritz eigensolver broke down (non-finite inverse iterate)");
         rep.rr_rounds_max = std::max(rep.rr_rounds_max, st_h->flags[1] - 1);
+        rep.p_dropped += st_h->flags[2];
         if (o.keep_history && rep.history_len < HSYM_MAX_HISTORY) rep.history[rep.history_len++] = mx;
         for (int j = 0; j < m; j++) { rep.theta[j] = st_h->theta[j]; rep.resnorm[j] = rho_[j]; }
         rep.iters = it;
@@ -354,23 +356,21 @@ struct Lobpcg {
     // nothing when the flag is set, so that a repair can start from them.
     void phase_b() {
         auto body = [&] {
+            // second Cholesky-QR stage of W (projection and normalisation);
+            // the Rayleigh-Ritz step measures what is left of W's deviation
+            // from orthonormality
             LincombArgs lc2 = orth_lc;
             lc2.skip = &st_d->flags[0];
-            GramArgs g2{};
-            g2.a[0] = W; g2.b[0] = W; g2.na = g2.nb = 1; g2.m = m; g2.n = n;
-            lincomb_gram(lc2, g2, gbuf, gram_scr, s);
-            // second Cholesky-QR pass: its factor U (W_orth = W U) is not
-            // applied to W; the SpMM takes W as it is and the Rayleigh-Ritz
-            // step applies U to the Gram matrix and to the W coefficients
-            OrthArgs o2{gbuf, coef, &st_d->flags[0], 0, m, 2};
-            small_orth(&o2, 1, s);
+            lincomb(lc2, s);
             spmm(W, AW);
             const int nblk = have_p ? 3 : 2;
             GramArgs g{};
-            g.a[0] = X; g.a[1] = W; g.a[2] = P; g.b[0] = AX; g.b[1] = AW; g.b[2] = AP;
-            g.na = g.nb = nblk; g.m = m; g.n = n;
+            g.a[0] = X; g.a[1] = W; g.a[2] = P;
+            g.b[0] = X; g.b[1] = W; g.b[2] = P;
+            g.b[nblk] = AX; g.b[nblk + 1] = AW; if (nblk == 3) g.b[5] = AP;
+            g.na = nblk; g.nb = 2 * nblk; g.m = m; g.n = n;
             gram(g, gbuf, gram_scr, s);
-            rayleigh_ritz(nblk, coef);
+            rayleigh_ritz(nblk);
             LincombArgs u{};
             u.in[0] = X; u.in[1] = W; u.in[2] = P; u.in[3] = AX; u.in[4] = AW; u.in[5] = AP;
             u.out[0] = X; u.out[1] = P; u.out[2] = AX; u.out[3] = AP;
@@ -468,7 +468,7 @@ struct BatchPlan {
     // device tables (one allocation) and their pinned staging
     char *dev = nullptr, *pin = nullptr;
     size_t bytes = 0;
-    GramJob *gA = nullptr, *gW = nullptr, *gS = nullptr;
+    GramJob *gA = nullptr, *gS = nullptr;
     LincombArgs *lcO = nullptr, *lcO2 = nullptr, *lcU = nullptr;   // lcO2: phase B's copy of lcO
     ColsumJob *cs = nullptr;
     SpmmJob *sp = nullptr;
@@ -479,11 +479,11 @@ struct BatchPlan {
     double *mu = nullptr;          // per round: count x 16
     // host-side copies needed for launch shapes and the small kernels
     std::vector<SpmmJob> sp_h;
-    std::vector<OrthArgs> o0, o1, o2;
+    std::vector<OrthArgs> o0, o1;
     std::vector<RRArgs> rr;
     int m = 0, storage = 0, count = 0;
     int64_t max_n = 0;
-    int maxpA = 0, maxpW = 0, maxpS = 0;
+    int maxpA = 0, maxpS = 0;
 
     ~BatchPlan() {
         if (dev) (void)hipFree(dev);
@@ -506,7 +506,7 @@ struct BatchPlan {
                 off += each * BATCH_CAP;
                 return o;
             };
-            const size_t oA = at(sizeof(GramJob)), oW = at(sizeof(GramJob)), oS = at(sizeof(GramJob));
+            const size_t oA = at(sizeof(GramJob)), oS = at(sizeof(GramJob));
             const size_t oO = at(sizeof(LincombArgs)), oO2 = at(sizeof(LincombArgs)), oU = at(sizeof(LincombArgs));
             const size_t oC = at(sizeof(ColsumJob)), oP = at(sizeof(SpmmJob)), oF = at(sizeof(int *));
             const size_t oR = at(sizeof(int *)), oT = at(sizeof(Status)), oJ = at(sizeof(JacobiJob));
@@ -514,23 +514,23 @@ struct BatchPlan {
             bytes = off;
             HIPCHK(hipMalloc((void **)&dev, bytes));
             HIPCHK(hipHostMalloc((void **)&pin, bytes, hipHostMallocDefault));
-            gA = (GramJob *)(dev + oA); gW = (GramJob *)(dev + oW); gS = (GramJob *)(dev + oS);
+            gA = (GramJob *)(dev + oA); gS = (GramJob *)(dev + oS);
             lcO = (LincombArgs *)(dev + oO); lcO2 = (LincombArgs *)(dev + oO2); lcU = (LincombArgs *)(dev + oU);
             cs = (ColsumJob *)(dev + oC); sp = (SpmmJob *)(dev + oP); flag_ptr = (int **)(dev + oF);
             stat_src = (const int **)(dev + oR); stat_dst = (int *)(dev + oT); jac = (JacobiJob *)(dev + oJ);
             mu = (double *)(dev + oM);
         }
         auto host = [&](const void *d) { return pin + ((const char *)d - dev); };
-        GramJob *hgA = (GramJob *)host(gA), *hgW = (GramJob *)host(gW), *hgS = (GramJob *)host(gS);
+        GramJob *hgA = (GramJob *)host(gA), *hgS = (GramJob *)host(gS);
         LincombArgs *hlO = (LincombArgs *)host(lcO), *hlO2 = (LincombArgs *)host(lcO2), *hlU = (LincombArgs *)host(lcU);
         ColsumJob *hcs = (ColsumJob *)host(cs);
         SpmmJob *hsp = (SpmmJob *)host(sp);
         int **hfl = (int **)host(flag_ptr);
         const int **hss = (const int **)host(stat_src);
         sp_h.assign((size_t)count, SpmmJob{});
-        o0.clear(); o1.clear(); o2.clear(); rr.clear();
+        o0.clear(); o1.clear(); rr.clear();
         key.clear();
-        max_n = 0; maxpA = maxpW = maxpS = 0;
+        max_n = 0; maxpA = maxpS = 0;
         auto gjob = [&](Lobpcg &L, const double *a0, const double *a1, const double *a2, const double *b0,
                         const double *b1, const double *b2, int na, int nb, int &maxp) {
             GramJob j{};
@@ -549,8 +549,8 @@ struct BatchPlan {
             key.emplace_back(&L, L.serial);
             max_n = std::max(max_n, L.n);
             hgA[i] = gjob(L, L.X, L.P, L.W, L.W, nullptr, nullptr, 3, 1, maxpA);
-            hgW[i] = gjob(L, L.W, nullptr, nullptr, L.W, nullptr, nullptr, 1, 1, maxpW);
-            hgS[i] = gjob(L, L.X, L.W, L.P, L.AX, L.AW, L.AP, 3, 3, maxpS);
+            hgS[i] = gjob(L, L.X, L.W, L.P, L.X, L.W, L.P, 3, 6, maxpS);
+            hgS[i].g.b[3] = L.AX; hgS[i].g.b[4] = L.AW; hgS[i].g.b[5] = L.AP;
             LincombArgs lo{};
             lo.in[0] = L.X; lo.in[1] = L.P; lo.in[2] = L.W; lo.out[0] = L.W; lo.coef = L.coef; lo.ldc = L.m;
             lo.nin = 3; lo.nout = 1; lo.nsets = 1; lo.m = L.m; lo.n = L.n;
@@ -564,16 +564,15 @@ struct BatchPlan {
             u.theta = L.st_d->theta; u.res = L.W; u.norm_part = L.norm_part; u.skip = &L.st_d->flags[0];
             hlU[i] = u;
             hcs[i] = ColsumJob{L.norm_part, lincomb_norm_parts(L.n), L.m, L.st_d->norms};
-            hsp[i] = spmm_job(L.H, L.m, L.W, L.AW, L.spmm_part);
+            hsp[i] = spmm_job(L.H, L.m, L.W, L.AW);
             sp_h[(size_t)i] = hsp[i];
             hfl[i] = &L.st_d->flags[0];
             hss[i] = (const int *)L.st_d;
             o0.push_back(OrthArgs{L.gbuf, L.coef, &L.st_d->flags[0], 2, L.m, 0});
             o1.push_back(OrthArgs{L.gbuf, L.coef, &L.st_d->flags[0], 2, L.m, 1});
-            o2.push_back(OrthArgs{L.gbuf, L.coef, &L.st_d->flags[0], 0, L.m, 2});
             RRArgs r{};
             r.gram = L.gbuf; r.coef = L.rrcoef; r.theta = L.st_d->theta; r.evals_all = nullptr;
-            r.flag = &L.st_d->flags[1]; r.nblk = 3; r.m = L.m; r.wtrans = L.coef;
+            r.flag = &L.st_d->flags[1]; r.nblk = 3; r.m = L.m;
             rr.push_back(r);
         }
         // the static tables: everything before the per-round Jacobi jobs
@@ -637,15 +636,9 @@ struct BatchPlan {
             small_orth(o1.data(), count, bs);
             // ---- phase B, enqueued at once: its launches that overwrite the
             // basis skip a problem whose rank flag is set (see Lobpcg::phase_b) ----
-            if (m == 16) {
-                lincomb_gram_batched(lcO2, gW, count, 1, maxpW, bs);
-            } else {
-                lincomb_batched(lcO2, count, max_n, bs);
-                gram_batched(gW, count, m, m, maxpW, bs);
-            }
-            small_orth(o2.data(), count, bs);
+            lincomb_batched(lcO2, count, max_n, bs);
             spmm_batched(sp, sp_h.data(), count, m, storage, bs);
-            gram_batched(gS, count, 3 * m, 3 * m, maxpS, bs);
+            gram_batched(gS, count, 3 * m, 6 * m, maxpS, bs);
             small_rr(rr.data(), count, bs);
             lincomb_batched(lcU, count, max_n, bs);
             colsum_batched(cs, count, m, bs);

@@ -158,6 +158,9 @@ void small_orth(const OrthArgs *a, int count, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Rayleigh-Ritz on k x k (k <= 48), one workgroup of 256 threads:
+//   0. the basis S = [X W P] is made orthonormal in coefficient space from its
+//      measured Gram matrix S^T S (Cholesky, twice when needed; P dropped at a
+//      small pivot) and the projected matrix formed on it;
 //   1. Householder reduction to tridiagonal form T = Q^T A Q (Golub and Van
 //      Loan, Section 8.3.1), a quad of lanes per row for A22 v and the
 //      rank-2 update, reflectors kept for step 4;
@@ -332,6 +335,81 @@ __device__ void proj_out(double (*Z)[17], const double (*Y)[17], int k, int m, d
     __syncthreads();
 }
 
+// Cholesky of the k x k (k <= 48) symmetric positive definite S (LDS) after
+// scaling it to unit diagonal, by the first wave alone: lane r holds row r in
+// registers; columns past k are padded with the identity.  Writes the factor
+// of the scaled matrix to L (lower part), the scales 1/sqrt(S_rr) to sc and
+// the pivots (the squared sine of the angle between basis vector r and the
+// span of the ones before it) to pv; returns nothing (other waves skip it).
+__device__ void wave_chol(const double (*S)[KMAX + 1], int k, double (*L)[KMAX + 1], double *sc, double *pv) {
+    const int lane = threadIdx.x & 63;
+    const int r = lane < KMAX ? lane : KMAX - 1;
+    const double sd = r < k ? S[r][r] : 1.0;
+    const double s_r = sd > 0.0 ? 1.0 / sqrt(sd) : 0.0;
+    double g[KMAX];
+#pragma unroll
+    for (int c = 0; c < KMAX; c++) {
+        const double s_c = read_lane(s_r, c);
+        g[c] = c <= r ? ((r < k) ? S[r][c] * s_r * s_c : (c == r ? 1.0 : 0.0)) : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < KMAX; j++) {
+        const double pj = read_lane(g[j], j);
+        const double dj = sqrt(fmax(pj, 1e-300));
+        const double l = (r == j) ? dj : g[j] / dj;
+        g[j] = l;
+#pragma unroll
+        for (int c = j + 1; c < KMAX; c++) g[c] = fma(-l, read_lane(l, c), g[c]);
+        if (lane == j) pv[j] = pj;
+    }
+    if (lane < k) {
+#pragma unroll
+        for (int c = 0; c < KMAX; c++)
+            if (c <= lane) L[lane][c] = g[c];
+        sc[lane] = s_r;
+    }
+}
+
+// Li = (D^-1 Ls)^-1 = Ls^-1 D for the factor Ls of the scaled matrix and
+// D = diag(sc): one lane per column c, forward substitution on its own column
+// of Li (the entries above the diagonal are zero).
+__device__ void tri_inverse(const double (*L)[KMAX + 1], const double *sc, int k, double (*Li)[KMAX + 1]) {
+    const int c = threadIdx.x;
+    if (c >= k) return;
+    for (int i = 0; i < c; i++) Li[i][c] = 0.0;
+    for (int i = c; i < k; i++) {
+        double v = i == c ? 1.0 : 0.0;
+        for (int q = c; q < i; q++) v = fma(-L[i][q], Li[q][c], v);
+        Li[i][c] = v / L[i][i];
+    }
+    const double s_c = sc[c];
+    for (int i = c; i < k; i++) Li[i][c] *= s_c;
+}
+
+// B <- Li S Li^T (k x k, exactly symmetric) for lower-triangular Li; T is
+// scratch.  Whole workgroup.
+__device__ void congruence(const double (*Li)[KMAX + 1], const double (*S)[KMAX + 1], int k,
+                           double (*T)[KMAX + 1], double (*B)[KMAX + 1]) {
+    const int tid = threadIdx.x;
+    for (int e0 = tid; e0 < k * k; e0 += 256) {
+        const int i = e0 / k, j = e0 - (e0 / k) * k;
+        double v = 0.0;
+        for (int q = 0; q <= i; q++) v = fma(Li[i][q], S[q][j], v);
+        T[i][j] = v;
+    }
+    __syncthreads();
+    for (int e0 = tid; e0 < k * k; e0 += 256) {
+        const int i = e0 / k, j = e0 - (e0 / k) * k;
+        if (i <= j) {
+            double v = 0.0;
+            for (int q = 0; q <= j; q++) v = fma(T[i][q], Li[j][q], v);
+            B[i][j] = v;
+            B[j][i] = v;
+        }
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
     __shared__ double A[KMAX][KMAX + 1];      // lower part: reflector vectors
     __shared__ double beta[KMAX], d[KMAX], e[KMAX], ds[KMAX + 4], e2s[KMAX + 4], lam[KMAX];
@@ -341,74 +419,101 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
     __shared__ unsigned char piv[KMAX][17];
     __shared__ double Z[KMAX][17];
     __shared__ double G[16][17];
-    __shared__ double Us[16][17];             // the W transform of RRArgs::wtrans
+    __shared__ double GS[KMAX][KMAX + 1];     // S^T S, then scratch
+    __shared__ double Lf[KMAX][KMAX + 1];     // Cholesky factor, then scratch
+    __shared__ double Li[KMAX][KMAX + 1];     // the basis transform: S Li^T is orthonormal
+    __shared__ double scl[KMAX], pvt[KMAX];
     __shared__ double sh[40];
-    __shared__ int bad, nrounds;
+    __shared__ int bad, nrounds, kk, second;
     const RRArgs a = b.a[blockIdx.x];
-    const int m = a.m, k = a.nblk * m;
+    const int m = a.m, k0 = a.nblk * m;
     const int tid = threadIdx.x, lane = tid & 63;
     {
-        // all loads in flight together, then the average of the two triangles
-        double v[9];
+        // gram is k0 x 2 k0: [S^T S | S^T (A S)]; all loads in flight
+        // together, then the average of the two triangles of each
+        double v[18];
 #pragma unroll
-        for (int t = 0; t < 9; t++) v[t] = tid + 256 * t < k * k ? a.gram[tid + 256 * t] : 0.0;
+        for (int t = 0; t < 18; t++) v[t] = tid + 256 * t < 2 * k0 * k0 ? a.gram[tid + 256 * t] : 0.0;
 #pragma unroll
-        for (int t = 0; t < 9; t++) {
+        for (int t = 0; t < 18; t++) {
             const int e0 = tid + 256 * t;
-            if (e0 < k * k) {
-                const int i = e0 / k, j = e0 - (e0 / k) * k;
-                A[i][j] = v[t];
+            if (e0 < 2 * k0 * k0) {
+                const int i = e0 / (2 * k0), j = e0 - i * (2 * k0);
+                if (j < k0) GS[i][j] = v[t];
+                else A[i][j - k0] = v[t];
             }
         }
     }
     __syncthreads();
-    for (int e0 = tid; e0 < k * k; e0 += 256) {
-        const int i = e0 / k, j = e0 - (e0 / k) * k;
+    for (int e0 = tid; e0 < k0 * k0; e0 += 256) {
+        const int i = e0 / k0, j = e0 - (e0 / k0) * k0;
         if (i < j) {
             const double v = 0.5 * (A[i][j] + A[j][i]);
             A[i][j] = v;
             A[j][i] = v;
+            const double w = 0.5 * (GS[i][j] + GS[j][i]);
+            GS[i][j] = w;
+            GS[j][i] = w;
         }
     }
-    if (tid == 0) { bad = 0; nrounds = 0; }
-    const bool wt = a.wtrans != nullptr;
-    if (wt && tid < m * m) Us[tid / m][tid % m] = a.wtrans[tid];   // staged: read in dependent chains below
+    if (tid == 0) { bad = 0; nrounds = 0; second = 0; }
     __syncthreads();
-    if (wt) {
-        // A <- T^T A T, T = diag(I, U, I) on the W block (rows and columns
-        // m .. 2m).  With Z = A T restricted to the W columns, the new W
-        // columns are Z, the new W rows are Z^T (A is symmetric, so both come
-        // from the same sums), and the W x W block is U^T Z_W, formed for
-        // c <= d and mirrored: A stays exactly symmetric.
-        for (int e0 = tid; e0 < k * m; e0 += 256) {
-            const int i = e0 / m, c = e0 - (e0 / m) * m;
+    // Orthonormalisation of S = [X W P] (Algorithm 1, step 7) in coefficient
+    // space: the Cholesky factor of the measured S^T S, in the block order X,
+    // W, P, is Gram-Schmidt of W against X and of P against X and W.  P is
+    // dropped for this iteration when a pivot of its column-normalised
+    // projection is below P_DROP (the oracle's rank test); a second pass
+    // follows when the basis was far from orthonormal.
+    if (tid < 64) wave_chol(GS, k0, Lf, scl, pvt);
+    __syncthreads();
+    if (tid == 0) {
+        int k = k0;
+        if (a.nblk == 3) {
+            for (int j = 2 * m; j < 3 * m; j++) {
+                double nn = 0.0;
+                for (int c = 2 * m; c <= j; c++) nn = fma(Lf[j][c], Lf[j][c], nn);
+                // the oracle's test on the normalised projection of P, and a
+                // P column whose angle to span[X W, earlier P] has a sine
+                // below 1e-5: the transform would amplify the rounding of the
+                // basis and of A S by more than 1e5
+                const double rel = Lf[j][j] / sqrt(fmax(nn, 1e-300));
+                if (!(rel >= 1e-4) || !(pvt[j] >= 1e-10)) k = 2 * m;
+            }
+        }
+        double pmin = 1.0;
+        for (int j = 0; j < k; j++) pmin = fmin(pmin, pvt[j]);
+        for (int j = 0; j < k; j++)
+            if (!isfinite(pvt[j]) || !isfinite(scl[j])) bad = 1;
+        kk = k;
+        second = pmin < 1e-4;
+        if (a.flag) a.flag[1] = k < k0 ? 1 : 0;
+    }
+    __syncthreads();
+    const int k = kk;
+    tri_inverse(Lf, scl, k, Li);
+    __syncthreads();
+    if (second) {
+        // Li <- L2^-1 Li with L2 L2^T = Li S^T S Li^T (Cholesky-QR twice)
+        congruence(Li, GS, k, Lf, GS);
+        if (tid < 64) wave_chol(GS, k, Lf, scl, pvt);
+        __syncthreads();
+        tri_inverse(Lf, scl, k, GS);   // GS <- L2^-1 (lower)
+        __syncthreads();
+        for (int e0 = tid; e0 < k * k; e0 += 256) {
+            const int i = e0 / k, j = e0 - (e0 / k) * k;
             double v = 0.0;
-            for (int q = 0; q < m; q++) v = fma(A[i][m + q], Us[q][c], v);
-            Z[i][c] = v;
+            for (int q = j; q <= i; q++) v = fma(GS[i][q], Li[q][j], v);
+            Lf[i][j] = i >= j ? v : 0.0;
         }
         __syncthreads();
-        {
-            const int c = tid >> 4, d = tid & 15;
-            if (c < m && d < m && c <= d) {
-                double v = 0.0;
-                for (int q = 0; q < m; q++) v = fma(Us[q][c], Z[m + q][d], v);
-                Y[c][d] = v;
-            }
-        }
-        __syncthreads();
-        for (int e0 = tid; e0 < k * m; e0 += 256) {
-            const int i = e0 / m, c = e0 - (e0 / m) * m;
-            if (i >= m && i < 2 * m) {
-                const int d = i - m;
-                const double v = c <= d ? Y[c][d] : Y[d][c];
-                A[i][m + c] = v;
-            } else {
-                A[i][m + c] = Z[i][c];
-                A[m + c][i] = Z[i][c];
-            }
+        for (int e0 = tid; e0 < k * k; e0 += 256) {
+            const int i = e0 / k, j = e0 - (e0 / k) * k;
+            Li[i][j] = Lf[i][j];
         }
         __syncthreads();
     }
+    // the projected matrix Li (S^T A S) Li^T on the orthonormal basis S Li^T
+    congruence(Li, A, k, Lf, A);
     // 1. tridiagonalisation; the arithmetic deciding each reflector is
     // repeated identically in every wave, so no broadcast is needed
     {
@@ -605,22 +710,23 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
     }
     __syncthreads();
     if (tid == 0) a.flag[0] = bad ? -1 : 1 + nrounds;
-    // coefficients of the basis as stored: the W rows premultiplied by U
-    for (int e0 = tid; e0 < k * m; e0 += 256) {
+    // coefficients of the basis as stored: C = Li^T Y (rows of a dropped P
+    // block are zero)
+    for (int e0 = tid; e0 < k0 * m; e0 += 256) {
         const int i = e0 / m, j = e0 - (e0 / m) * m;
-        double v = Y[i][j];
-        if (wt && i >= m && i < 2 * m) {
-            v = 0.0;
-            for (int c = 0; c < m; c++) v = fma(Us[i - m][c], Y[m + c][j], v);
-        }
+        double v = 0.0;
+        if (i < k)
+            for (int r = i; r < k; r++) v = fma(Li[r][i], Y[r][j], v);
         a.coef[i * 2 * m + j] = v;
     }
-    // Next search direction in coefficient space: the W,P-components of C_X,
-    // made orthogonal to C_X and orthonormal (span{C_X, C_P} = span{C_X, Y}
-    // with Y = C_X with its X rows zeroed).
+    // Next search direction in coefficient space (step 10): on the
+    // orthonormal basis S Li^T, whose first m vectors span the old X, the
+    // components of the new X outside the old X, made orthogonal to the new X
+    // and orthonormal (span{C_X, C_P} = span{C_X, Y} with Y = C_X with its X
+    // rows zeroed).
     const int kr = k - m;
     if (kr == 0) {          // Rayleigh-Ritz on X alone: no search direction yet
-        for (int e0 = tid; e0 < k * m; e0 += 256) {
+        for (int e0 = tid; e0 < k0 * m; e0 += 256) {
             const int i = e0 / m, j = e0 - (e0 / m) * m;
             a.coef[i * 2 * m + m + j] = 0.0;
         }
@@ -693,13 +799,11 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
             }
         }
     }
-    for (int e0 = tid; e0 < k * m; e0 += 256) {
+    for (int e0 = tid; e0 < k0 * m; e0 += 256) {
         const int i = e0 / m, j = e0 - (e0 / m) * m;
-        double v = Z[i][j];
-        if (wt && i >= m && i < 2 * m) {
-            v = 0.0;
-            for (int c = 0; c < m; c++) v = fma(Us[i - m][c], Z[m + c][j], v);
-        }
+        double v = 0.0;
+        if (i < k)
+            for (int r = i; r < k; r++) v = fma(Li[r][i], Z[r][j], v);
         a.coef[i * 2 * m + m + j] = v;
     }
 }

@@ -110,11 +110,20 @@ extern "C" int hsym_autotune_geometry(int64_t n, const int64_t *rowptr, const in
 
     double best = -1.0;
     int used = 0;
-    for (int lr = 8; lr <= 12; lr++) {
-        for (int lc = lr - 3; lc <= lr - 1; lc++) {
-            const int R = 1 << lr, C = 1 << lc;
-            if (spmm_lds_bytes(storage, m, R, C) > 160 * 1024) continue;
-            const int flags = HSYM_GEOM_M(m) | HSYM_GEOM_PANEL(lr, lc);
+    // candidates: panel rows a multiple of 64 from 256 to 2048, chunks of
+    // 64 or 128 columns dividing them, those that fit the LDS at width m
+    for (int r64 = 4; r64 <= 32; r64 += (r64 < 8 ? 1 : r64 < 16 ? 2 : 4)) {
+        for (int lc = 6; lc <= 7; lc++) {
+            const int R = 64 * r64, C = 1 << lc;
+            if (R % C) continue;
+            Geom gt;
+            try {
+                gt = geometry_for(storage, m, k, r64, lc);
+            } catch (Error &) {
+                continue;
+            }
+            if (spmm_lds_bytes(storage, m, gt) > 160 * 1024) continue;
+            const int flags = HSYM_GEOM_M(m) | HSYM_GEOM_PANEL(r64, lc);
             double ms = -1.0;
             Handle hg;   // destroyed on every path, errors included
             int rc = hsym_create(&hg.h, k, S.rp.data(), S.ci.data(), sv, values_prec, storage, flags, st.s);

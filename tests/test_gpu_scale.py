@@ -3,8 +3,10 @@ nonzeros per full row (1.0e9 stored entries), built by streaming create.
 
 Checks (sampled where the full product is not formed on the host):
   - rows of H X at the start, middle and end of the matrix against the
-    oracle, for fp32 storage (fp64 blocks taken as they are, fp32 blocks) and
-    fp64 storage;
+    oracle: for fp32 storage (the mixed form: X staged in fp32, fp32
+    products and sums) against the oracle on the fp32 values and the
+    fp32-rounded block, to the size of an fp32 sum of some 400 terms; for
+    fp64 storage to 1e-12;
   - LOBPCG in the mixed form (fp32 storage) against the fp64 form, nev = 10,
     m = 16, tol 1e-6, Jacobi: both converge, and every eigenvalue of the
     mixed form is within 1e-6 relative of the fp64 one.
@@ -67,12 +69,14 @@ def test_c3_scale_mixed_vs_fp64():
     Yd = torch.empty_like(Xd)
     hs.spmm_sym(h32, Xd, Yd)
     torch.cuda.synchronize()
-    # fp32 values, the fp64 block as it is, fp64 products and sums
-    check_rows(Yd.cpu().numpy(), reference_rows(g, X, np.float32), 1e-12)
+    # fp32 values, the block staged in fp32, fp32 products and run sums:
+    # against the oracle on the same fp32 operands, within an fp32 sum of
+    # about 400 terms (gamma_400 u32 |H||X| is about 2.4e-5 |H||X|)
+    check_rows(Yd.cpu().numpy(), ref32, 2e-5)
     Yf = torch.empty((g.n, 16), dtype=torch.float32, device=dev)
     hs.spmm_sym_f32(h32, Xd.float(), Yf)
     torch.cuda.synchronize()
-    check_rows(Yf.double().cpu().numpy(), ref32, 1e-6)  # result rounded to fp32
+    check_rows(Yf.double().cpu().numpy(), ref32, 2e-5)  # result rounded to fp32
     del Yf
     t = time.perf_counter()
     st, ev32, rep32 = hs.lobpcg_solve(h32, 10, 16, 1e-6, precond="jacobi",

@@ -118,16 +118,22 @@ def test_spmm_edge_cases():
 
 
 def test_spmm_fp32_storage():
+    """The mixed form: fp32 values, X staged in fp32, products and run sums in
+    fp32 (run sums added across runs in fp64).  Against the fp64 oracle the
+    error is the rounding of H and X plus an fp32 sum of at most k terms:
+    gamma_{k+2}(u32) |H||X| (plus one more rounding for fp32 output)."""
     A = hsymgen.config("C1")
     H = oracle.SymMatrix.from_csr(A)
     X = hsymgen.gauss_block(3, A.n, 16)
+    k = int(np.diff(H.full()[0]).max()) + 1
     for f32 in (False, True):
         Y, info = _run(A, X, storage=hs.HSYM_FP32, f32=f32)
         Yref = H.spmm(X)
-        k = int(np.diff(H.full()[0]).max()) + 1
-        # rounding of H and X to fp32 plus fp32 accumulation: (k + 2) u32 |H||X|
-        assert np.all(np.abs(Y - Yref) <= 2 * _abs_bound(H, X, k + 2, U32))
+        assert np.all(np.abs(Y - Yref) <= _abs_bound(H, X, k + 3, U32))
         assert np.linalg.norm(Y - Yref) <= 1e-5 * np.linalg.norm(Yref)
+        # and the error is that of fp32 arithmetic, not of fp64: the
+        # fp64 result on the fp32-rounded operator is clearly closer
+        assert np.linalg.norm(Y - Yref) > 1e-9 * np.linalg.norm(Yref)
 
 
 def test_spmm_c2_size():
@@ -179,39 +185,30 @@ def test_streaming_create_matches_whole():
 
 @pytest.mark.parametrize("storage", [hs.HSYM_FP64, hs.HSYM_FP32])
 def test_index_code_widths(storage):
-    """16-bit tile-local codes on request where R * C <= 2^16, 32-bit
-    otherwise; the product is the same within rounding either way."""
+    """16-bit tile-local codes wherever R * C <= 2^16 (the default geometries
+    at widths of 4 and more), 32-bit otherwise; the product is the same
+    within rounding either way."""
     A = hsymgen.generate(9001, 150, 17)
     H = oracle.SymMatrix.from_csr(A)
     X = hsymgen.gauss_block(4, A.n, 16)
     Yref = H.spmm(X)
     tol = 1e-12 if storage == hs.HSYM_FP64 else 1e-5
-    I16 = hs.HSYM_INDEX16
-    cases = [(hs.HSYM_GEOM_M(16) | I16, 2),                            # R = 256, C = 64
-             (hs.HSYM_GEOM_M(16), 4),
-             (hs.HSYM_GEOM_PANEL(9, 7) | I16, 2),                      # R * C = 2^16 exactly
-             (hs.HSYM_GEOM_PANEL(9, 8) | hs.HSYM_GEOM_M(8) | I16, 4)]  # 2^17: 32-bit codes
-    out = []
-    for flags, width in cases:
-        M = hs.Matrix(A, storage=storage, flags=flags)
+    G = hs.HSYM_GEOM_PANEL
+    cases = [(0, 2, 16),                  # automatic
+             (G(4, 6), 2, 16),            # R = 256, C = 64
+             (G(16, 6), 2, 8),            # R * C = 2^16 exactly
+             (G(16, 7), 4, 4)]            # 2^17: 32-bit codes
+    for flags, width, m in cases:
+        M = hs.Matrix(A, storage=storage, geom_m=m, flags=flags)
         info = M.info
         assert info["index_bytes"] == width, (flags, info)
-        # LDS per row of the panel and of the chunk: an fp64 accumulator and
-        # the fp64-staged X row, for both storage precisions
-        m = 16 if (info["panel_rows"] + info["chunk_cols"]) * 16 * 16 <= 160 * 1024 else 8
         Xd = torch.from_numpy(X[:, :m].copy()).to(_dev())
         Yd = torch.empty_like(Xd)
         hs.spmm_sym(M.h, Xd, Yd)
         torch.cuda.synchronize()
         Y = Yd.cpu().numpy()
         assert np.linalg.norm(Y - Yref[:, :m]) <= tol * np.linalg.norm(Yref[:, :m])
-        out.append((info, Y))
         M.close()
-    # the same geometry with 16- and 32-bit codes: 2 bytes less per padded entry
-    (i16, y16), (i32, y32) = out[0], out[1]
-    assert i16["padded_entries"] == i32["padded_entries"]
-    assert i16["device_bytes"] <= i32["device_bytes"] - 2 * i32["padded_entries"] + 4096
-    assert np.linalg.norm(y16 - y32) <= 1e-13 * np.linalg.norm(y32)
 
 
 def test_create_from_device_csr():

@@ -60,21 +60,33 @@ def test_lincomb_in_place():
     assert np.allclose(Xd.cpu().numpy(), X @ C, rtol=1e-13, atol=1e-13)
 
 
-@pytest.mark.parametrize("nblk,m", [(3, 16), (3, 8), (2, 8), (1, 8), (3, 5), (2, 1)])
-def test_rayleigh_ritz(nblk, m):
+def _rr(nblk, m, S, A):
+    """Run the Rayleigh-Ritz kernel on the basis S (rows x k) for the
+    symmetric A (rows x rows): G = [S^T S | S^T A S]."""
     k = nblk * m
-    A = hsymgen.gauss_block(7 + k, k, k)
-    A = A + A.T + np.diag(np.arange(k, dtype=float))
+    G = np.hstack([S.T @ S, S.T @ (A @ S)])
     th = torch.zeros(m, dtype=torch.float64, device="cuda:0")
     ev = torch.zeros(k, dtype=torch.float64, device="cuda:0")
     coef = torch.zeros((k, 2 * m), dtype=torch.float64, device="cuda:0")
-    hs.hsym_kernel_rayleigh_ritz(nblk, m, dev(A), th, ev, coef)
+    dropped = hs.hsym_kernel_rayleigh_ritz(nblk, m, dev(G), th, ev, coef)
     torch.cuda.synchronize()
-    lam = np.linalg.eigvalsh(0.5 * (A + A.T))
+    return th.cpu().numpy(), ev.cpu().numpy(), coef.cpu().numpy(), dropped
+
+
+@pytest.mark.parametrize("nblk,m", [(3, 16), (3, 8), (2, 8), (1, 8), (3, 5), (2, 1)])
+def test_rayleigh_ritz(nblk, m):
+    """Orthonormal basis (S^T S = I): the Ritz pairs of the k x k projected
+    matrix against LAPACK, and the search-direction coefficients."""
+    k = nblk * m
+    A = hsymgen.gauss_block(7 + k, k, k)
+    A = A + A.T + np.diag(np.arange(k, dtype=float))
+    th, ev, C, dropped = _rr(nblk, m, np.eye(k), 0.5 * (A + A.T))
+    assert dropped == 0
+    A = 0.5 * (A + A.T)
+    lam = np.linalg.eigvalsh(A)
     nA = np.linalg.norm(A, 2)
-    assert np.max(np.abs(ev.cpu().numpy() - lam)) <= 50 * k * U * nA
-    assert np.max(np.abs(th.cpu().numpy() - lam[:m])) <= 50 * k * U * nA
-    C = coef.cpu().numpy()
+    assert np.max(np.abs(ev - lam)) <= 50 * k * U * nA
+    assert np.max(np.abs(th - lam[:m])) <= 50 * k * U * nA
     CX, CP = C[:, :m], C[:, m:]
     assert np.max(np.abs(A @ CX - CX * lam[None, :m])) <= 100 * k * U * nA
     assert np.max(np.abs(CX.T @ CX - np.eye(m))) <= 100 * k * U
@@ -88,6 +100,65 @@ def test_rayleigh_ritz(nblk, m):
         assert np.linalg.norm(Y - Q @ (Q.T @ Y)) <= 1e-11 * max(1.0, np.linalg.norm(Y))
     else:
         assert np.all(CP == 0)
+
+
+@pytest.mark.parametrize("nblk,m,skew", [(3, 16, 1e-3), (3, 8, 0.3), (2, 8, 1e-6), (3, 5, 0.5)])
+def test_rayleigh_ritz_measured_basis(nblk, m, skew):
+    """A basis S that is not orthonormal (columns perturbed away from an
+    orthonormal set by `skew`): the kernel orthonormalises it in coefficient
+    space from S^T S (Algorithm 1, step 7), so that S C_X are the Ritz
+    vectors of span(S): against LAPACK's generalized eigenproblem
+    (S^T A S) c = theta (S^T S) c, with S C_X and S C_P orthonormal, S C_P
+    orthogonal to S C_X, and span{S C_X, S C_P} holding the part of S C_X
+    outside the first block (step 10)."""
+    import scipy.linalg as sla
+    k = nblk * m
+    rows = 400
+    Q, _ = np.linalg.qr(hsymgen.gauss_block(31 + k, rows, k))
+    S = Q + skew * hsymgen.gauss_block(32 + k, rows, k)
+    B = hsymgen.gauss_block(33 + k, rows, rows)
+    A = 0.5 * (B + B.T) + np.diag(np.linspace(-3, 3, rows))
+    th, ev, C, dropped = _rr(nblk, m, S, A)
+    assert dropped == 0
+    Ah, Bh = S.T @ A @ S, S.T @ S
+    lam = sla.eigh(0.5 * (Ah + Ah.T), 0.5 * (Bh + Bh.T), eigvals_only=True)
+    nA = np.linalg.norm(A, 2)
+    kap = np.linalg.cond(Bh)
+    assert np.max(np.abs(th - lam[:m])) <= 100 * k * U * nA * kap
+    X = S @ C[:, :m]
+    P = S @ C[:, m:]
+    assert np.max(np.abs(X.T @ X - np.eye(m))) <= 100 * k * U * kap
+    R = A @ X - X * th[None, :]
+    # Ritz residuals are orthogonal to span(S)
+    assert np.max(np.abs(S.T @ R)) <= 100 * k * U * nA * kap * np.linalg.norm(S, 2)
+    if nblk > 1:
+        assert np.max(np.abs(P.T @ P - np.eye(m))) <= 1e-10 * kap
+        assert np.max(np.abs(X.T @ P)) <= 1e-10 * kap
+        Q1, _ = np.linalg.qr(S[:, :m])
+        Yo = X - Q1 @ (Q1.T @ X)
+        Qxp, _ = np.linalg.qr(np.hstack([X, P]))
+        assert np.linalg.norm(Yo - Qxp @ (Qxp.T @ Yo)) <= 1e-9 * kap * max(1.0, np.linalg.norm(Yo))
+
+
+def test_rayleigh_ritz_drops_dependent_p():
+    """A third block nearly inside the span of the first two (a pivot of its
+    normalised projection below 1e-4) is dropped for the iteration, as the
+    oracle drops P: its coefficient rows are zero and the Ritz values are
+    those of span[X W]."""
+    import scipy.linalg as sla
+    m, rows = 8, 300
+    Q, _ = np.linalg.qr(hsymgen.gauss_block(41, rows, 2 * m))
+    mix = hsymgen.gauss_block(42, 2 * m, m)
+    Pn = Q @ mix
+    Pn = Pn + 1e-7 * hsymgen.gauss_block(43, rows, m)
+    S = np.hstack([Q, Pn])
+    B = hsymgen.gauss_block(44, rows, rows)
+    A = 0.5 * (B + B.T)
+    th, ev, C, dropped = _rr(3, m, S, A)
+    assert dropped == 1
+    assert np.all(C[2 * m:] == 0)
+    lam = np.linalg.eigvalsh(Q.T @ A @ Q)
+    assert np.max(np.abs(th - lam[:m])) <= 1e-12 * np.linalg.norm(A, 2)
 
 
 @pytest.mark.parametrize("nb,m", [(0, 8), (1, 8), (2, 16), (2, 5)])

@@ -39,23 +39,23 @@ def _check(A, X, Y):
     assert np.all(np.abs(Y - ref) <= bound + 1e-300)
 
 
-@pytest.mark.parametrize("lr,lc", [(6, 3), (8, 5), (9, 7), (10, 6), (10, 8)])
-def test_explicit_geometry_parity(lr, lc):
+@pytest.mark.parametrize("r64,lc", [(1, 3), (4, 5), (8, 7), (12, 6), (16, 6)])
+def test_explicit_geometry_parity(r64, lc):
     A = hsymgen.generate(30_000, 60, 11)
     X = hsymgen.gauss_block(12, A.n, 8)
-    Y, info = _spmm(A, X, hs.HSYM_GEOM_M(8) | hs.HSYM_GEOM_PANEL(lr, lc))
-    assert (info["panel_rows"], info["chunk_cols"]) == (1 << lr, 1 << lc)
+    Y, info = _spmm(A, X, hs.HSYM_GEOM_M(8) | hs.HSYM_GEOM_PANEL(r64, lc))
+    assert (info["panel_rows"], info["chunk_cols"]) == (64 * r64, 1 << lc)
     _check(A, X, Y)
 
 
 def test_explicit_geometry_rejected():
     A = hsymgen.config("C1")
     with pytest.raises(hs.HsymError) as e:
-        hs.hsym_create(A.n, A.rowptr, A.colind, A.values, hs.HSYM_FP64, hs.HSYM_GEOM_PANEL(8, 9))
+        hs.hsym_create(A.n, A.rowptr, A.colind, A.values, hs.HSYM_FP64, hs.HSYM_GEOM_PANEL(4, 9))
     assert e.value.status == hs.HSYM_E_INVALID_ARG
     # fits at m = 8 but not at m = 16: the SpMM refuses it
     h = hs.hsym_create(A.n, A.rowptr, A.colind, A.values, hs.HSYM_FP64,
-                       hs.HSYM_GEOM_M(8) | hs.HSYM_GEOM_PANEL(10, 7))
+                       hs.HSYM_GEOM_M(8) | hs.HSYM_GEOM_PANEL(16, 6))
     X = torch.zeros((A.n, 16), dtype=torch.float64, device="cuda:0")
     with pytest.raises(hs.HsymError) as e:
         hs.spmm_sym(h, X, torch.empty_like(X))
@@ -71,12 +71,13 @@ def test_autotune_picks_fastest_and_is_correct(storage, m):
     timed = [t for t in table if t[2] > 0]
     assert len(timed) >= 3
     R, C, ms = min(timed, key=lambda t: t[2])
-    assert flags == hs.HSYM_GEOM_M(m) | hs.HSYM_GEOM_PANEL(R.bit_length() - 1, C.bit_length() - 1)
-    # every candidate fits the LDS at width m (an fp64 accumulator and an
-    # fp64-staged X row per panel and chunk row, for both storage precisions)
+    assert flags == hs.HSYM_GEOM_M(m) | hs.HSYM_GEOM_PANEL(R // 64, C.bit_length() - 1)
+    # every candidate fits the LDS at width m: an fp64 accumulator and an X
+    # row in the arithmetic precision per panel and chunk row
     Mr = 1 << (m - 1).bit_length()
+    sa = 8 if storage == hs.HSYM_FP64 else 4
     for R_, C_, _ in table:
-        assert (R_ + C_) * Mr * 16 <= 160 * 1024
+        assert (R_ + C_) * Mr * (8 + sa) <= 160 * 1024
     X = hsymgen.gauss_block(13, A.n, m)
     if storage == hs.HSYM_FP32:
         X = X.astype(np.float32).astype(np.float64)
@@ -85,10 +86,14 @@ def test_autotune_picks_fastest_and_is_correct(storage, m):
     if storage == hs.HSYM_FP64:
         _check(A, X, Y)
     else:
+        # fp32 arithmetic on the fp32 operator and the fp32 block
         v32 = A.values.astype(np.float32).astype(np.float64)
         H = oracle.SymMatrix(A.n, A.rowptr, A.colind, v32)
         ref = H.spmm(X)
-        assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref))
+        Habs = oracle.SymMatrix(A.n, A.rowptr, A.colind, np.abs(v32))
+        k = int(np.max(np.diff(A.rowptr) + np.bincount(A.colind, minlength=A.n))) + 1
+        u32 = 2.0 ** -24
+        assert np.all(np.abs(Y - ref) <= (k * u32 / (1 - k * u32)) * Habs.spmm(np.abs(X)) + 1e-300)
 
 
 def test_autotune_rejects_bad_input():
