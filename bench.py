@@ -1,16 +1,20 @@
 """Benchmark of the LOBPCG hot path on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): seeded
-synthetic CI-shaped symmetric matrix, n = 500,000, about 300 nonzeros per full
-row (75.5M stored upper entries), fp64 values, block width m, nev = 8,
-tol = 1e-8, Jacobi preconditioner.  One step = one complete LOBPCG solve to
-tolerance (every step of the hot path: SpMM, residual, preconditioner,
-Cholesky-QR, Rayleigh-Ritz, update), with the matrix already resident in HBM.
+Default workload (the configuration the headline metric, mixed against fp64
+time to tolerance, is quoted on): the largest single-GPU instance, a seeded
+synthetic CI-shaped symmetric matrix with n = 30,000,000 and about 500
+nonzeros per full row (7.5e9 stored upper entries), m = 16, nev = 10,
+tol = 1e-6, the block-diagonal preconditioner from exact 64x64 diagonal
+blocks.  One step = one complete LOBPCG solve of the mixed form (fp32
+storage and SpMM; Cholesky-QR, Rayleigh-Ritz and residuals in fp64) with the
+matrix resident in HBM; the fp64 form is built and solved once for the
+ratio.  The roofline is that of the SpMM launches inside the timed solves
+(HIP events on the solve stream); the per-phase split comes from the
+solver's own phase events.  cpu_baseline is the oracle on a bounded slab.
 
-Also measured, outside the timed steps: the symmetric SpMM alone (HIP events
-on the stream it runs on; roofline against 8 TB/s), the Lanczos baseline on
-the same GPU, the mixed-precision (fp32 SpMM) solve, and the CPU oracle on a
-bounded sample (cpu_baseline).
+--workload C2 gives the n = 500,000 fp64 line with the Lanczos baseline,
+the FOM preconditioner, the multi-level start block and the request loop;
+--workload C3 the n = 5,000,000 mixed-vs-fp64 line.
 
 Prints one JSON line.
 """
@@ -46,16 +50,16 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(m):
-    """HBM bytes per SpMM call from the committed counter summary (FETCH_SIZE
-    and WRITE_SIZE of k_zero_rows + k_spmm_panel, scaled by the factor the
-    same counters give for an elementwise kernel of known size), or None when
-    the summary is absent, for another block width, or the kernel sources
-    changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(path, m):
+    """HBM bytes per SpMM call from a committed counter summary (FETCH_SIZE
+    and WRITE_SIZE of the SpMM's kernels, scaled by the factor the same
+    counters give for an elementwise kernel of known size), or None when the
+    summary is absent, for another block width, or the kernel sources changed
+    since it was taken."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -180,12 +184,99 @@ def stream_create(hs, g, storage, dtype, flags, slab=250_000):
     return h
 
 
+def host_info():
+    """CPU model, cores this process may use, and RAM of the host."""
+    model, mem_kb = "unknown", 0
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    mem_kb = int(line.split()[1])
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cores": len(os.sched_getaffinity(0)), "ram_GB": round(mem_kb / 1e6, 1)}
+
+
+def traffic_file(form, m, n):
+    return os.path.join(ROOT, "profiles", "spmm_sym_%s_m%d_n%s_traffic.txt" % (form, m, short_n(n)))
+
+
+def short_n(n):
+    return "%dM" % (n // 1_000_000) if n % 1_000_000 == 0 else "%dk" % (n // 1000)
+
+
+def solve_timed(hs, torch, h, nev, m, tol, precond, opts, steps, warmup, label):
+    """warmup untimed solves, then steps timed ones (synchronised on both
+    sides); returns the times, the last report and eigenvalues, and the SpMM
+    launch time and the phase split summed over the timed solves."""
+    for k in range(warmup):
+        t = time.perf_counter()
+        st, ev, rep = hs.lobpcg_solve(h, nev, m, tol, precond=precond, opts=opts)
+        torch.cuda.synchronize()
+        log("%s: warm-up solve %d: status %d, %d iterations, %.2fs" % (label, k, st, rep.iters,
+                                                                      time.perf_counter() - t))
+    times, iters = [], []
+    phase = np.zeros(8)
+    spmm_calls = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        t = time.perf_counter()
+        st, ev, rep = hs.lobpcg_solve(h, nev, m, tol, precond=precond, opts=opts)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        iters.append(rep.iters)
+        phase += np.array(rep.phase_ms[:8])
+        spmm_calls += rep.spmm_calls
+        log("%s: timed solve %d: status %d, %d iterations, %.2fs" % (label, k, st, rep.iters, times[-1]))
+        assert st == hs.HSYM_OK, "%s solve did not converge (status %d)" % (label, st)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    return {"times": times, "total": total, "iters": iters, "rep": rep, "evals": ev, "phase_ms": phase,
+            "spmm_calls": spmm_calls}
+
+
+def phase_split(ph, steps):
+    names = ["spmm", "preconditioner", "cholesky_qr", "rr_gram", "rr_eigensolve", "update", "host_wait", "other"]
+    return {k: float(v) / max(1, steps) for k, v in zip(names, ph)}
+
+
+def spmm_only(args, name):
+    """The SpMM of the workload's timed form alone, for counter runs: the
+    handle (built as the benchmark builds it), the calibration kernel and
+    three calls."""
+    import torch
+    import hsymgen
+    import paper_1609_01689_amd as hs
+    cfg = hsymgen.CONFIGS[name]
+    m = 16
+    g = hsymgen.Generator(cfg["n"], cfg["N"], cfg["seed"])
+    storage = hs.HSYM_FP64 if args.form == "fp64" else hs.HSYM_FP32
+    flags = hs.HSYM_GEOM_M(m) | (hs.HSYM_BUILD_BLOCK64 if name == "C4" else 0)
+    h = stream_create(hs, g, storage, np.float64 if storage == hs.HSYM_FP64 else np.float32, flags)
+    calibration_kernel(torch)
+    X = torch.randn((g.n, m), dtype=torch.float64, device="cuda:0")
+    Y = torch.empty_like(X)
+    for _ in range(3):
+        hs.spmm_sym(h, X, Y)
+    torch.cuda.synchronize()
+    log("spmm-only %s %s: %s" % (name, args.form, hs.hsym_info(h)))
+    hs.hsym_destroy(h)
+
+
 def scale_workload(args, name):
-    """The large configurations (C3: n = 5M, N = 400; C4: n = 30M, N = 500):
-    nev = 10, m = 16, tol 1e-6, Jacobi (C3) or block-64 (C4) preconditioner,
-    the mixed form (fp32 storage) against the fp64 form.  Each handle is
-    built by streaming create from generator slabs and freed before the
-    next.  One step = one solve of the mixed form."""
+    """The large configurations (C3: n = 5M, N = 400, Jacobi; C4: n = 30M,
+    N = 500, block-64 preconditioner): nev = 10, m = 16, tol 1e-6, the mixed
+    form (fp32 storage) against the fp64 form.  Each handle is built by
+    streaming create from generator slabs and freed before the next.  One
+    step = one solve of the mixed form; the fp64 form is solved once for the
+    ratio."""
     import torch
     import hsymgen
     import paper_1609_01689_amd as hs
@@ -196,6 +287,7 @@ def scale_workload(args, name):
     g = hsymgen.Generator(cfg["n"], cfg["N"], cfg["seed"])
     dev = torch.device("cuda:0")
     res = {}
+    opts = hs.default_lobpcg_opts(seed=1, keep_history=0, timers=1)
     for label, storage, dtype in (("mixed", hs.HSYM_FP32, np.float32), ("fp64", hs.HSYM_FP64, np.float64)):
         t = time.perf_counter()
         h = stream_create(hs, g, storage, dtype, flags)
@@ -218,46 +310,102 @@ def scale_workload(args, name):
         del X, Y
         vb = 4 if storage == hs.HSYM_FP32 else 8
         alg = info["nnz_stored"] * (vb + 4) + g.n * m * 16
-        opts = hs.default_lobpcg_opts(seed=1, keep_history=0)
-        times = []
-        for k in range(args.warmup + args.steps):
-            t = time.perf_counter()
-            stt, ev, rep = hs.lobpcg_solve(h, nev, m, tol, precond=precond, opts=opts)
-            torch.cuda.synchronize()
-            if k >= args.warmup:
-                times.append(time.perf_counter() - t)
-            log("%s %s: solve %d: status %d, %d iterations, %.2fs" % (name, label, k, stt, rep.iters,
-                                                                     time.perf_counter() - t))
-        live = rep.phase_ms[0] / max(1, rep.spmm_calls)
-        res[label] = {"build_s": build_s, "s_to_tol": float(np.mean(times)), "iters": rep.iters, "status": stt,
-                      "evals": ev.tolist(), "resnorm_max": float(max(rep.resnorm[:nev])),
-                      "spmm_ms": spmm_ms, "spmm_ms_in_solve": live,
-                      "spmm_GBs_algorithmic": alg / (live * 1e-3) / 1e9, "device_bytes": info["device_bytes"]}
+        if label == "mixed":
+            steps, warmup = args.steps, args.warmup
+        else:
+            steps, warmup = 1, 0
+        r = solve_timed(hs, torch, h, nev, m, tol, precond, opts, steps, warmup, "%s %s" % (name, label))
+        live = r["phase_ms"][0] / max(1, r["spmm_calls"])
+        rep = r["rep"]
+        res[label] = {"build_s": build_s, "s_to_tol": r["total"] / steps, "times": r["times"],
+                      "iters": int(np.median(r["iters"])), "evals": r["evals"].tolist(),
+                      "resnorm_max": float(max(rep.resnorm[:nev])), "spmm_ms_microbench": spmm_ms,
+                      "spmm_ms_in_solve": live, "spmm_calls_timed": r["spmm_calls"], "algorithmic_bytes": alg,
+                      "spmm_GBs_algorithmic": alg / (live * 1e-3) / 1e9, "device_bytes": info["device_bytes"],
+                      "phase_ms_per_solve": phase_split(r["phase_ms"], steps), "p_dropped": rep.p_dropped,
+                      "nnz_stored": int(info["nnz_stored"])}
+        log("%s %s: %s" % (name, label, json.dumps(res[label])))
         hs.hsym_destroy(h)
         torch.cuda.synchronize()
     ev32, ev64 = np.array(res["mixed"]["evals"]), np.array(res["fp64"]["evals"])
+    mixed = res["mixed"]
+    times = sorted(mixed["times"])
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_slab(g, cfg, m, nev, tol, precond, mixed["iters"], args.cpu_budget)
+        log("cpu baseline: %s" % cpu)
+    tf = traffic_file("fp32", m, g.n)
     out = {
         "metric": METRIC,
-        "value": 1.0 / res["mixed"]["s_to_tol"],
+        "value": args.steps / (mixed["s_to_tol"] * args.steps),
         "unit": "solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1000.0 * res["mixed"]["s_to_tol"],
+        "ms_per_step": 1000.0 * mixed["s_to_tol"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-storage/f64", "data": "synthetic",
         "config": {"workload": "GEN n=%d N=%d seed=%d (CI-shaped upper CSR), LOBPCG nev=%d m=%d tol=%g %s, "
-                               "mixed (fp32 storage) vs fp64" % (cfg["n"], cfg["N"], cfg["seed"], nev, m, tol,
-                                                                 precond)},
-        "roofline": {"bound": "hbm", "achieved": res["mixed"]["spmm_GBs_algorithmic"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": res["mixed"]["spmm_GBs_algorithmic"] / HBM_PEAK_GBS, "traffic": None,
+                               "mixed (fp32 storage, fp32 SpMM) vs fp64" % (cfg["n"], cfg["N"], cfg["seed"], nev, m,
+                                                                            tol, precond),
+                   "n": g.n, "nnz_stored": mixed["nnz_stored"], "block_width": m, "nev": nev, "tol": tol},
+        "s_to_tol": mixed["s_to_tol"],
+        "p50_s": times[len(times) // 2],
+        "p99_s": times[min(len(times) - 1, int(0.99 * len(times)))],
+        "iters": mixed["iters"],
+        "roofline": {"bound": "hbm", "achieved": mixed["spmm_GBs_algorithmic"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": mixed["spmm_GBs_algorithmic"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(tf, m),
                      "kernel": "spmm_sym fp32 storage m=16 (k_zero_rows + k_spmm_panel)",
-                     "launch_ms": res["mixed"]["spmm_ms_in_solve"]},
-        "cpu_baseline": None,
-        "mixed_vs_fp64_speedup": res["fp64"]["s_to_tol"] / res["mixed"]["s_to_tol"],
+                     "launch_ms": mixed["spmm_ms_in_solve"], "launches_timed": mixed["spmm_calls_timed"],
+                     "algorithmic_bytes": mixed["algorithmic_bytes"]},
+        "cpu_baseline": cpu,
+        "mixed_vs_fp64_speedup": res["fp64"]["s_to_tol"] / mixed["s_to_tol"],
+        "mixed_vs_fp64_spmm_speedup": res["fp64"]["spmm_ms_in_solve"] / mixed["spmm_ms_in_solve"],
         "max_rel_eval_diff_mixed_vs_fp64": float(np.max(np.abs(ev32 - ev64) / np.abs(ev64))),
         "per_pair_rel_diff": (np.abs(ev32 - ev64) / np.abs(ev64)).tolist(),
+        "phase_ms_per_solve": mixed["phase_ms_per_solve"],
         "forms": res,
     }
     print(json.dumps(out))
+
+
+def cpu_baseline_slab(g, cfg, m, nev, tol, precond, gpu_iters, budget_s, rows=1_000_000):
+    """The oracle on a bounded slab of the workload: the principal submatrix
+    of the first `rows` rows (same generator, same density).  Oracle LOBPCG
+    iterations run for about budget_s seconds; the per-iteration time, which
+    grows linearly with n at fixed nonzeros per row, is scaled by n / rows
+    and by the GPU's iteration count to a full-solve rate."""
+    import oracle
+    import hsymgen
+    rows = min(rows, g.n)
+    rp, ci, v = g.rows(0, rows, np.float64)
+    keep = ci < rows
+    row_of = np.repeat(np.arange(rows, dtype=np.int64), np.diff(rp))
+    rp2 = np.zeros(rows + 1, np.int64)
+    np.cumsum(np.bincount(row_of[keep], minlength=rows), out=rp2[1:])
+    A = hsymgen.UpperCSR(rows, rp2, np.ascontiguousarray(ci[keep]), np.ascontiguousarray(v[keep]))
+    H = oracle.SymMatrix.from_csr(A)
+    H.full()
+    H.norm1()
+    X0 = hsymgen.gauss_block(1, rows, m)
+    t = time.perf_counter()
+    r = oracle.lobpcg(H, nev, m, tol, X0=X0, precond=precond, maxit=2, keep_history=False)
+    dt = time.perf_counter() - t
+    per_it = dt / max(1, r.iters)
+    its = 2 + int(max(0, budget_s - dt) / max(per_it, 1e-9))
+    if its > 2:
+        t = time.perf_counter()
+        r = oracle.lobpcg(H, nev, m, tol, X0=X0, precond=precond, maxit=its, keep_history=False)
+        dt = time.perf_counter() - t
+        per_it = dt / max(1, r.iters)
+    hi = host_info()
+    threads = int(os.environ.get("OMP_NUM_THREADS", hi["cores"]))
+    solve_s = per_it * (g.n / rows) * gpu_iters
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": min(threads, hi["cores"]), "kind": "oracle",
+            "cpu_model": hi["cpu_model"], "ram_GB": hi["ram_GB"],
+            "sample": "slab: %d oracle LOBPCG iterations (%s, %.1f s, %.3f s/iteration) on the principal "
+                      "submatrix of the first %d rows (%d stored entries), per-iteration time scaled by "
+                      "n/rows = %.0f and by the %d iterations of the GPU solve" %
+                      (r.iters, precond, dt, per_it, rows, int(rp2[-1]), g.n / rows, gpu_iters)}
 
 
 def cpu_baseline(A, m, nev, tol, gpu_iters, budget_s):
@@ -292,28 +440,38 @@ def cpu_baseline(A, m, nev, tol, gpu_iters, budget_s):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 3 for C3/C4, 5 for C2)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--m", type=int, default=16, help="block width (8 or 16)")
+    ap.add_argument("--m", type=int, default=16, help="block width of the C2 line (8 or 16)")
     ap.add_argument("--spmm-reps", type=int, default=50)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4"],
-                    help="C2 (default bench line) or the large configurations C3 / C4")
+    ap.add_argument("--workload", default="C4", choices=["C2", "C3", "C4"],
+                    help="C4 (default: n = 30M, the mixed-vs-fp64 line), C3, or C2 (n = 500k, fp64, "
+                         "with the Lanczos, FOM, multi-level and serving extras)")
+    ap.add_argument("--spmm-only", action="store_true",
+                    help="build the workload's handle and run three SpMMs and the calibration kernel "
+                         "(for counter runs)")
+    ap.add_argument("--form", default="fp32", choices=["fp32", "fp64"], help="storage of --spmm-only")
     ap.add_argument("--serve-requests", type=int, default=150,
-                    help="requests of the request-loop measurement (0: skip)")
+                    help="requests of the request-loop measurement of the C2 line (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.steps is None:
+        args.steps = 5 if args.workload == "C2" else 3
 
     import torch
     import hsymgen
     import paper_1609_01689_amd as hs
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    if args.spmm_only and args.workload != "C2":
+        spmm_only(args, args.workload)
+        return
     if args.workload != "C2":
         scale_workload(args, args.workload)
         return
@@ -468,7 +626,7 @@ def main():
         "p99_s": times[min(len(times) - 1, int(0.99 * len(times)))],
         "iters": int(np.median(iters)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(m),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(TRAFFIC_FILE, m),
                      "kernel": "spmm_sym fp64 m=%d (k_zero_rows + k_spmm_panel)" % m,
                      "launch_ms": live_ms, "launches_timed": spmm_live_calls, "algorithmic_bytes": alg,
                      "microbench_ms": spmm_ms},

@@ -221,6 +221,10 @@ typedef struct {
                                the solve runs without graphs                    */
     int fom_iters;          /* FOM steps of HSYM_PRECOND_FOM, 1..4; default 3 (the
                                paper performs up to three)                       */
+    int timers;             /* 1: time every phase of the iteration with events on
+                               the solve stream (lobpcg_report.phase_ms[1..7], the
+                               split of Section 5.2, Fig. 7); default 0.  Phases
+                               replayed from a graph are not timed              */
 } lobpcg_opts;
 
 #define HSYM_MAX_BLOCK 16
@@ -237,7 +241,17 @@ typedef struct {
     double seconds;                   /* wall time of the solve                      */
     double phase_ms[8];               /* [0]: device time of the block SpMMs launched on
                                          the context's own stream (events; SpMMs of
-                                         batched rounds are not timed); [1..7] 0 */
+                                         batched rounds are not timed).  With
+                                         opts.timers, device time of [1] the
+                                         preconditioner (with the Jacobi apply, the
+                                         first Gram of the orthogonalisation, fused
+                                         into it), [2] the Cholesky-QR of W, [3] the
+                                         Gram products of Rayleigh-Ritz, [4] the
+                                         Rayleigh-Ritz eigensolve, [5] the update of
+                                         X, P, AX, AP with the next residuals and
+                                         norms, [7] the start block, repairs and
+                                         status copies; [6] is host wall time spent
+                                         waiting for the stream.  Otherwise 0      */
     int history_len;
     double history[HSYM_MAX_HISTORY]; /* max_{j<=nev} rho_j per iteration           */
     int rr_rounds_max;                /* most multisection rounds any Rayleigh-Ritz eigenvalue search took */

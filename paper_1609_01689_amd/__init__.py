@@ -65,7 +65,8 @@ class hsym_info_t(ctypes.Structure):
 class lobpcg_opts(ctypes.Structure):
     _fields_ = [("maxit", ctypes.c_int), ("seed", ctypes.c_uint64), ("check_every", ctypes.c_int),
                 ("no_precond_iters", ctypes.c_int), ("near", ctypes.c_double), ("guard", ctypes.c_double),
-                ("keep_history", ctypes.c_int), ("graph", ctypes.c_int), ("fom_iters", ctypes.c_int)]
+                ("keep_history", ctypes.c_int), ("graph", ctypes.c_int), ("fom_iters", ctypes.c_int),
+                ("timers", ctypes.c_int)]
 
 
 class lobpcg_report(ctypes.Structure):

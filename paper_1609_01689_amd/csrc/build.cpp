@@ -66,12 +66,11 @@ size_t spmm_lds_bytes(int storage, int m, const Geom &g) {
 }
 
 // Lane groups of the 1024-thread SpMM workgroup at block width M: a group
-// holds one 16-byte piece of an X row per lane (the whole row when it is
-// shorter), so the number of groups (segments per piece) is 1024 divided by
-// the lanes one row needs.
+// holds spmm_lane_elems(M) elements of an X row per lane, so the number of
+// groups (segments per piece) is 1024 divided by the lanes one row needs.
 static int segments_for(int storage, int M) {
-    const int sa = storage == HSYM_FP64 ? 8 : 4;
-    const int mw = M * sa >= 16 ? 16 / sa : M;
+    (void)storage;
+    const int mw = spmm_lane_elems(M);
     return 1024 / (M / mw);
 }
 
@@ -131,11 +130,9 @@ Geom geometry_for(int storage, int m, int64_t n, int r64, int lc) {
 // one panel
 // ---------------------------------------------------------------------------
 struct PanelOut {
-    std::vector<TileDesc> tiles;      // pieces, base relative to the panel
-    std::vector<uint32_t> idx;        // codes (narrowed to 16 bits on upload when the geometry allows)
-    std::vector<uint16_t> perm;
-    std::vector<double> v64;
-    std::vector<float> v32;
+    std::vector<TileDesc> tiles;      // pieces, base (bytes) relative to the panel
+    std::vector<unsigned char> blob;  // the pieces' codes, perm and values
+    int64_t positions = 0;            // padded entries of the pieces
     int64_t next = 0;                 // external tiles
     std::vector<double> colsum;       // |a| summed per column, window [r0, r0 + size)
     double rowsum_max = 0.0;
@@ -248,20 +245,31 @@ static void build_panel(int64_t n, int64_t r0, int64_t r1, const Geom &geo, int 
             const int pc = (int)std::min<int64_t>(cut, tcnt - q0);
             const int len = (pc + G - 1) / G;
             const int64_t E = (int64_t)G * len;
-            const int64_t base = ((int64_t)out.idx.size() + 7) & ~(int64_t)7;
+            // the piece's bytes: codes (idx_bytes each), perm (2 each) and
+            // values, each part padded to a multiple of 16 bytes
+            const int ib = geo.idx_bytes, sv = storage == HSYM_FP64 ? 8 : 4;
+            const int64_t oc = 0, op = (E * ib + 15) & ~(int64_t)15, ov = op + ((E * 2 + 15) & ~(int64_t)15);
+            const int64_t bytes = ov + ((E * sv + 15) & ~(int64_t)15);
+            const int64_t base = (int64_t)out.blob.size();
+            out.blob.resize((size_t)(base + bytes), 0);
+            unsigned char *bp = out.blob.data() + base;
             const int64_t last = q0 + pc - 1;
-            const uint32_t lastcode = ((uint32_t)tr[last] << cb) | (uint32_t)tc[last];
-            out.idx.resize((size_t)(base + E), lastcode);
-            out.perm.resize((size_t)(base + E), 0);
-            if (storage == HSYM_FP64) out.v64.resize((size_t)(base + E), 0.0);
-            else out.v32.resize((size_t)(base + E), 0.0f);
-            // the alignment gap before base repeats a code with value 0 too
+            const uint32_t lastcode = ((uint32_t)tr[(size_t)last] << cb) | (uint32_t)tc[(size_t)last];
+            auto put_code = [&](int64_t at, uint32_t c) {
+                if (ib == 2) { const uint16_t h = (uint16_t)c; memcpy(bp + oc + at * 2, &h, 2); }
+                else memcpy(bp + oc + at * 4, &c, 4);
+            };
+            auto put_val = [&](int64_t at, int64_t p) {
+                if (sv == 8) { const double v = vin64 ? vin64[p] : (double)vin32[p]; memcpy(bp + ov + at * 8, &v, 8); }
+                else { const float v = vin64 ? (float)vin64[p] : vin32[p]; memcpy(bp + ov + at * 4, &v, 4); }
+            };
+            // padding positions repeat the last code with value 0
+            for (int64_t at = 0; at < E; at++) put_code(at, lastcode);
             for (int64_t q = 0; q < pc; q++) {
-                const int64_t at = base + (q % len) * G + q / len;
-                const int64_t k = q0 + q, p = tp[(size_t)k];
-                out.idx[(size_t)at] = ((uint32_t)tr[(size_t)k] << cb) | (uint32_t)tc[(size_t)k];
-                if (storage == HSYM_FP64) out.v64[(size_t)at] = vin64 ? vin64[p] : (double)vin32[p];
-                else out.v32[(size_t)at] = vin64 ? (float)vin64[p] : vin32[p];
+                const int64_t at = (q % len) * G + q / len;
+                const int64_t k = q0 + q;
+                put_code(at, ((uint32_t)tr[(size_t)k] << cb) | (uint32_t)tc[(size_t)k]);
+                put_val(at, tp[(size_t)k]);
             }
             // column-major order of the piece (a stable counting sort by
             // column keeps rows ascending within a column)
@@ -274,14 +282,16 @@ static void build_panel(int64_t n, int64_t r0, int64_t r1, const Geom &geo, int 
             // position of the row order (value 0), which exists when E > pc
             const int64_t padpos = E > pc ? ((int64_t)pc % len) * G + pc / len : 0;
             for (int64_t q = 0; q < E; q++) {
-                const int64_t at = base + (q % len) * G + q / len;
+                const int64_t at = (q % len) * G + q / len;
                 int64_t src = padpos;
                 if (q < pc) {
                     const int64_t o = order[(size_t)q];
                     src = (o % len) * G + o / len;
                 }
-                out.perm[(size_t)at] = (uint16_t)src;
+                const uint16_t h = (uint16_t)src;
+                memcpy(bp + op + at * 2, &h, 2);
             }
+            out.positions += E;
             TileDesc td;
             td.base = base;
             td.len = len;
@@ -290,15 +300,6 @@ static void build_panel(int64_t n, int64_t r0, int64_t r1, const Geom &geo, int 
             td.flags = (q0 == 0 ? TILE_FIRST : 0) | (q0 + pc == tcnt ? TILE_LAST : 0);
             out.tiles.push_back(td);
         }
-    }
-    // a whole number of 8-entry groups per panel keeps every base aligned
-    const size_t tot = (out.idx.size() + 7) & ~(size_t)7;
-    if (tot != out.idx.size()) {
-        const uint32_t lc = out.idx.empty() ? 0u : out.idx.back();
-        out.idx.resize(tot, lc);
-        out.perm.resize(tot, 0);
-        if (storage == HSYM_FP64) out.v64.resize(tot, 0.0);
-        else out.v32.resize(tot, 0.0f);
     }
 }
 
@@ -347,20 +348,16 @@ struct Builder {
     std::vector<float> carry_v32;
     // device arrays
     DevVec<TileDesc> tiles;
-    DevVec<uint32_t> idx;
-    DevVec<uint16_t> idx16v;
-    DevVec<uint16_t> perm;
-    DevVec<double> v64;
-    DevVec<float> v32;
+    DevVec<unsigned char> blob;
     std::vector<int64_t> panel_tile_ptr{0};
     std::vector<int64_t> panel_weight;  // per panel: padded entries + a per-piece cost, in entry units
     std::vector<double> diag;          // n
     std::vector<double> abssum;        // n: row+column absolute sums
     double norm1 = 0.0;
-    int64_t nentries = 0, npieces = 0, ntiles = 0, next = 0;
+    int64_t nentries = 0, npieces = 0, ntiles = 0, next = 0, nbytes = 0;
 
     void release() {
-        tiles.release(); idx.release(); idx16v.release(); perm.release(); v64.release(); v32.release();
+        tiles.release(); blob.release();
         preq.release(); prelam.release();
     }
 
@@ -381,24 +378,20 @@ struct Builder {
             });
             // concatenate in panel order
             std::vector<TileDesc> t;
-            std::vector<uint32_t> c;
-            std::vector<uint16_t> pm;
-            std::vector<double> d64;
-            std::vector<float> d32;
+            std::vector<unsigned char> bl;
             std::vector<double> pq, pl;
+            int64_t pos = 0;
             for (int64_t k = 0; k < b1 - b0; k++) {
                 PanelOut &o = outs[(size_t)k];
                 int64_t r0 = (b0 + k) * R;
-                int64_t entry_off = nentries + (int64_t)c.size();
+                const int64_t byte_off = nbytes + (int64_t)bl.size();
                 for (auto td : o.tiles) {
-                    td.base += entry_off;
+                    td.base += byte_off;
                     t.push_back(td);
                     if (td.flags & TILE_FIRST) ntiles++;
                 }
-                c.insert(c.end(), o.idx.begin(), o.idx.end());
-                pm.insert(pm.end(), o.perm.begin(), o.perm.end());
-                d64.insert(d64.end(), o.v64.begin(), o.v64.end());
-                d32.insert(d32.end(), o.v32.begin(), o.v32.end());
+                bl.insert(bl.end(), o.blob.begin(), o.blob.end());
+                pos += o.positions;
                 next += o.next;
                 pq.insert(pq.end(), o.preq.begin(), o.preq.end());
                 pl.insert(pl.end(), o.prelam.begin(), o.prelam.end());
@@ -413,20 +406,14 @@ struct Builder {
                 for (size_t w = 0; w < o.colsum.size(); w++) abssum[(size_t)r0 + w] += o.colsum[w];
                 nnz += o.nnz;
                 PanelOut().tiles.swap(o.tiles);
+                std::vector<unsigned char>().swap(o.blob);
             }
             tiles.append(t.data(), (int64_t)t.size());
-            if (geo.idx_bytes == 2) {
-                std::vector<uint16_t> c16(c.begin(), c.end());
-                idx16v.append(c16.data(), (int64_t)c16.size());
-            } else {
-                idx.append(c.data(), (int64_t)c.size());
-            }
-            perm.append(pm.data(), (int64_t)pm.size());
-            if (storage == HSYM_FP64) v64.append(d64.data(), (int64_t)d64.size());
-            else v32.append(d32.data(), (int64_t)d32.size());
+            blob.append(bl.data(), (int64_t)bl.size());
             if (b64) { preq.append(pq.data(), (int64_t)pq.size()); prelam.append(pl.data(), (int64_t)pl.size()); }
             npieces += (int64_t)t.size();
-            nentries += (int64_t)c.size();
+            nentries += pos;
+            nbytes += (int64_t)bl.size();
             npanels_done = b1;
         }
     }
@@ -515,9 +502,7 @@ void builder_begin(hsym_matrix *H, int64_t nnz_hint) {
     b->abssum.assign((size_t)H->n, 0.0);
     if (nnz_hint > 0) {
         int64_t est = nnz_hint + nnz_hint / 8 + 4096;
-        if (geo.idx_bytes == 2) b->idx16v.reserve(est); else b->idx.reserve(est);
-        b->perm.reserve(est);
-        if (H->storage == HSYM_FP64) b->v64.reserve(est); else b->v32.reserve(est);
+        b->blob.reserve(est * ((int64_t)geo.idx_bytes + 2 + (H->storage == HSYM_FP64 ? 8 : 4)));
     }
     std::lock_guard<std::mutex> g(g_builders_mu);
     g_builders.push_back({H, b.release()});
@@ -547,31 +532,15 @@ void builder_finish(hsym_matrix *H) {
     if (b->next_row != H->n || b->carry_rp.size() != 1)
         fail(HSYM_E_INVALID_ARG, "streaming create finished before all n rows were appended");
     DeviceTiles &dt = H->tiles;
-    // 16 more positions at the end of every stream: the SpMM stages a piece
-    // in whole 16-byte loads, which may read past its last position
-    {
-        std::vector<uint32_t> z32(16, 0);
-        std::vector<uint16_t> z16(16, 0);
-        std::vector<double> zd(16, 0.0);
-        std::vector<float> zf(16, 0.0f);
-        if (b->geo.idx_bytes == 2) b->idx16v.append(z16.data(), 16); else b->idx.append(z32.data(), 16);
-        b->perm.append(z16.data(), 16);
-        if (H->storage == HSYM_FP64) b->v64.append(zd.data(), 16); else b->v32.append(zf.data(), 16);
-    }
     dt.g = b->geo;
     dt.npanels = (H->n + b->R - 1) / b->R;
     dt.nchunks = (H->n + b->geo.C - 1) / b->geo.C;
     dt.ntiles = b->ntiles; dt.npieces = b->npieces; dt.nentries = b->nentries; dt.next = b->next;
+    dt.nbytes = b->nbytes;
     dt.tiles = b->tiles.p;
-    dt.idx = b->geo.idx_bytes == 2 ? (void *)b->idx16v.p : (void *)b->idx.p;
-    dt.perm = b->perm.p;
-    dt.vals = H->storage == HSYM_FP64 ? (void *)b->v64.p : (void *)b->v32.p;
-    const int64_t idx_cap_bytes = b->geo.idx_bytes == 2 ? b->idx16v.cap * 2 : b->idx.cap * 4;
-    b->tiles.p = nullptr; b->idx.p = nullptr; b->idx16v.p = nullptr; b->perm.p = nullptr;
-    b->v64.p = nullptr; b->v32.p = nullptr;
-    int vs = H->storage == HSYM_FP64 ? 8 : 4;
-    dt.bytes = b->tiles.cap * (int64_t)sizeof(TileDesc) + idx_cap_bytes + b->perm.cap * 2 +
-               (H->storage == HSYM_FP64 ? b->v64.cap : b->v32.cap) * vs;
+    dt.blob = b->blob.p;
+    b->tiles.p = nullptr; b->blob.p = nullptr;
+    dt.bytes = b->tiles.cap * (int64_t)sizeof(TileDesc) + b->blob.cap;
     // panel pointers
     HIPCHK(hipMalloc(&dt.panel_tile_ptr, sizeof(int64_t) * b->panel_tile_ptr.size()));
     HIPCHK(hipMemcpy(dt.panel_tile_ptr, b->panel_tile_ptr.data(), sizeof(int64_t) * b->panel_tile_ptr.size(),
@@ -626,7 +595,7 @@ void builder_finish(hsym_matrix *H) {
 }
 
 void free_tiles(DeviceTiles *dt) {
-    void *ptrs[] = {dt->panel_tile_ptr, dt->panel_order, dt->tiles, dt->idx, dt->perm, dt->vals};
+    void *ptrs[] = {dt->panel_tile_ptr, dt->panel_order, dt->tiles, dt->blob};
     for (void *p : ptrs) if (p) (void)hipFree(p);
     *dt = DeviceTiles();
 }

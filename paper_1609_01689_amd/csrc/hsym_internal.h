@@ -11,6 +11,13 @@
 
 namespace hsym {
 
+// Elements of an X row that one lane of the SpMM handles: 2 (one 16-byte LDS
+// read at fp64, 8 bytes at fp32), so that a run's flush issues two fp64 LDS
+// atomics per lane, the count measured fastest on gfx950 (four per lane, as
+// 32-byte fp64 or 16-byte fp32 lanes need, run at half the rate).
+__host__ __device__ constexpr int spmm_lane_elems(int M) { return M < 2 ? M : 2; }
+
+
 // block widths are rounded up to the next of 1, 2, 4, 8, 16 for the kernels
 inline int round_m(int m) { return m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : m <= 8 ? 8 : 16; }
 
@@ -33,22 +40,23 @@ void check_hip(hipError_t e, const char *what);
 // chunks of C columns (C a power of two dividing R).  The strictly-upper
 // entries of one panel that fall into one chunk form a tile; a tile with more
 // than MAXE entries is cut into pieces of consecutive entries.  A piece of cnt
-// entries is padded to E = G * len and stored as three arrays:
+// entries is padded to E = G * len positions and stored as one contiguous run
+// of bytes (16-byte aligned) holding three parts, each padded to 16 bytes:
 //   - codes: local row << cb | local column (cb = log2 C), 16-bit when
 //     R * C <= 2^16, else 32-bit, in row-major order (rows ascending, columns
 //     ascending within a row), cut into G equal segments: entry q of the
-//     row-major order is segment q / len, step q % len, and sits at
-//     base + step * G + segment;
-//   - values (T), in the same positions;
+//     row-major order is segment q / len, step q % len, and sits at position
+//     step * G + segment;
 //   - perm (16-bit): the column-major order of the same entries, cut into G
-//     segments the same way; each position holds the staged position of the
-//     entry (its index within the piece's codes/values).
+//     segments the same way; each position holds the position of the entry in
+//     the code and value parts;
+//   - values (T), at the positions of their codes.
 // Padding positions repeat the code of the piece's last entry with value 0.
 // A tile is "own" when its chunk lies inside the panel (its transposed half
 // lands in the panel's rows) and "external" otherwise.
 // ---------------------------------------------------------------------------
 struct TileDesc {
-    int64_t base;          // first stored position (a multiple of 8)
+    int64_t base;          // first byte of the piece (a multiple of 16)
     int32_t len;           // steps per segment
     int32_t chunk;         // global chunk index g: columns [g*C, g*C+C)
     int32_t ext;           // 1 for an external tile, 0 for an own tile
@@ -71,9 +79,8 @@ struct DeviceTiles {
     int64_t *panel_tile_ptr = nullptr;   // pieces of panel p: [ptp[p], ptp[p+1])
     int32_t *panel_order = nullptr;      // panel of workgroup b (see build.cpp: per-XCD runs)
     TileDesc *tiles = nullptr;
-    void *idx = nullptr;                 // codes (uint16_t or uint32_t)
-    uint16_t *perm = nullptr;
-    void *vals = nullptr;
+    unsigned char *blob = nullptr;       // the pieces
+    int64_t nbytes = 0;
     int64_t bytes = 0;
 };
 
@@ -141,9 +148,7 @@ struct SpmmJob {
     const int64_t *ptp;
     const int32_t *porder;
     const TileDesc *tiles;
-    const void *idx;
-    const uint16_t *perm;
-    const void *vals;
+    const unsigned char *blob;
     const void *diag;
     const double *X;
     int64_t ldx;

@@ -21,6 +21,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "dense.h"
 
 namespace hsym {
@@ -104,6 +106,13 @@ struct Lobpcg {
     std::vector<void *> allocs;
     hipEvent_t ev_spmm[2] = {nullptr, nullptr};   // brackets the latest SpMM on s
     bool spmm_pending = false;
+    // opts.timers: an event opens each phase's stretch of the stream; the
+    // stretches are added to phase_ms[] at the next synchronisation
+    static constexpr int NMARK = 24;
+    hipEvent_t ev_mark[NMARK] = {};
+    int mark_phase[NMARK] = {};
+    int nmark = 0;
+    bool range_open = false;
     // graphs of the steady-state iteration (opts.graph): phase A without and
     // with the preconditioner, phase B
     hipGraphExec_t graph_a[2] = {nullptr, nullptr}, graph_b = nullptr;
@@ -128,6 +137,9 @@ struct Lobpcg {
             if (ge) (void)hipGraphExecDestroy(ge);
         for (hipEvent_t e : ev_spmm)
             if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : ev_mark)
+            if (e) (void)hipEventDestroy(e);
+        if (range_open) roctxRangePop();
         for (void *p : allocs) (void)hipFree(p);
         if (st_h) (void)hipHostFree(st_h);
         if (mu_h) (void)hipHostFree(mu_h);
@@ -162,19 +174,26 @@ struct Lobpcg {
         HIPCHK(hipHostMalloc((void **)&mu_h, sizeof(double) * HSYM_MAX_BLOCK, hipHostMallocDefault));
         memset(&rep, 0, sizeof(rep));
         for (hipEvent_t &e : ev_spmm) HIPCHK(hipEventCreate(&e));
+        if (o.timers)
+            for (hipEvent_t &e : ev_mark) HIPCHK(hipEventCreate(&e));
         t0 = std::chrono::steady_clock::now();
+        mark(7);
         // start block: X0 or a seeded Gaussian block
         if (X0) HIPCHK(hipMemcpyAsync(X, X0, sizeof(double) * nm, hipMemcpyDeviceToDevice, s));
         else gauss_fill(X, n, m, m, o.seed, 8, -1, s);
         // step 1: orthonormalise X0, Rayleigh quotient, Ritz vectors of span(X0)
         OrthWork ow{gbuf, coef, gram_scr, &st_d->flags[0], &st_h->flags[0]};
         rep.w_replaced += orthonormalize_block(n, m, X, nullptr, 0, o.seed * 1000003ULL + 5ULL, ow, s);
+        mark(0);
         spmm(X, AX);
         rep.spmm_calls++;
         GramArgs g{};
         g.a[0] = X; g.b[0] = X; g.b[1] = AX; g.na = 1; g.nb = 2; g.m = m; g.n = n;
+        mark(3);
         gram(g, gbuf, gram_scr, s);
+        mark(4);
         rayleigh_ritz(1);
+        mark(5);
         LincombArgs u{};
         u.in[0] = X; u.in[3] = AX; u.out[0] = X; u.out[2] = AX;
         u.coef = rrcoef; u.ldc = 2 * m; u.nin = 1; u.nout = 1; u.nsets = 2; u.m = m; u.n = n;
@@ -295,6 +314,7 @@ struct Lobpcg {
     void orth_part1(bool gram_done = false) {
         const double *B[2] = {X, P};
         const int kb = have_p ? 2 : 1;
+        mark(2);
         set_int(&st_d->flags[0], 0, s);
         const GramArgs g = orth_gram();
         if (!gram_done) gram(g, gbuf, gram_scr, s);
@@ -319,6 +339,7 @@ struct Lobpcg {
         auto body = [&] {
             bool gram_done = false;
             if (pre) {
+                mark(1);
                 HIPCHK(hipMemcpyAsync(mu, mu_h, sizeof(double) * m, hipMemcpyHostToDevice, s));
                 const GramArgs g = orth_gram();
                 if (precond == HSYM_PRECOND_JACOBI && jacobi_gram_fusable(g)) {
@@ -342,6 +363,7 @@ struct Lobpcg {
         if (orth_attempt >= 3) fail(HSYM_E_BREAKDOWN, "block stays rank deficient after 3 random repairs");
         int mask = flag & ((1 << m) - 1);
         rep.w_replaced += __builtin_popcount((unsigned)mask);
+        mark(7);
         gauss_fill(W, n, m, m, o.seed * 1000003ULL + (uint64_t)it * 101ULL + 7ULL + (uint64_t)orth_attempt, 10,
                    mask, s);
         orth_attempt++;
@@ -362,6 +384,7 @@ struct Lobpcg {
             LincombArgs lc2 = orth_lc;
             lc2.skip = &st_d->flags[0];
             lincomb(lc2, s);
+            mark(0);
             spmm(W, AW);
             const int nblk = have_p ? 3 : 2;
             GramArgs g{};
@@ -369,8 +392,11 @@ struct Lobpcg {
             g.b[0] = X; g.b[1] = W; g.b[2] = P;
             g.b[nblk] = AX; g.b[nblk + 1] = AW; if (nblk == 3) g.b[5] = AP;
             g.na = nblk; g.nb = 2 * nblk; g.m = m; g.n = n;
+            mark(3);
             gram(g, gbuf, gram_scr, s);
+            mark(4);
             rayleigh_ritz(nblk);
+            mark(5);
             LincombArgs u{};
             u.in[0] = X; u.in[1] = W; u.in[2] = P; u.in[3] = AX; u.in[4] = AW; u.in[5] = AP;
             u.out[0] = X; u.out[1] = P; u.out[2] = AX; u.out[3] = AP;
@@ -378,6 +404,7 @@ struct Lobpcg {
             u.theta = st_d->theta; u.res = W; u.norm_part = norm_part; u.skip = &st_d->flags[0];
             lincomb(u, s);
             colsum_final(norm_part, lincomb_norm_parts(n), m, st_d->norms, s);
+            mark(7);
             post_status();
         };
         if (use_graph()) graphed(graph_b, body);
@@ -416,8 +443,60 @@ struct Lobpcg {
         }
     }
 
+    // The launches enqueued from here on belong to phase ph (phase_ms[ph];
+    // 0 is the SpMM, timed by its own events).  A roctx range names the phase
+    // on the host timeline of a trace.
+    static constexpr const char *PHASE_NAMES[8] = {"lobpcg: spmm", "lobpcg: preconditioner", "lobpcg: cholesky-qr",
+                                                   "lobpcg: rr gram", "lobpcg: rr eigensolve", "lobpcg: update",
+                                                   "lobpcg: wait", "lobpcg: other"};
+    void mark(int ph) {
+        if (!o.timers || capturing) return;
+        if (range_open) roctxRangePop();
+        roctxRangePush(PHASE_NAMES[ph]);
+        range_open = true;
+        record_mark(ph);
+    }
+    void record_mark(int ph) {
+        if (nmark == NMARK) settle_marks(true);   // not reached in one iteration
+        HIPCHK(hipEventRecord(ev_mark[nmark], s));
+        mark_phase[nmark++] = ph;
+    }
+    // add the stretches between recorded marks to their phases (the last
+    // mark ends a stretch and opens none, unless keep_last: then it stays
+    // open as the first mark of the next window)
+    void settle_marks(bool keep_last) {
+        if (nmark == 0) return;
+        HIPCHK(hipEventSynchronize(ev_mark[nmark - 1]));
+        for (int i = 0; i + 1 < nmark; i++) {
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, ev_mark[i], ev_mark[i + 1]));
+            if (mark_phase[i] > 0) rep.phase_ms[mark_phase[i]] += ms;
+        }
+        if (keep_last) {
+            std::swap(ev_mark[0], ev_mark[nmark - 1]);
+            mark_phase[0] = mark_phase[nmark - 1];
+            nmark = 1;
+        } else {
+            nmark = 0;
+        }
+    }
+
     void sync() {
+        const bool timed = o.timers && !capturing;
+        if (timed) {
+            if (nmark > 0) record_mark(-1);   // closes the stretch in flight
+            if (range_open) roctxRangePop();
+            roctxRangePush(PHASE_NAMES[6]);
+            range_open = true;
+        }
+        const auto w0 = std::chrono::steady_clock::now();
         HIPCHK(hipStreamSynchronize(s));
+        if (timed) {
+            rep.phase_ms[6] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
+            settle_marks(false);
+            roctxRangePop();
+            range_open = false;
+        }
         if (spmm_pending) {
             float ms = 0.0f;
             HIPCHK(hipEventElapsedTime(&ms, ev_spmm[0], ev_spmm[1]));

@@ -20,7 +20,7 @@
 // A run's sum is added to its LDS accumulator row when the run ends, with
 // fp64 LDS atomics (runs cut by a segment boundary have two owners); no
 // per-entry atomics remain, and the X rows are read as whole rows by the
-// lanes of a group (16 bytes per lane), which keeps the LDS banks free of
+// lanes of a group (two elements per lane), which keeps the LDS banks free of
 // conflicts.  While a piece runs, the next piece's entries and X chunk are
 // already in flight into registers.
 // Output: Y is cleared first; every panel adds its own rows and its external
@@ -41,7 +41,7 @@ constexpr int SPMM_XE = 4;   // X chunk elements per thread (C * M <= 4096)
 template <int M, typename A>
 struct Lay {
     static constexpr int SA = (int)sizeof(A);
-    static constexpr int MW = M * SA >= 16 ? 16 / SA : M;   // elements per lane
+    static constexpr int MW = spmm_lane_elems(M);            // elements per lane
     static constexpr int L = M / MW;                         // lanes per row
     static constexpr int GK = SPMM_NT / L;                   // lane groups
 };
@@ -50,9 +50,7 @@ struct SpmmArgs {
     const int64_t *ptp;
     const int32_t *porder;
     const TileDesc *tiles;
-    const void *idx;
-    const uint16_t *perm;
-    const void *vals;
+    const unsigned char *blob;
     const void *diag;
     const void *X;
     int64_t ldx;
@@ -64,10 +62,19 @@ struct SpmmArgs {
     int m;
 };
 
-// MW consecutive elements of an LDS row
+// MW consecutive elements of an LDS row (32, 16, 8 or 4 bytes)
 template <int MW, typename A>
 __device__ __forceinline__ void lds_get(const A *p, A *o) {
-    if constexpr (MW * sizeof(A) == 16 && sizeof(A) == 8) {
+    if constexpr (MW * sizeof(A) == 32 && sizeof(A) == 8) {
+        const double2 v = *reinterpret_cast<const double2 *>(p);
+        const double2 w = *reinterpret_cast<const double2 *>(p + 2);
+        o[0] = v.x; o[1] = v.y; o[2] = w.x; o[3] = w.y;
+    } else if constexpr (MW * sizeof(A) == 32) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        const float4 w = *reinterpret_cast<const float4 *>(p + 4);
+        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+        o[4] = w.x; o[5] = w.y; o[6] = w.z; o[7] = w.w;
+    } else if constexpr (MW * sizeof(A) == 16 && sizeof(A) == 8) {
         const double2 v = *reinterpret_cast<const double2 *>(p);
         o[0] = v.x; o[1] = v.y;
     } else if constexpr (MW * sizeof(A) == 16) {
@@ -96,27 +103,18 @@ __device__ __forceinline__ void y_add(YT *p, double v) {
     unsafeAtomicAdd(p, (YT)v);
 }
 
-// Load piece t into registers: 16-byte units of its codes, perm and values
-// (thread tid takes units tid, tid + 1024, ...), and the X chunk of an
-// external tile's first piece (element i = tid + k * 1024 of the C x M chunk).
-template <int M, typename T, typename XT, typename IT>
-__device__ __forceinline__ void spmm_fetch(const SpmmArgs &a, const TileDesc &td, uint4 &s0, uint4 &s1, uint4 &s2,
-                                           uint4 &s3, XT &x0, XT &x1, XT &x2, XT &x3) {
+// Load a piece into registers: 16-byte units of its bytes (thread tid takes
+// units tid, tid + 1024, ...), and the X chunk of an external tile's first
+// piece (element i = tid + k * 1024 of the C x M chunk).
+template <int M, typename XT>
+__device__ __forceinline__ void spmm_fetch(const SpmmArgs &a, const TileDesc &td, int nunits, uint4 &s0, uint4 &s1,
+                                           uint4 &s2, uint4 &s3, XT &x0, XT &x1, XT &x2, XT &x3) {
     const int tid = threadIdx.x;
-    const int E = a.g.G * td.len;
-    const int nc = (E * (int)sizeof(IT) + 15) >> 4, np = (E * 2 + 15) >> 4, nv = (E * (int)sizeof(T) + 15) >> 4;
-    const uint4 *gc = reinterpret_cast<const uint4 *>(reinterpret_cast<const IT *>(a.idx) + td.base);
-    const uint4 *gp = reinterpret_cast<const uint4 *>(a.perm + td.base);
-    const uint4 *gv = reinterpret_cast<const uint4 *>(reinterpret_cast<const T *>(a.vals) + td.base);
-    auto get = [&](int u, uint4 &d) {
-        if (u < nc) d = gc[u];
-        else if (u < nc + np) d = gp[u - nc];
-        else if (u < nc + np + nv) d = gv[u - nc - np];
-    };
-    get(tid, s0);
-    get(tid + SPMM_NT, s1);
-    get(tid + 2 * SPMM_NT, s2);
-    get(tid + 3 * SPMM_NT, s3);
+    const uint4 *g = reinterpret_cast<const uint4 *>(a.blob + td.base);
+    if (tid < nunits) s0 = g[tid];
+    if (tid + SPMM_NT < nunits) s1 = g[tid + SPMM_NT];
+    if (tid + 2 * SPMM_NT < nunits) s2 = g[tid + 2 * SPMM_NT];
+    if (tid + 3 * SPMM_NT < nunits) s3 = g[tid + 3 * SPMM_NT];
     if (td.ext && (td.flags & TILE_FIRST)) {
         const XT *X = reinterpret_cast<const XT *>(a.X);
         const int C = a.g.C, m = a.m;
@@ -137,7 +135,7 @@ template <int M, typename T, typename A, typename XT, typename YT, typename IT>
 __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, unsigned char *smem) {
     using Ly = Lay<M, A>;
     constexpr int MW = Ly::MW, L = Ly::L, GK = Ly::GK, SA = Ly::SA;
-    constexpr int IB = (int)sizeof(IT), SV = (int)sizeof(T), U = 4;
+    constexpr int IB = (int)sizeof(IT), SV = (int)sizeof(T), U = 2;
     const int R = a.g.R, C = a.g.C, G = a.g.G, cb = a.g.cb, maxe = a.g.maxe, m = a.m;
     const uint32_t cm = (uint32_t)C - 1u;
     const int tid = threadIdx.x, grp = tid / L, q = tid - grp * L;
@@ -146,12 +144,16 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
     double *ts = acc + (size_t)R * M;
     A *xp = reinterpret_cast<A *>(ts + (size_t)C * M);
     A *xs = xp + (size_t)R * M;
-    const size_t off_c = (size_t)(R + C) * M * (8 + SA);
-    const size_t off_p = off_c + (((size_t)maxe * IB + 15) & ~(size_t)15);
-    const size_t off_v = off_p + (((size_t)maxe * 2 + 15) & ~(size_t)15);
-    const IT *scode = reinterpret_cast<const IT *>(smem + off_c);
-    const uint16_t *sperm = reinterpret_cast<const uint16_t *>(smem + off_p);
-    const T *sval = reinterpret_cast<const T *>(smem + off_v);
+    // the staged piece: its bytes as stored (codes, perm, values; the offsets
+    // of the last two depend on the piece's size)
+    unsigned char *stg = smem + (size_t)(R + C) * M * (8 + SA);
+    (void)maxe;
+    auto parts = [&](int len, int &op, int &ov, int &nunits) {
+        const int E = G * len;
+        op = (E * IB + 15) & ~15;
+        ov = op + ((E * 2 + 15) & ~15);
+        nunits = (ov + ((E * SV + 15) & ~15)) >> 4;
+    };
 
     const XT *X = reinterpret_cast<const XT *>(a.X);
     YT *Y = reinterpret_cast<YT *>(a.Y);
@@ -192,7 +194,9 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
     TileDesc tdc{}, tdn{};
     if (t0 < t1) {
         tdc = tile_at(t0);
-        spmm_fetch<M, T, XT, IT>(a, tdc, su0, su1, su2, su3, xr0, xr1, xr2, xr3);
+        int op0, ov0, nu0;
+        parts(tdc.len, op0, ov0, nu0);
+        spmm_fetch<M, XT>(a, tdc, nu0, su0, su1, su2, su3, xr0, xr1, xr2, xr3);
         if (t0 + 1 < t1) tdn = tile_at(t0 + 1);
     }
 
@@ -221,20 +225,14 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
         }
         const int len = td.len;
         const int64_t col0 = (int64_t)td.chunk * C;
+        int op, ov, nunits;
+        parts(len, op, ov, nunits);
         {
-            const int E = G * len;
-            const int nc = (E * IB + 15) >> 4, np = (E * 2 + 15) >> 4, nv = (E * SV + 15) >> 4;
-            auto put = [&](int u, const uint4 &v) {
-                size_t dst = 0;
-                if (u < nc) dst = off_c + (size_t)u * 16;
-                else if (u < nc + np) dst = off_p + (size_t)(u - nc) * 16;
-                else dst = off_v + (size_t)(u - nc - np) * 16;
-                if (u < nc + np + nv) *reinterpret_cast<uint4 *>(smem + dst) = v;
-            };
-            put(tid, su0);
-            put(tid + SPMM_NT, su1);
-            put(tid + 2 * SPMM_NT, su2);
-            put(tid + 3 * SPMM_NT, su3);
+            uint4 *sdst = reinterpret_cast<uint4 *>(stg);
+            if (tid < nunits) sdst[tid] = su0;
+            if (tid + SPMM_NT < nunits) sdst[tid + SPMM_NT] = su1;
+            if (tid + 2 * SPMM_NT < nunits) sdst[tid + 2 * SPMM_NT] = su2;
+            if (tid + 3 * SPMM_NT < nunits) sdst[tid + 3 * SPMM_NT] = su3;
             if (td.ext && (td.flags & TILE_FIRST)) {
                 if (tid < C * M) xs[tid] = (A)xr0;
                 if (tid + SPMM_NT < C * M) xs[tid + SPMM_NT] = (A)xr1;
@@ -243,12 +241,17 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
             }
         }
         if (t + 1 < t1) {
-            spmm_fetch<M, T, XT, IT>(a, tdn, su0, su1, su2, su3, xr0, xr1, xr2, xr3);
+            int opn, ovn, nun;
+            parts(tdn.len, opn, ovn, nun);
+            spmm_fetch<M, XT>(a, tdn, nun, su0, su1, su2, su3, xr0, xr1, xr2, xr3);
             tdc = tdn;
             if (t + 2 < t1) tdn = tile_at(t + 2);
         }
         __syncthreads();
 
+        const IT *scode = reinterpret_cast<const IT *>(stg);
+        const uint16_t *sperm = reinterpret_cast<const uint16_t *>(stg + op);
+        const T *sval = reinterpret_cast<const T *>(stg + ov);
         // row pass: U X
         {
             const A *xsrc = td.ext ? xs : xp + (size_t)(col0 - row0) * M;
@@ -352,7 +355,7 @@ __global__ __launch_bounds__(SPMM_NT) void k_spmm_panel_b(const SpmmJob *__restr
     const SpmmJob J = jobs[blockIdx.y];
     if ((int64_t)blockIdx.x >= J.npanels) return;
     SpmmArgs a;
-    a.ptp = J.ptp; a.porder = J.porder; a.tiles = J.tiles; a.idx = J.idx; a.perm = J.perm; a.vals = J.vals;
+    a.ptp = J.ptp; a.porder = J.porder; a.tiles = J.tiles; a.blob = J.blob;
     a.diag = J.diag; a.X = J.X; a.ldx = J.ldx; a.Y = J.Y; a.ldy = J.ldy; a.n = J.n; a.npanels = J.npanels;
     a.g = J.g; a.m = J.m;
     // the code width is a property of each job's handle (uniform per workgroup)
@@ -393,9 +396,9 @@ static void check_fit(int storage, int m, const Geom &g) {
         fail(HSYM_E_UNSUPPORTED, "block width too large for this handle's panel geometry");
     if ((size_t)g.C * M > (size_t)SPMM_XE * SPMM_NT)
         fail(HSYM_E_UNSUPPORTED, "chunk too wide for this block width");
-    const int eb = g.idx_bytes + 2 + (storage == HSYM_FP64 ? 8 : 4);
-    if (((int64_t)g.maxe * eb + 47) / 16 > (int64_t)SPMM_KU * SPMM_NT)
-        fail(HSYM_E_UNSUPPORTED, "pieces too large for the staging registers");
+    const int64_t e = g.maxe, sv = storage == HSYM_FP64 ? 8 : 4;
+    const int64_t bytes = ((e * g.idx_bytes + 15) & ~15) + ((e * 2 + 15) & ~15) + ((e * sv + 15) & ~15);
+    if (bytes / 16 > (int64_t)SPMM_KU * SPMM_NT) fail(HSYM_E_UNSUPPORTED, "pieces too large for the staging registers");
 }
 
 template <int M, typename T, typename A, typename XT, typename YT, typename IT>
@@ -408,8 +411,7 @@ static void launch_typed(hsym_matrix *H, int m, const void *X, int64_t ldx, void
         HIPCHK(hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     });
     SpmmArgs a;
-    a.ptp = dt.panel_tile_ptr; a.porder = dt.panel_order; a.tiles = dt.tiles; a.idx = dt.idx; a.perm = dt.perm;
-    a.vals = dt.vals;
+    a.ptp = dt.panel_tile_ptr; a.porder = dt.panel_order; a.tiles = dt.tiles; a.blob = dt.blob;
     a.diag = H->storage == HSYM_FP64 ? (const void *)H->diag64 : (const void *)H->diag32;
     a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.n = H->n; a.npanels = dt.npanels; a.g = dt.g; a.m = m;
     zero_rows<YT>((YT *)Y, H->n, m, ldy, s);
@@ -437,8 +439,7 @@ static void launch_m(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y,
 SpmmJob spmm_job(hsym_matrix *H, int m, const double *X, double *Y) {
     const DeviceTiles &dt = H->tiles;
     SpmmJob J{};
-    J.ptp = dt.panel_tile_ptr; J.porder = dt.panel_order; J.tiles = dt.tiles; J.idx = dt.idx; J.perm = dt.perm;
-    J.vals = dt.vals;
+    J.ptp = dt.panel_tile_ptr; J.porder = dt.panel_order; J.tiles = dt.tiles; J.blob = dt.blob;
     J.diag = H->storage == HSYM_FP64 ? (const void *)H->diag64 : (const void *)H->diag32;
     J.X = X; J.ldx = m; J.Y = Y; J.ldy = m;
     J.n = H->n; J.npanels = dt.npanels; J.g = dt.g; J.m = m;

@@ -115,10 +115,8 @@ static void replay(const hsym_matrix *H, const std::vector<double> &X, int m, st
     const Geom &g = dt.g;
     const int64_t n = H->n;
     const int M = round_m(m);
-    const IT *idx = (const IT *)dt.idx;
-    const T *vals = (const T *)dt.vals;
     const T *diag = H->storage == HSYM_FP64 ? (const T *)(const void *)H->diag64 : (const T *)(const void *)H->diag32;
-    const int64_t total = dt.nentries + 16;   // the streams carry 16 positions of slack
+    const int64_t total = dt.nbytes;
     Y.assign((size_t)(n * m), 0.0);
     std::vector<char> seen((size_t)dt.npanels, 0);
     for (int64_t b = 0; b < dt.npanels; b++) {
@@ -137,12 +135,18 @@ static void replay(const hsym_matrix *H, const std::vector<double> &X, int m, st
             const TileDesc td = dt.tiles[t];
             const int64_t E = (int64_t)g.G * td.len;
             const int64_t col0 = (int64_t)td.chunk * g.C;
-            REQUIRE(td.base % 8 == 0, "piece base %ld not a multiple of 8", (long)td.base);
+            const int64_t op = (E * (int64_t)sizeof(IT) + 15) & ~(int64_t)15;
+            const int64_t ov = op + ((E * 2 + 15) & ~(int64_t)15);
+            const int64_t bytes = ov + ((E * (int64_t)sizeof(T) + 15) & ~(int64_t)15);
+            REQUIRE(td.base % 16 == 0, "piece base %ld not a multiple of 16", (long)td.base);
             REQUIRE(td.len >= 1 && E <= g.maxe, "piece of %ld positions exceeds %d", (long)E, g.maxe);
-            REQUIRE(td.base + E + 8 <= total, "piece at %ld overruns the streams", (long)td.base);
+            REQUIRE(td.base + bytes <= total, "piece at %ld overruns the stream", (long)td.base);
             REQUIRE(td.ext == (col0 >= row0 + g.R ? 1 : 0), "external flag of chunk %d in panel %ld", td.chunk, (long)p);
             REQUIRE(col0 >= row0 && col0 < n, "chunk %d outside the panel's column range", td.chunk);
-            if (!(td.base % 8 == 0 && E <= g.maxe && td.base + E + 8 <= total)) return;
+            if (!(td.base % 16 == 0 && E <= g.maxe && td.base + bytes <= total)) return;
+            const IT *idx = (const IT *)(dt.blob + td.base);
+            const uint16_t *pm = (const uint16_t *)(dt.blob + td.base + op);
+            const T *vals = (const T *)(dt.blob + td.base + ov);
             if (td.flags & TILE_FIRST) {
                 REQUIRE(!open_ext, "first piece inside an open tile");
                 if (td.ext) {
@@ -160,9 +164,9 @@ static void replay(const hsym_matrix *H, const std::vector<double> &X, int m, st
             std::vector<T> sv((size_t)E);
             std::vector<int> hits((size_t)E, 0);
             for (int64_t e = 0; e < E; e++) {
-                sc[(size_t)e] = (uint32_t)idx[td.base + e];
-                sp[(size_t)e] = dt.perm[td.base + e];
-                sv[(size_t)e] = vals[td.base + e];
+                sc[(size_t)e] = (uint32_t)idx[e];
+                sp[(size_t)e] = pm[e];
+                sv[(size_t)e] = vals[e];
                 const int r = (int)(sc[(size_t)e] >> g.cb), c = (int)(sc[(size_t)e] & (g.C - 1));
                 REQUIRE(r < nrow && col0 + c < n && col0 + c > row0 + r, "code %u outside the tile", sc[(size_t)e]);
                 REQUIRE(sp[(size_t)e] < E, "perm %d outside the piece", sp[(size_t)e]);

@@ -6,6 +6,9 @@
 #include <cstdlib>
 #include <cstring>
 
+#define __host__
+#define __device__
+
 typedef int hipError_t;
 typedef void *hipStream_t;
 enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorMemoryAllocation = 2 };
