@@ -25,6 +25,22 @@ int hsym_kernel_gram(int64_t n, int m, int na, const double *const *A, int nb, c
                      double *G, void *stream);
 
 /*
+ * hsym_kernel_gram without allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and result (bitwise) as
+ * hsym_kernel_gram, but the per-slice partials live in a static device array
+ * of 36 MiB per GPU (room for K1 = na*m <= 48, K2 = nb*m <= 96 and up to 1024
+ * row slices, i.e. every accepted shape), held until the process ends.  The
+ * call only enqueues work on `stream` and returns: G is ready when the stream
+ * is.  Every call on a GPU shares that GPU's array, so calls that overlap on
+ * one GPU (other streams, other threads) race: order them on one stream.
+ * Makes no hipMalloc/hipFree call.  Errors: HSYM_E_INVALID_ARG (sizes, NULL,
+ * partials beyond the array), HSYM_E_DEVICE (symbol lookup failed).
+ */
+int hsym_kernel_gram_noalloc(int64_t n, int m, int na, const double *const *A, int nb, const double *const *B,
+                             double *G, void *stream);
+
+/*
  * Linear combination (Section 4.4, "linear combination", eq. 7):
  * Out_q = sum_i In_i C[i*m:(i+1)*m, q*m:(q+1)*m] for nin (1..3) inputs and
  * nout (1..2) outputs; C is device (nin*m) x (nout*m) with row stride ldc.

@@ -146,6 +146,7 @@ _SIGS = {
     "hsym_last_error": [],
     # step-level entry points (include/hsym_kernels.h)
     "hsym_kernel_gram": [_i64, _int, _int, _vp, _int, _vp, _vp, _vp],
+    "hsym_kernel_gram_noalloc": [_i64, _int, _int, _vp, _int, _vp, _vp, _vp],
     "hsym_kernel_lincomb": [_i64, _int, _int, _vp, _int, _vp, _vp, _int, _vp],
     "hsym_kernel_rayleigh_ritz": [_int, _int, _vp, _vp, _vp, _vp, ctypes.POINTER(_int), _vp],
     "hsym_kernel_precond": [_vp, _int, _int, _vp, _vp, _dbl, _vp],
@@ -390,6 +391,14 @@ def hsym_kernel_gram(A, B, G, stream=None):
     n, m = A[0].shape
     return _check(lib().hsym_kernel_gram(n, m, len(A), _ptr_array(A), len(B), _ptr_array(B), _dptr(G),
                                          _stream(stream)))
+
+
+def hsym_kernel_gram_noalloc(A, B, G, stream=None):
+    """hsym_kernel_gram with its partials in the library's static device
+    scratch (no allocation; asynchronous on `stream`)."""
+    n, m = A[0].shape
+    return _check(lib().hsym_kernel_gram_noalloc(n, m, len(A), _ptr_array(A), len(B), _ptr_array(B), _dptr(G),
+                                                 _stream(stream)))
 
 
 def hsym_kernel_lincomb(In, Out, C, stream=None):
