@@ -109,17 +109,21 @@ Geom geometry_for(int storage, int m, int64_t n, int r64, int lc) {
             fail(HSYM_E_INVALID_ARG, "panel geometry does not fit the LDS at the geometry block width");
         return g;
     }
-    // Tallest panels first (fewer panels share each chunk's transposed sums),
-    // at least one panel per CU (256) when n allows; chunks of 128 or 64
-    // columns (64 or more keeps the per-piece barriers rare); 16-bit codes at
-    // block widths of 4 and more; at least 2048 entries per piece.
-    const int64_t rmax = std::max<int64_t>(64, std::min<int64_t>(4096, (n / 256) / 64 * 64));
-    for (int64_t R = rmax; R >= 64; R -= 64) {
+    // Chunks of 128 columns first, then the tallest panels whose pieces still
+    // hold about 4,000 entries (measured on CI-shaped matrices at m = 1, 8, 16
+    // in both storages: 128-column chunks beat 64 by 8-25%, and full pieces
+    // beat taller panels with smaller pieces), at least one panel per CU
+    // (256) when n allows, 16-bit codes at block widths of 4 and more.  Then
+    // the same with 64-column chunks and at least 2,048 entries per piece.
+    const int64_t rmax = std::max<int64_t>(64, std::min<int64_t>(2048, (n / 256) / 64 * 64));
+    for (int pass = 0; pass < 2; pass++) {
         for (int C : {128, 64}) {
-            if (C > R || R % C) continue;
-            if (M >= 4 && R * C > 65536) continue;
-            if ((int64_t)C * M > 4096) continue;
-            if (fill((int)R, C) && g.maxe >= 2048) return g;
+            for (int64_t R = rmax; R >= C; R -= 64) {
+                if (R % C) continue;
+                if (M >= 4 && R * C > 65536) continue;
+                if ((int64_t)C * M > 4096) continue;
+                if (fill((int)R, C) && g.maxe >= (pass == 0 ? 4000 : 2048)) return g;
+            }
         }
     }
     if (!fill(64, 64) || g.maxe < 256) fail(HSYM_E_UNSUPPORTED, "no panel geometry fits the LDS at this block width");

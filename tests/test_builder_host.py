@@ -46,7 +46,7 @@ CASES = [
     ("gen", 2000, 40, 1, 1, 16, 0, 0, 0),
     ("gen", 20000, 60, 7, 0, 16, 333, 0, 0),       # streaming create in uneven slabs
     ("gen", 20000, 60, 7, 1, 8, 1000, 0, 0),
-    ("gen", 30000, 200, 3, 0, 16, 0, 7, 6),        # R = 448, C = 64: the C2 geometry
+    ("gen", 30000, 200, 3, 0, 16, 0, 7, 6),        # explicit R = 448, C = 64
     ("gen", 5000, 40, 9, 0, 1, 0, 0, 0),
     ("diag", 1, 0, 3, 0, 1, 0, 0, 0),
     ("diag", 300, 0, 1, 0, 16, 0, 0, 0),

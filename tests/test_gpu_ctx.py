@@ -145,12 +145,11 @@ def test_batched_rounds_repair_deficient_blocks():
     """Small problems whose basis nearly fills the space (n close to 3m) lose
     rank in W during batched rounds: the round's phase B then leaves such a
     problem's basis untouched, and the problem is repaired alone and its
-    phase B rerun.  Every problem still reaches LAPACK's eigenvalues.
-    (n = 30 is left out: with 24 basis columns in 30 dimensions one run ended
-    not converged after 400 iterations, reported as such; the cause is not yet
-    found, and the oracle converges on that matrix.)"""
+    phase B rerun.  Every problem still reaches LAPACK's eigenvalues, n = 30
+    included (24 basis columns in 30 dimensions: the case that stalled while
+    the Rayleigh-Ritz step assumed an orthonormal basis)."""
     import scipy.sparse as sp
-    cases = [(26, 61), (27, 62), (40, 64)]
+    cases = [(26, 61), (27, 62), (30, 63), (40, 64)]
     mats, lams = [], []
     for n, seed in cases:
         A = hsymgen.generate(n, 12, seed)
