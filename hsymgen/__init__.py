@@ -110,8 +110,9 @@ class Generator:
         self.ntiles = lib.hsg_ntiles(self._h)
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            _load().hsg_destroy(self._h)
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "_h", None) and _load is not None and _lib is not None:
+            _lib.hsg_destroy(self._h)
             self._h = None
 
     def blocks(self):

@@ -610,41 +610,61 @@ __global__ __launch_bounds__(256) void k_precond_jacobi_b(const JacobiJob *__res
     jb.W[e] = jb.W[e] / guard_den(jb.diag[r] - jb.mu[j], jb.delta);
 }
 
-// One workgroup per 64-row chunk: W_b = Q diag(1/g(lambda - mu_j)) Q^T R_b.
+// One wave per 64-row chunk: W_b = Q diag(1/g(lambda - mu_j)) Q^T R_b.
 __global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W, const double *__restrict__ Q,
                                                          const double *__restrict__ lam,
                                                          const double *__restrict__ mu, double delta, int64_t n,
                                                          int m) {
-    __shared__ double qs[64][65];
-    __shared__ double rs[64][17];
-    __shared__ double ts[64][17];
-    const int64_t b = blockIdx.x;
+    // One wave per 64-row block, both products on the matrix cores
+    // (v_mfma_f64_16x16x4f64; lane l: li = l & 15, lk = l >> 4; A operand
+    // A[li][lk], B operand B[lk][li], accumulator v = row lk + 4v, column li):
+    //   T = Q^T R as four 16-row tiles over 16 k-steps, scaled row-wise by
+    //   1/g(lambda_i - mu_j); then W = Q T, whose B operand for k-step s is
+    //   the accumulator register s % 4 of tile s / 4 in the same lane.
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t r0 = b * 64;
+    if (r0 >= n) return;   // whole wave
     const int rows = (int)((n - r0) < 64 ? (n - r0) : 64);
     const double *Qb = Q + b * 64 * 64;
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) qs[e >> 6][e & 63] = Qb[e];
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-        int i = e >> 4, j = e & 15;
-        rs[i][j] = (i < rows && j < m) ? W[(r0 + i) * m + j] : 0.0;
+    const bool col = li < m;
+    // R rows 4s + lk of column li, s = 0..15
+    double rv[16];
+#pragma unroll
+    for (int s = 0; s < 16; s++) {
+        const int k = 4 * s + lk;
+        rv[s] = (col && k < rows) ? W[(r0 + k) * m + li] : 0.0;
     }
-    __syncthreads();
-    // T = Q^T R, scaled row-wise by 1/g(lambda_i - mu_j)
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-        int i = e >> 4, j = e & 15;
-        double s = 0.0;
-        if (j < m) {
-            for (int k = 0; k < 64; k++) s = fma(qs[k][i], rs[k][j], s);
-            s = s / guard_den(lam[b * 64 + i] - mu[j], delta);
+    double4_t t[4];
+#pragma unroll
+    for (int tt = 0; tt < 4; tt++) {
+        t[tt] = (double4_t){0.0, 0.0, 0.0, 0.0};
+        double qa[16];
+#pragma unroll
+        for (int s = 0; s < 16; s++) qa[s] = Qb[(4 * s + lk) * 64 + 16 * tt + li];   // Q^T[16tt + li][4s + lk]
+#pragma unroll
+        for (int s = 0; s < 16; s++) t[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[s], rv[s], t[tt], 0, 0, 0);
+    }
+    const double muj = col ? mu[li] : 0.0;
+#pragma unroll
+    for (int tt = 0; tt < 4; tt++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int i = 16 * tt + lk + 4 * v;
+            t[tt][v] = col ? t[tt][v] / guard_den(lam[b * 64 + i] - muj, delta) : 0.0;
         }
-        ts[i][j] = s;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-        int i = e >> 4, j = e & 15;
-        if (i < rows && j < m) {
-            double s = 0.0;
-            for (int k = 0; k < 64; k++) s = fma(qs[i][k], ts[k][j], s);
-            W[(r0 + i) * m + j] = s;
+#pragma unroll
+    for (int tt = 0; tt < 4; tt++) {
+        double qa[16];
+#pragma unroll
+        for (int s = 0; s < 16; s++) qa[s] = Qb[(16 * tt + li) * 64 + 4 * s + lk];   // Q[16tt + li][4s + lk]
+        double4_t w = (double4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 16; s++) w = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[s], t[s >> 2][s & 3], w, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int i = 16 * tt + lk + 4 * v;
+            if (col && i < rows) W[(r0 + i) * m + li] = w[v];
         }
     }
 }
@@ -880,7 +900,7 @@ void precond_apply(hsym_matrix *H, int kind, double *W, const double *mu, double
             default: fail(HSYM_E_INVALID_ARG, "block width must be 1..16");
         }
     } else if (kind == HSYM_PRECOND_BLOCK64) {
-        hipLaunchKernelGGL(k_precond_block64, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, W, H->pre_q,
+        hipLaunchKernelGGL(k_precond_block64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, H->pre_q,
                            H->pre_lam, mu, delta, n, m);
     }
     HIPCHK(hipGetLastError());
