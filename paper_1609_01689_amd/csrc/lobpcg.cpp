@@ -360,12 +360,22 @@ struct Lobpcg {
     // the first Cholesky-QR stage, ending with a new flag copy
     void repair_once() {
         const int flag = st_h->flags[0];
-        if (orth_attempt >= 3) fail(HSYM_E_BREAKDOWN, "block stays rank deficient after 3 random repairs");
+        if (orth_attempt >= 3) {
+            // W stays dependent on [X P] after three random repairs (a basis
+            // that nearly fills the space): restart the recurrence without P
+            // for this iteration, which leaves W the room P took, as the
+            // oracle drops P at a small pivot; without P the failure stands
+            if (!have_p) fail(HSYM_E_BREAKDOWN, "block stays rank deficient after 3 random repairs");
+            have_p = false;
+            rep.p_dropped++;
+            orth_attempt = 0;
+        }
         int mask = flag & ((1 << m) - 1);
         rep.w_replaced += __builtin_popcount((unsigned)mask);
         mark(7);
-        gauss_fill(W, n, m, m, o.seed * 1000003ULL + (uint64_t)it * 101ULL + 7ULL + (uint64_t)orth_attempt, 10,
-                   mask, s);
+        gauss_fill(W, n, m, m,
+                   o.seed * 1000003ULL + (uint64_t)it * 101ULL + 7ULL + (uint64_t)orth_attempt + (have_p ? 0 : 50),
+                   10, mask, s);
         orth_attempt++;
         orth_part1();
     }

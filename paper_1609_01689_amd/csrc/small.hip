@@ -6,6 +6,8 @@
 //     by Householder tridiagonalisation, Sturm-count bisection and inverse
 //     iteration (Golub and Van Loan, Matrix Computations, Sections 8.3.1,
 //     8.4.1 and 8.2.2).
+#include <type_traits>
+
 #include "dense.h"
 #include "wave.h"
 
@@ -410,6 +412,69 @@ __device__ void congruence(const double (*Li)[KMAX + 1], const double (*S)[KMAX 
     __syncthreads();
 }
 
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// Householder tridiagonalisation of the symmetric k x k A (LDS, k <= KMAX) by
+// the first wave alone, with no barrier: lane r holds row r in registers, the
+// vectors of each step are read across lanes (readlane), and the rank-2
+// update keeps the matrix exactly symmetric (both products rounded, then
+// added in either order).  Leaves what the barrier version left: A with its
+// diagonal and first subdiagonal (T), the reflector of step j in column j
+// below the subdiagonal (first entry x0 - alpha), beta[j] = 2 / v.v and
+// e[j] = alpha (0 where nothing was annihilated).
+__device__ void tridiag_wave(double (*A)[KMAX + 1], int k, double *beta, double *e) {
+    const int lane = threadIdx.x & 63;
+    const int r = lane < KMAX ? lane : KMAX - 1;
+    double a[KMAX];
+#pragma unroll
+    for (int c = 0; c < KMAX; c++) a[c] = (lane < k && c < k) ? A[r][c] : 0.0;
+    static_for<0, KMAX - 2>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (j + 2 < k) {
+            const bool below = lane > j && lane < k;
+            const double x = below ? a[j] : 0.0;
+            const double nrm2 = wave_sum(x * x);
+            const double x0 = read_lane(a[j], j + 1);
+            double alpha = 0.0, bt = 0.0;
+            if (nrm2 > 0.0) {
+                const double nrm = sqrt(nrm2);
+                alpha = x0 >= 0 ? -nrm : nrm;
+                bt = 1.0 / (nrm2 - alpha * x0);   // 2 / v.v with v.v = 2 (nrm2 - alpha x0)
+            }
+            if (lane == 0) { beta[j] = bt; e[j] = alpha; }
+            if (bt != 0.0) {
+                const double v = below ? (lane == j + 1 ? x - alpha : x) : 0.0;
+                // p = beta A22 v
+                double p = 0.0;
+#pragma unroll
+                for (int c = j + 1; c < KMAX; c++) p = fma(a[c], read_lane(v, c), p);
+                p = lane < k ? bt * p : 0.0;
+                const double vp = wave_sum(v * p);
+                const double w = fma(-0.5 * bt * vp, v, p);
+                if (below) {
+#pragma unroll
+                    for (int c = j + 1; c < KMAX; c++) {
+                        const double vc = read_lane(v, c), wc = read_lane(w, c);
+                        a[c] = a[c] - __dadd_rn(__dmul_rn(v, wc), __dmul_rn(w, vc));
+                    }
+                }
+                if (lane == j + 1) a[j] = v;   // the reflector's first entry, x0 - alpha
+            }
+        }
+    });
+    if (lane < k) {
+#pragma unroll
+        for (int c = 0; c < KMAX; c++)
+            if (c < k) A[r][c] = a[c];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
     __shared__ double A[KMAX][KMAX + 1];      // lower part: reflector vectors
     __shared__ double beta[KMAX], d[KMAX], e[KMAX], ds[KMAX + 4], e2s[KMAX + 4], lam[KMAX];
@@ -514,65 +579,9 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
     }
     // the projected matrix Li (S^T A S) Li^T on the orthonormal basis S Li^T
     congruence(Li, A, k, Lf, A);
-    // 1. tridiagonalisation; the arithmetic deciding each reflector is
-    // repeated identically in every wave, so no broadcast is needed
-    {
-        const int qi = tid >> 2, qp = tid & 3;
-        for (int j = 0; j + 2 < k; j++) {
-            const int len = k - j - 1;   // x = A[j+1 .. k-1][j]
-            const double xl = lane < len ? A[j + 1 + lane][j] : 0.0;
-            const double nrm2 = wave_sum(xl * xl);
-            const double x0 = A[j + 1][j];
-            double alpha = 0.0, bt = 0.0;
-            if (nrm2 > 0.0) {
-                const double nrm = sqrt(nrm2);
-                alpha = x0 >= 0 ? -nrm : nrm;
-                bt = 1.0 / (nrm2 - alpha * x0);    // 2 / v.v with v.v = 2 (nrm2 - alpha x0)
-            }
-            if (tid == 0) { beta[j] = bt; e[j] = alpha; }
-            if (bt == 0.0) continue;                // x = 0: nothing to annihilate
-            // v = x - alpha e_1 (read from column j, first entry corrected on the fly)
-            // p = beta A22 v, a quad of lanes per row
-            // rows and columns past len are clamped to len-1 so that every
-            // load is in bounds and can be issued ahead; their terms are masked
-            const int rc = qi < len ? qi : len - 1;
-            double vl[12], al[12];
-#pragma unroll
-            for (int t = 0; t < 12; t++) {
-                const int l = qp + 4 * t, lc = l < len ? l : len - 1;
-                vl[t] = l < len ? A[j + 1 + lc][j] - (l == 0 ? alpha : 0.0) : 0.0;
-                al[t] = A[j + 1 + rc][j + 1 + lc];
-            }
-            double pi = 0.0;
-#pragma unroll
-            for (int t = 0; t < 12; t++) pi = fma(al[t], vl[t], pi);
-            pi = quad_sum(pi);
-            if (qp == 0 && qi < len) pv[qi] = bt * pi;
-            __syncthreads();
-            // w = p - (beta/2)(v.p) v;  A22 -= v w^T + w v^T (exactly symmetric)
-            const double vlane = lane < len ? A[j + 1 + lane][j] - (lane == 0 ? alpha : 0.0) : 0.0;
-            const double vp = wave_sum(lane < len ? vlane * pv[lane] : 0.0);
-            const double half = 0.5 * bt * vp;
-            const double vi = A[j + 1 + rc][j] - (rc == 0 ? alpha : 0.0);
-            const double wi = fma(-half, vi, pv[rc]);
-            double wl[12];
-#pragma unroll
-            for (int t = 0; t < 12; t++) {
-                const int l = qp + 4 * t, lc = l < len ? l : len - 1;
-                wl[t] = fma(-half, vl[t], pv[lc]);
-            }
-            if (qi < len) {
-#pragma unroll
-                for (int t = 0; t < 12; t++) {
-                    const int l = qp + 4 * t;
-                    const double upd = __dadd_rn(__dmul_rn(vi, wl[t]), __dmul_rn(wi, vl[t]));
-                    if (l < len) A[j + 1 + qi][j + 1 + l] = al[t] - upd;
-                }
-            }
-            __syncthreads();
-            if (tid == 0) A[j + 1][j] = x0 - alpha;  // store v (column j is not read again until step 4)
-        }
-    }
+    // 1. tridiagonalisation, by the first wave
+    __syncthreads();
+    if (tid < 64) tridiag_wave(A, k, beta, e);
     __syncthreads();
     if (tid < k) d[tid] = A[tid][tid];
     if (tid == 0) {
