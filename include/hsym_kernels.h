@@ -52,7 +52,8 @@ int hsym_kernel_lincomb(int64_t n, int m, int nin, const double *const *In, int 
 /*
  * Rayleigh-Ritz of eq. 9 on a basis S of nblk (1..3) blocks of m columns
  * (Algorithm 1, steps 7-9), k = nblk*m: G is device k x 2k row-major,
- * [S^T S | S^T A S], each half symmetrised on input.  The basis is made
+ * [S^T S | S^T A S]; each half is read from its upper triangle (the entries
+ * below the diagonal are not used).  The basis is made
  * orthonormal in coefficient space from S^T S: its Cholesky factor in the
  * block order [X W P] is Gram-Schmidt of W against X and of P against X and
  * W (a second factorisation follows when a pivot is below 1e-4); the third

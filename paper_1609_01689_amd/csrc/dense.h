@@ -11,6 +11,10 @@ struct GramArgs {
     int na, nb;       // number of n x m blocks on each side
     int m;
     int64_t n;
+    // 1: b = [a, A a] (the Rayleigh-Ritz Gram [S^T S | S^T A S]) and only the
+    // blocks on and above the diagonal of each half are needed; with
+    // na * m a multiple of 16 the 16 x 16 tiles below them are left zero
+    int sym;
 };
 // out (na*m x nb*m, row-major) = [a]^T [b]; scratch >= gram_scratch_bytes
 void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s);

@@ -26,7 +26,7 @@ __device__ __forceinline__ double guard_den(double d, double delta) {
 // ---------------------------------------------------------------------------
 // MFMA f64 16x16x4 operand layout: lane l holds A[i=l%16][k=l/16] and
 // B[k=l/16][j=l%16]; accumulator register v of lane l holds D[l/16 + 4v][l%16].
-template <int T1, int T2>
+template <int T1, int T2, bool SYM = false>
 __device__ __forceinline__ void gram_partial_body(const GramArgs &g, double *__restrict__ part, int64_t rows_per_wg,
                                                   int64_t bx) {
     // the four waves' partial sums meet in LDS, at most 3 column tiles at a time
@@ -81,8 +81,11 @@ __device__ __forceinline__ void gram_partial_body(const GramArgs &g, double *__r
 #pragma unroll
             for (int i = 0; i < T1; i++)
 #pragma unroll
-                for (int j = 0; j < T2; j++)
+                for (int j = 0; j < T2; j++) {
+                    // SYM: tiles below the diagonal of either half are not formed
+                    if (SYM && (j < T1 ? j < i : j - T1 < i)) continue;
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i], bv[u][j], acc[i][j], 0, 0, 0);
+                }
     }
     double *out = part + bx * K1 * K2;
 #pragma unroll
@@ -104,9 +107,9 @@ __device__ __forceinline__ void gram_partial_body(const GramArgs &g, double *__r
     }
 }
 
-template <int T1, int T2>
+template <int T1, int T2, bool SYM = false>
 __global__ __launch_bounds__(256) void k_gram_partial(GramArgs g, double *__restrict__ part, int64_t rows_per_wg) {
-    gram_partial_body<T1, T2>(g, part, rows_per_wg, blockIdx.x);
+    gram_partial_body<T1, T2, SYM>(g, part, rows_per_wg, blockIdx.x);
 }
 
 // batched over problems: blockIdx.y selects the job
@@ -185,11 +188,19 @@ void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s) {
     const int T1 = (K1 + 15) / 16, T2 = (K2 + 15) / 16;
     const int parts = gram_parts(g.n);
     const int64_t rpw = gram_rows(g.n, parts);
+    if (g.sym && K1 % 16 == 0 && g.nb == 2 * g.na) {
+        // [S^T S | S^T A S]: the half-tile skipping needs the halves to start on a tile
+#define GS(a) if (T1 == a) { hipLaunchKernelGGL((k_gram_partial<a, 2 * a, true>), dim3(parts), dim3(256), 0, s, g, scratch, rpw); } else
+        GS(1) GS(2) GS(3)
+            fail(HSYM_E_UNSUPPORTED, "gram shape");
+#undef GS
+    } else {
 #define GL(a, b) if (T1 == a && T2 == b) { gram_launch_t<a, b>(g, scratch, parts, rpw, s); } else
     GL(1, 1) GL(1, 2) GL(1, 3) GL(2, 1) GL(2, 2) GL(2, 3) GL(3, 1) GL(3, 2) GL(3, 3)
     GL(1, 4) GL(1, 6) GL(2, 4) GL(2, 5) GL(2, 6) GL(3, 4) GL(3, 5) GL(3, 6)
         fail(HSYM_E_UNSUPPORTED, "gram shape");
 #undef GL
+    }
     HIPCHK(hipGetLastError());
     const int kk = K1 * K2;
     hipLaunchKernelGGL(k_gram_final, dim3((kk + 63) / 64), dim3(1024), 0, s, scratch, parts, kk, out);

@@ -188,7 +188,7 @@ struct Lobpcg {
         spmm(X, AX);
         rep.spmm_calls++;
         GramArgs g{};
-        g.a[0] = X; g.b[0] = X; g.b[1] = AX; g.na = 1; g.nb = 2; g.m = m; g.n = n;
+        g.a[0] = X; g.b[0] = X; g.b[1] = AX; g.na = 1; g.nb = 2; g.m = m; g.n = n; g.sym = 1;
         mark(3);
         gram(g, gbuf, gram_scr, s);
         mark(4);
@@ -401,7 +401,7 @@ struct Lobpcg {
             g.a[0] = X; g.a[1] = W; g.a[2] = P;
             g.b[0] = X; g.b[1] = W; g.b[2] = P;
             g.b[nblk] = AX; g.b[nblk + 1] = AW; if (nblk == 3) g.b[5] = AP;
-            g.na = nblk; g.nb = 2 * nblk; g.m = m; g.n = n;
+            g.na = nblk; g.nb = 2 * nblk; g.m = m; g.n = n; g.sym = 1;
             mark(3);
             gram(g, gbuf, gram_scr, s);
             mark(4);

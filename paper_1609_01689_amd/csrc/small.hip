@@ -510,15 +510,13 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
         }
     }
     __syncthreads();
+    // each half is taken from its upper triangle (the Gram may leave the
+    // tiles below the diagonal unformed)
     for (int e0 = tid; e0 < k0 * k0; e0 += 256) {
         const int i = e0 / k0, j = e0 - (e0 / k0) * k0;
         if (i < j) {
-            const double v = 0.5 * (A[i][j] + A[j][i]);
-            A[i][j] = v;
-            A[j][i] = v;
-            const double w = 0.5 * (GS[i][j] + GS[j][i]);
-            GS[i][j] = w;
-            GS[j][i] = w;
+            A[j][i] = A[i][j];
+            GS[j][i] = GS[i][j];
         }
     }
     if (tid == 0) { bad = 0; nrounds = 0; second = 0; }

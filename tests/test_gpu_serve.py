@@ -73,6 +73,11 @@ def test_serve_budget_limits_inflight():
     print("unconstrained", free, "budget", budget, rep)
     assert all(r["status"] == hs.HSYM_OK for r in res), [r["status"] for r in res]
     assert rep["peak_reserved_bytes"] <= budget
+    # what each request held on the device (handle + solver context) stays
+    # within the estimate it was admitted on
+    for r, q in zip(res, reqs):
+        print("n=%d held %d estimate %d" % (q["csr"].n, r["device_bytes"], estimate(q)))
+        assert 0 < r["device_bytes"] <= estimate(q)
     if budget < free["peak_reserved_bytes"]:
         # fewer requests fit at once than without a budget
         assert rep["peak_reserved_bytes"] < free["peak_reserved_bytes"]
