@@ -93,9 +93,10 @@ Geom geometry_for(int storage, int m, int64_t n, int r64, int lc) {
         // perm codes of a piece index at most 2^16 positions
         const size_t eb = (size_t)g.idx_bytes + 2 + sa;
         int64_t e = (int64_t)((budget - fixed - 64) / eb);
-        // a piece is staged through registers: at most 4 units of 16 bytes per
-        // thread of the workgroup, three streams each rounded up to 16 bytes
-        e = std::min<int64_t>(e, ((int64_t)4 * 1024 - 3) * 16 / (int64_t)eb);
+        // a piece is staged through registers: at most spmm_stage_units(M)
+        // units of 16 bytes per thread of the workgroup, three streams each
+        // rounded up to 16 bytes
+        e = std::min<int64_t>(e, ((int64_t)spmm_stage_units(M) * 1024 - 3) * 16 / (int64_t)eb);
         e = std::min<int64_t>(e, 16384) & ~(int64_t)7;
         g.maxe = (int)e;
         return spmm_lds_bytes(storage, M, g) <= budget;

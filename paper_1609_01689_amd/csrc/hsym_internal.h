@@ -16,6 +16,10 @@ namespace hsym {
 // atomics per lane, the count measured fastest on gfx950 (four per lane, as
 // 32-byte fp64 or 16-byte fp32 lanes need, run at half the rate).
 __host__ __device__ constexpr int spmm_lane_elems(int M) { return M < 2 ? M : 2; }
+// 16-byte units of a staged piece per thread of the 1024-thread SpMM
+// workgroup: 8 at block widths 1 and 2 (the X rows and accumulators then leave
+// room for larger pieces and the kernel for the registers), else 4.
+__host__ __device__ constexpr int spmm_stage_units(int M) { return M <= 2 ? 8 : 4; }
 
 
 // block widths are rounded up to the next of 1, 2, 4, 8, 16 for the kernels

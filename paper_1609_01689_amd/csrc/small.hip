@@ -373,19 +373,26 @@ __device__ void wave_chol(const double (*S)[KMAX + 1], int k, double (*L)[KMAX +
 }
 
 // Li = (D^-1 Ls)^-1 = Ls^-1 D for the factor Ls of the scaled matrix and
-// D = diag(sc): one lane per column c, forward substitution on its own column
-// of Li (the entries above the diagonal are zero).
+// D = diag(sc): one lane of the first wave per column c, forward substitution
+// with the column held in registers (entries above the diagonal are zero) and
+// the rows of Ls read from LDS as broadcasts.  Other threads return at once.
 __device__ void tri_inverse(const double (*L)[KMAX + 1], const double *sc, int k, double (*Li)[KMAX + 1]) {
     const int c = threadIdx.x;
-    if (c >= k) return;
-    for (int i = 0; i < c; i++) Li[i][c] = 0.0;
-    for (int i = c; i < k; i++) {
+    if (c >= 64) return;
+    double li[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; i++) {
         double v = i == c ? 1.0 : 0.0;
-        for (int q = c; q < i; q++) v = fma(-L[i][q], Li[q][c], v);
-        Li[i][c] = v / L[i][i];
+#pragma unroll
+        for (int q = 0; q < i; q++) v = fma(-L[i < k ? i : 0][q], li[q], v);
+        li[i] = (i >= c && i < k) ? v / L[i < k ? i : 0][i < k ? i : 0] : 0.0;
     }
-    const double s_c = sc[c];
-    for (int i = c; i < k; i++) Li[i][c] *= s_c;
+    if (c < k) {
+        const double s_c = sc[c];
+#pragma unroll
+        for (int i = 0; i < KMAX; i++)
+            if (i < k) Li[i][c] = li[i] * s_c;
+    }
 }
 
 // B <- Li S Li^T (k x k, exactly symmetric) for lower-triangular Li; T is

@@ -35,7 +35,6 @@
 namespace hsym {
 
 constexpr int SPMM_NT = 1024;
-constexpr int SPMM_KU = 4;   // 16-byte staging units per thread (see geometry_for)
 constexpr int SPMM_XE = 4;   // X chunk elements per thread (C * M <= 4096)
 
 template <int M, typename A>
@@ -106,15 +105,22 @@ __device__ __forceinline__ void y_add(YT *p, double v) {
 // Load a piece into registers: 16-byte units of its bytes (thread tid takes
 // units tid, tid + 1024, ...), and the X chunk of an external tile's first
 // piece (element i = tid + k * 1024 of the C x M chunk).
-template <int M, typename XT>
-__device__ __forceinline__ void spmm_fetch(const SpmmArgs &a, const TileDesc &td, int nunits, uint4 &s0, uint4 &s1,
-                                           uint4 &s2, uint4 &s3, XT &x0, XT &x1, XT &x2, XT &x3) {
+template <int M, typename XT, int KU>
+__device__ __forceinline__ void spmm_fetch(const SpmmArgs &a, const TileDesc &td, int nunits, uint4 &u0, uint4 &u1,
+                                           uint4 &u2, uint4 &u3, uint4 &u4, uint4 &u5, uint4 &u6, uint4 &u7, XT &x0,
+                                           XT &x1, XT &x2, XT &x3) {
     const int tid = threadIdx.x;
     const uint4 *g = reinterpret_cast<const uint4 *>(a.blob + td.base);
-    if (tid < nunits) s0 = g[tid];
-    if (tid + SPMM_NT < nunits) s1 = g[tid + SPMM_NT];
-    if (tid + 2 * SPMM_NT < nunits) s2 = g[tid + 2 * SPMM_NT];
-    if (tid + 3 * SPMM_NT < nunits) s3 = g[tid + 3 * SPMM_NT];
+    if (tid < nunits) u0 = g[tid];
+    if (tid + SPMM_NT < nunits) u1 = g[tid + SPMM_NT];
+    if (tid + 2 * SPMM_NT < nunits) u2 = g[tid + 2 * SPMM_NT];
+    if (tid + 3 * SPMM_NT < nunits) u3 = g[tid + 3 * SPMM_NT];
+    if constexpr (KU > 4) {
+        if (tid + 4 * SPMM_NT < nunits) u4 = g[tid + 4 * SPMM_NT];
+        if (tid + 5 * SPMM_NT < nunits) u5 = g[tid + 5 * SPMM_NT];
+        if (tid + 6 * SPMM_NT < nunits) u6 = g[tid + 6 * SPMM_NT];
+        if (tid + 7 * SPMM_NT < nunits) u7 = g[tid + 7 * SPMM_NT];
+    }
     if (td.ext && (td.flags & TILE_FIRST)) {
         const XT *X = reinterpret_cast<const XT *>(a.X);
         const int C = a.g.C, m = a.m;
@@ -131,7 +137,7 @@ __device__ __forceinline__ void spmm_fetch(const SpmmArgs &a, const TileDesc &td
     }
 }
 
-template <int M, typename T, typename A, typename XT, typename YT, typename IT>
+template <int M, typename T, typename A, typename XT, typename YT, typename IT, int KU>
 __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, unsigned char *smem) {
     using Ly = Lay<M, A>;
     constexpr int MW = Ly::MW, L = Ly::L, GK = Ly::GK, SA = Ly::SA;
@@ -173,9 +179,11 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
     const int64_t t0 = a.ptp[p], t1 = a.ptp[p + 1];
     // registers holding the next piece: 16-byte units of its three streams,
     // and (first piece of an external tile) its X chunk
-    uint4 su0, su1, su2, su3;
+    // (the first KU of the eight are used; named registers, not an array,
+    // which the compiler would place in scratch memory)
+    uint4 su0, su1, su2, su3, su4, su5, su6, su7;
     XT xr0 = (XT)0, xr1 = (XT)0, xr2 = (XT)0, xr3 = (XT)0;
-    static_assert(SPMM_KU == 4 && SPMM_XE == 4, "staging registers are unrolled by hand");
+    static_assert(SPMM_XE == 4, "X chunk registers are unrolled by hand");
     // descriptors travel one piece ahead of the data they describe, so that
     // no wait on memory sits between two pieces
     // (scalar loads through the constant address space: they do not wait
@@ -196,7 +204,7 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
         tdc = tile_at(t0);
         int op0, ov0, nu0;
         parts(tdc.len, op0, ov0, nu0);
-        spmm_fetch<M, XT>(a, tdc, nu0, su0, su1, su2, su3, xr0, xr1, xr2, xr3);
+        spmm_fetch<M, XT, KU>(a, tdc, nu0, su0, su1, su2, su3, su4, su5, su6, su7, xr0, xr1, xr2, xr3);
         if (t0 + 1 < t1) tdn = tile_at(t0 + 1);
     }
 
@@ -233,6 +241,12 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
             if (tid + SPMM_NT < nunits) sdst[tid + SPMM_NT] = su1;
             if (tid + 2 * SPMM_NT < nunits) sdst[tid + 2 * SPMM_NT] = su2;
             if (tid + 3 * SPMM_NT < nunits) sdst[tid + 3 * SPMM_NT] = su3;
+            if constexpr (KU > 4) {
+                if (tid + 4 * SPMM_NT < nunits) sdst[tid + 4 * SPMM_NT] = su4;
+                if (tid + 5 * SPMM_NT < nunits) sdst[tid + 5 * SPMM_NT] = su5;
+                if (tid + 6 * SPMM_NT < nunits) sdst[tid + 6 * SPMM_NT] = su6;
+                if (tid + 7 * SPMM_NT < nunits) sdst[tid + 7 * SPMM_NT] = su7;
+            }
             if (td.ext && (td.flags & TILE_FIRST)) {
                 if (tid < C * M) xs[tid] = (A)xr0;
                 if (tid + SPMM_NT < C * M) xs[tid + SPMM_NT] = (A)xr1;
@@ -243,7 +257,7 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
         if (t + 1 < t1) {
             int opn, ovn, nun;
             parts(tdn.len, opn, ovn, nun);
-            spmm_fetch<M, XT>(a, tdn, nun, su0, su1, su2, su3, xr0, xr1, xr2, xr3);
+            spmm_fetch<M, XT, KU>(a, tdn, nun, su0, su1, su2, su3, su4, su5, su6, su7, xr0, xr1, xr2, xr3);
             tdc = tdn;
             if (t + 2 < t1) tdn = tile_at(t + 2);
         }
@@ -342,10 +356,10 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
     }
 }
 
-template <int M, typename T, typename A, typename XT, typename YT, typename IT>
+template <int M, typename T, typename A, typename XT, typename YT, typename IT, int KU>
 __global__ __launch_bounds__(SPMM_NT) void k_spmm_panel(SpmmArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    spmm_panel_body<M, T, A, XT, YT, IT>(a, blockIdx.x, smem_raw);
+    spmm_panel_body<M, T, A, XT, YT, IT, KU>(a, blockIdx.x, smem_raw);
 }
 
 // batched over matrices (fp64 blocks): blockIdx.y selects the job
@@ -359,8 +373,9 @@ __global__ __launch_bounds__(SPMM_NT) void k_spmm_panel_b(const SpmmJob *__restr
     a.diag = J.diag; a.X = J.X; a.ldx = J.ldx; a.Y = J.Y; a.ldy = J.ldy; a.n = J.n; a.npanels = J.npanels;
     a.g = J.g; a.m = J.m;
     // the code width is a property of each job's handle (uniform per workgroup)
-    if (J.g.idx_bytes == 2) spmm_panel_body<M, T, A, double, double, uint16_t>(a, blockIdx.x, smem_raw);
-    else spmm_panel_body<M, T, A, double, double, uint32_t>(a, blockIdx.x, smem_raw);
+    constexpr int KU = spmm_stage_units(M);
+    if (J.g.idx_bytes == 2) spmm_panel_body<M, T, A, double, double, uint16_t, KU>(a, blockIdx.x, smem_raw);
+    else spmm_panel_body<M, T, A, double, double, uint32_t, KU>(a, blockIdx.x, smem_raw);
 }
 
 // Y[r][0..m) = 0 for r < n (leading dimension ldy): the SpMM adds into Y (a
@@ -390,7 +405,9 @@ static void zero_rows(YT *Y, int64_t n, int m, int64_t ldy, hipStream_t s) {
     HIPCHK(hipGetLastError());
 }
 
-static void check_fit(int storage, int m, const Geom &g) {
+// Checks that a call of width m fits the handle's geometry; returns the
+// staging units per thread its pieces need (4 or 8).
+static int check_fit(int storage, int m, const Geom &g) {
     const int M = round_m(m);
     if (spmm_lds_bytes(storage, m, g) > 160 * 1024)
         fail(HSYM_E_UNSUPPORTED, "block width too large for this handle's panel geometry");
@@ -398,14 +415,16 @@ static void check_fit(int storage, int m, const Geom &g) {
         fail(HSYM_E_UNSUPPORTED, "chunk too wide for this block width");
     const int64_t e = g.maxe, sv = storage == HSYM_FP64 ? 8 : 4;
     const int64_t bytes = ((e * g.idx_bytes + 15) & ~15) + ((e * 2 + 15) & ~15) + ((e * sv + 15) & ~15);
-    if (bytes / 16 > (int64_t)SPMM_KU * SPMM_NT) fail(HSYM_E_UNSUPPORTED, "pieces too large for the staging registers");
+    const int64_t units = (bytes / 16 + SPMM_NT - 1) / SPMM_NT;
+    if (units > 8) fail(HSYM_E_UNSUPPORTED, "pieces too large for the staging registers");
+    return units > 4 ? 8 : 4;
 }
 
-template <int M, typename T, typename A, typename XT, typename YT, typename IT>
+template <int M, typename T, typename A, typename XT, typename YT, typename IT, int KU>
 static void launch_typed(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
     const DeviceTiles &dt = H->tiles;
     const size_t lds = spmm_lds_bytes(H->storage, m, dt.g);
-    auto kp = k_spmm_panel<M, T, A, XT, YT, IT>;
+    auto kp = k_spmm_panel<M, T, A, XT, YT, IT, KU>;
     static std::once_flag attr_once;   // the 160 KB LDS limit, set once (threads may launch concurrently)
     std::call_once(attr_once, [&] {
         HIPCHK(hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
@@ -419,21 +438,32 @@ static void launch_typed(hsym_matrix *H, int m, const void *X, int64_t ldx, void
     HIPCHK(hipGetLastError());
 }
 
+// pieces of a handle built for block width 1 or 2 need 8 staging units per
+// thread; a wider call on such a handle takes the 8-unit kernel of its width
+template <int M, typename T, typename A, typename XT, typename YT, typename IT>
+static void launch_ku(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y, int64_t ldy, int ku,
+                      hipStream_t s) {
+    if (ku > 4) launch_typed<M, T, A, XT, YT, IT, 8>(H, m, X, ldx, Y, ldy, s);
+    else launch_typed<M, T, A, XT, YT, IT, spmm_stage_units(M)>(H, m, X, ldx, Y, ldy, s);
+}
+
 template <typename T, typename A, typename XT, typename YT, typename IT>
-static void launch_mi(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
+static void launch_mi(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y, int64_t ldy, int ku,
+                      hipStream_t s) {
     switch (round_m(m)) {
-        case 1: launch_typed<1, T, A, XT, YT, IT>(H, m, X, ldx, Y, ldy, s); break;
-        case 2: launch_typed<2, T, A, XT, YT, IT>(H, m, X, ldx, Y, ldy, s); break;
-        case 4: launch_typed<4, T, A, XT, YT, IT>(H, m, X, ldx, Y, ldy, s); break;
-        case 8: launch_typed<8, T, A, XT, YT, IT>(H, m, X, ldx, Y, ldy, s); break;
-        default: launch_typed<16, T, A, XT, YT, IT>(H, m, X, ldx, Y, ldy, s); break;
+        case 1: launch_ku<1, T, A, XT, YT, IT>(H, m, X, ldx, Y, ldy, ku, s); break;
+        case 2: launch_ku<2, T, A, XT, YT, IT>(H, m, X, ldx, Y, ldy, ku, s); break;
+        case 4: launch_ku<4, T, A, XT, YT, IT>(H, m, X, ldx, Y, ldy, ku, s); break;
+        case 8: launch_ku<8, T, A, XT, YT, IT>(H, m, X, ldx, Y, ldy, ku, s); break;
+        default: launch_ku<16, T, A, XT, YT, IT>(H, m, X, ldx, Y, ldy, ku, s); break;
     }
 }
 
 template <typename T, typename A, typename XT, typename YT>
-static void launch_m(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
-    if (H->tiles.g.idx_bytes == 2) launch_mi<T, A, XT, YT, uint16_t>(H, m, X, ldx, Y, ldy, s);
-    else launch_mi<T, A, XT, YT, uint32_t>(H, m, X, ldx, Y, ldy, s);
+static void launch_m(hsym_matrix *H, int m, const void *X, int64_t ldx, void *Y, int64_t ldy, int ku,
+                     hipStream_t s) {
+    if (H->tiles.g.idx_bytes == 2) launch_mi<T, A, XT, YT, uint16_t>(H, m, X, ldx, Y, ldy, ku, s);
+    else launch_mi<T, A, XT, YT, uint32_t>(H, m, X, ldx, Y, ldy, ku, s);
 }
 
 SpmmJob spmm_job(hsym_matrix *H, int m, const double *X, double *Y) {
@@ -451,7 +481,8 @@ static void batched_typed(const SpmmJob *jobs, const SpmmJob *host, int count, i
     size_t lds = 0;
     int64_t maxp = 0, maxn = 0;
     for (int i = 0; i < count; i++) {
-        check_fit(storage, host[i].m, host[i].g);
+        if (check_fit(storage, host[i].m, host[i].g) > spmm_stage_units(M))
+            fail(HSYM_E_UNSUPPORTED, "batched SpMM: pieces too large for the staging registers of this width");
         lds = std::max(lds, spmm_lds_bytes(storage, host[i].m, host[i].g));
         maxp = std::max(maxp, host[i].npanels);
         maxn = std::max(maxn, host[i].n * host[i].m);
@@ -481,15 +512,15 @@ void spmm_batched(const SpmmJob *jobs, const SpmmJob *host, int count, int m, in
 
 void spmm_launch(hsym_matrix *H, int m, const void *X, int xprec, int64_t ldx, void *Y, int yprec, int64_t ldy,
                  hipStream_t s) {
-    check_fit(H->storage, m, H->tiles.g);
+    const int ku = check_fit(H->storage, m, H->tiles.g);
     if (H->storage == HSYM_FP64) {
         if (xprec != T_F64 || yprec != T_F64) fail(HSYM_E_INVALID_ARG, "fp64 storage takes fp64 blocks");
-        launch_m<double, double, double, double>(H, m, X, ldx, Y, ldy, s);
+        launch_m<double, double, double, double>(H, m, X, ldx, Y, ldy, ku, s);
     } else {
-        if (xprec == T_F64 && yprec == T_F64) launch_m<float, float, double, double>(H, m, X, ldx, Y, ldy, s);
-        else if (xprec == T_F32 && yprec == T_F32) launch_m<float, float, float, float>(H, m, X, ldx, Y, ldy, s);
-        else if (xprec == T_F32 && yprec == T_F64) launch_m<float, float, float, double>(H, m, X, ldx, Y, ldy, s);
-        else launch_m<float, float, double, float>(H, m, X, ldx, Y, ldy, s);
+        if (xprec == T_F64 && yprec == T_F64) launch_m<float, float, double, double>(H, m, X, ldx, Y, ldy, ku, s);
+        else if (xprec == T_F32 && yprec == T_F32) launch_m<float, float, float, float>(H, m, X, ldx, Y, ldy, ku, s);
+        else if (xprec == T_F32 && yprec == T_F64) launch_m<float, float, float, double>(H, m, X, ldx, Y, ldy, ku, s);
+        else launch_m<float, float, double, float>(H, m, X, ldx, Y, ldy, ku, s);
     }
 }
 
