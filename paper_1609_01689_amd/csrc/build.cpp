@@ -61,7 +61,8 @@ void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, in
 size_t spmm_lds_bytes(int storage, int m, const Geom &g) {
     const size_t M = (size_t)round_m(m), sa = storage == HSYM_FP64 ? 8 : 4;
     auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
-    return (size_t)(g.R + g.C) * M * (8 + sa) + r16((size_t)g.maxe * g.idx_bytes) + r16((size_t)g.maxe * 2) +
+    const size_t xs = M + (size_t)spmm_xpad((int)M);   // staged X row stride
+    return (size_t)(g.R + g.C) * (M * 8 + xs * sa) + r16((size_t)g.maxe * g.idx_bytes) + r16((size_t)g.maxe * 2) +
            r16((size_t)g.maxe * sa);
 }
 

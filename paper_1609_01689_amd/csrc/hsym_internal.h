@@ -20,6 +20,12 @@ __host__ __device__ constexpr int spmm_lane_elems(int M) { return M < 2 ? M : 2;
 // workgroup: 8 at block widths 1 and 2 (the X rows and accumulators then leave
 // room for larger pieces and the kernel for the registers), else 4.
 __host__ __device__ constexpr int spmm_stage_units(int M) { return M <= 2 ? 8 : 4; }
+// Elements of padding after each X row the SpMM stages in LDS (block widths of
+// 4 and more), so that the rows gathered by one wave start on more banks.
+#ifndef HSYM_XPAD
+#define HSYM_XPAD 0
+#endif
+__host__ __device__ constexpr int spmm_xpad(int M) { return M >= 4 ? HSYM_XPAD : 0; }
 
 
 // block widths are rounded up to the next of 1, 2, 4, 8, 16 for the kernels

@@ -148,11 +148,12 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
     // LDS layout (byte offsets): acc, ts (fp64), xp, xs (A), codes, perm, values
     double *acc = reinterpret_cast<double *>(smem);
     double *ts = acc + (size_t)R * M;
+    constexpr int XS = M + spmm_xpad(M);   // staged X row stride (padded)
     A *xp = reinterpret_cast<A *>(ts + (size_t)C * M);
-    A *xs = xp + (size_t)R * M;
+    A *xs = xp + (size_t)R * XS;
     // the staged piece: its bytes as stored (codes, perm, values; the offsets
     // of the last two depend on the piece's size)
-    unsigned char *stg = smem + (size_t)(R + C) * M * (8 + SA);
+    unsigned char *stg = smem + (size_t)(R + C) * ((size_t)M * 8 + (size_t)XS * SA);
     (void)maxe;
     auto parts = [&](int len, int &op, int &ov, int &nunits) {
         const int E = G * len;
@@ -171,7 +172,7 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
         const int r = i / M, k = i - r * M;
         A v = (A)0;
         if (r < nrow && k < m) v = (A)X[(row0 + r) * a.ldx + k];
-        xp[i] = v;
+        xp[r * XS + k] = v;
         acc[i] = 0.0;
     }
     for (int i = tid; i < C * M; i += SPMM_NT) ts[i] = 0.0;
@@ -248,10 +249,14 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
                 if (tid + 7 * SPMM_NT < nunits) sdst[tid + 7 * SPMM_NT] = su7;
             }
             if (td.ext && (td.flags & TILE_FIRST)) {
-                if (tid < C * M) xs[tid] = (A)xr0;
-                if (tid + SPMM_NT < C * M) xs[tid + SPMM_NT] = (A)xr1;
-                if (tid + 2 * SPMM_NT < C * M) xs[tid + 2 * SPMM_NT] = (A)xr2;
-                if (tid + 3 * SPMM_NT < C * M) xs[tid + 3 * SPMM_NT] = (A)xr3;
+                // element i of the chunk (row i / M, column i % M) at its padded place
+                auto xput = [&](int i, XT v) {
+                    if (i < C * M) xs[(i / M) * XS + i % M] = (A)v;
+                };
+                xput(tid, xr0);
+                xput(tid + SPMM_NT, xr1);
+                xput(tid + 2 * SPMM_NT, xr2);
+                xput(tid + 3 * SPMM_NT, xr3);
             }
         }
         if (t + 1 < t1) {
@@ -268,7 +273,7 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
         const T *sval = reinterpret_cast<const T *>(stg + ov);
         // row pass: U X
         {
-            const A *xsrc = td.ext ? xs : xp + (size_t)(col0 - row0) * M;
+            const A *xsrc = td.ext ? xs : xp + (size_t)(col0 - row0) * XS;
             for (int seg = grp; seg < G; seg += GK) {
                 int cur = -1;
                 A ra[MW];
@@ -285,7 +290,7 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
                         av[u] = s0 + u < len ? (A)sval[e] : (A)0;
                     }
 #pragma unroll
-                    for (int u = 0; u < U; u++) lds_get<MW, A>(xsrc + (size_t)(w[u] & cm) * M + q * MW, xv[u]);
+                    for (int u = 0; u < U; u++) lds_get<MW, A>(xsrc + (size_t)(w[u] & cm) * XS + q * MW, xv[u]);
 #pragma unroll
                     for (int u = 0; u < U; u++) {
                         const int r = (int)(w[u] >> cb);
@@ -324,7 +329,7 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
                         av[u] = s0 + u < len ? (A)sval[pe[u]] : (A)0;
                     }
 #pragma unroll
-                    for (int u = 0; u < U; u++) lds_get<MW, A>(xp + (size_t)(w[u] >> cb) * M + q * MW, xv[u]);
+                    for (int u = 0; u < U; u++) lds_get<MW, A>(xp + (size_t)(w[u] >> cb) * XS + q * MW, xv[u]);
 #pragma unroll
                     for (int u = 0; u < U; u++) {
                         const int c = (int)(w[u] & cm);
@@ -351,7 +356,7 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
         const int r = i / M, k = i - r * M;
         if (k < m) {
             const int64_t row = row0 + r;
-            y_add<YT>(Y + row * a.ldy + k, acc[i] + (double)diag[row] * (double)xp[i]);
+            y_add<YT>(Y + row * a.ldy + k, acc[i] + (double)diag[row] * (double)xp[r * XS + k]);
         }
     }
 }
