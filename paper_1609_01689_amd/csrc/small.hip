@@ -183,22 +183,23 @@ void small_orth(const OrthArgs *a, int count, hipStream_t s) {
 // rescaled by a power of two every 4 steps.  A pivot of magnitude below PIV
 // is replaced by -PIV (the LAPACK bisection convention), which also keeps
 // every p_i nonzero and each step's growth within 2^62.
-// d is held in registers (KMAX entries; padded past k with d = 4, e^2 = 0,
+// d is held in registers (KM entries; padded past k with d = 4, e^2 = 0,
 // steps that keep the sign, since x lies in [-1.01, 1.01]); e^2 is read from
 // LDS as a broadcast.
-__device__ __forceinline__ int sturm_count_r(const double (&d)[KMAX], const double *e2, double x) {
+template <int KM>
+__device__ __forceinline__ int sturm_count_r(const double (&d)[KM], const double *e2, double x) {
     constexpr double PIV = 0x1p-60;
     double p = d[0] - x, q = 1.0;
     if (fabs(p) < PIV) p = -PIV;
     int n = p < 0.0;
 #pragma unroll
-    for (int i = 1; i < KMAX; i++) {
+    for (int i = 1; i < KM; i++) {
         double tt = fma(d[i] - x, p, -e2[i - 1] * q);
         if (fabs(tt) < PIV * fabs(p)) tt = -PIV * p;
         n += (tt < 0.0) != (p < 0.0);
         q = p;
         p = tt;
-        if (i % 4 == 0 || i == KMAX - 1) {
+        if (i % 4 == 0 || i == KM - 1) {
             const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(p), fabs(q)));
             p = __builtin_amdgcn_ldexp(p, -ex);
             q = __builtin_amdgcn_ldexp(q, -ex);
@@ -343,30 +344,31 @@ __device__ void proj_out(double (*Z)[17], const double (*Y)[17], int k, int m, d
 // of the scaled matrix to L (lower part), the scales 1/sqrt(S_rr) to sc and
 // the pivots (the squared sine of the angle between basis vector r and the
 // span of the ones before it) to pv; returns nothing (other waves skip it).
+template <int KM>
 __device__ void wave_chol(const double (*S)[KMAX + 1], int k, double (*L)[KMAX + 1], double *sc, double *pv) {
     const int lane = threadIdx.x & 63;
-    const int r = lane < KMAX ? lane : KMAX - 1;
+    const int r = lane < KM ? lane : KM - 1;
     const double sd = r < k ? S[r][r] : 1.0;
     const double s_r = sd > 0.0 ? 1.0 / sqrt(sd) : 0.0;
-    double g[KMAX];
+    double g[KM];
 #pragma unroll
-    for (int c = 0; c < KMAX; c++) {
+    for (int c = 0; c < KM; c++) {
         const double s_c = read_lane(s_r, c);
         g[c] = c <= r ? ((r < k) ? S[r][c] * s_r * s_c : (c == r ? 1.0 : 0.0)) : 0.0;
     }
 #pragma unroll
-    for (int j = 0; j < KMAX; j++) {
+    for (int j = 0; j < KM; j++) {
         const double pj = read_lane(g[j], j);
         const double dj = sqrt(fmax(pj, 1e-300));
         const double l = (r == j) ? dj : g[j] / dj;
         g[j] = l;
 #pragma unroll
-        for (int c = j + 1; c < KMAX; c++) g[c] = fma(-l, read_lane(l, c), g[c]);
+        for (int c = j + 1; c < KM; c++) g[c] = fma(-l, read_lane(l, c), g[c]);
         if (lane == j) pv[j] = pj;
     }
     if (lane < k) {
 #pragma unroll
-        for (int c = 0; c < KMAX; c++)
+        for (int c = 0; c < KM; c++)
             if (c <= lane) L[lane][c] = g[c];
         sc[lane] = s_r;
     }
@@ -376,12 +378,13 @@ __device__ void wave_chol(const double (*S)[KMAX + 1], int k, double (*L)[KMAX +
 // D = diag(sc): one lane of the first wave per column c, forward substitution
 // with the column held in registers (entries above the diagonal are zero) and
 // the rows of Ls read from LDS as broadcasts.  Other threads return at once.
+template <int KM>
 __device__ void tri_inverse(const double (*L)[KMAX + 1], const double *sc, int k, double (*Li)[KMAX + 1]) {
     const int c = threadIdx.x;
     if (c >= 64) return;
-    double li[KMAX];
+    double li[KM];
 #pragma unroll
-    for (int i = 0; i < KMAX; i++) {
+    for (int i = 0; i < KM; i++) {
         double v = i == c ? 1.0 : 0.0;
 #pragma unroll
         for (int q = 0; q < i; q++) v = fma(-L[i < k ? i : 0][q], li[q], v);
@@ -390,7 +393,7 @@ __device__ void tri_inverse(const double (*L)[KMAX + 1], const double *sc, int k
     if (c < k) {
         const double s_c = sc[c];
 #pragma unroll
-        for (int i = 0; i < KMAX; i++)
+        for (int i = 0; i < KM; i++)
             if (i < k) Li[i][c] = li[i] * s_c;
     }
 }
@@ -435,13 +438,14 @@ __device__ __forceinline__ void static_for(F &&f) {
 // diagonal and first subdiagonal (T), the reflector of step j in column j
 // below the subdiagonal (first entry x0 - alpha), beta[j] = 2 / v.v and
 // e[j] = alpha (0 where nothing was annihilated).
+template <int KM>
 __device__ void tridiag_wave(double (*A)[KMAX + 1], int k, double *beta, double *e) {
     const int lane = threadIdx.x & 63;
-    const int r = lane < KMAX ? lane : KMAX - 1;
-    double a[KMAX];
+    const int r = lane < KM ? lane : KM - 1;
+    double a[KM];
 #pragma unroll
-    for (int c = 0; c < KMAX; c++) a[c] = (lane < k && c < k) ? A[r][c] : 0.0;
-    static_for<0, KMAX - 2>([&](auto jc) {
+    for (int c = 0; c < KM; c++) a[c] = (lane < k && c < k) ? A[r][c] : 0.0;
+    static_for<0, KM - 2>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         if (j + 2 < k) {
             const bool below = lane > j && lane < k;
@@ -460,13 +464,13 @@ __device__ void tridiag_wave(double (*A)[KMAX + 1], int k, double *beta, double 
                 // p = beta A22 v
                 double p = 0.0;
 #pragma unroll
-                for (int c = j + 1; c < KMAX; c++) p = fma(a[c], read_lane(v, c), p);
+                for (int c = j + 1; c < KM; c++) p = fma(a[c], read_lane(v, c), p);
                 p = lane < k ? bt * p : 0.0;
                 const double vp = wave_sum(v * p);
                 const double w = fma(-0.5 * bt * vp, v, p);
                 if (below) {
 #pragma unroll
-                    for (int c = j + 1; c < KMAX; c++) {
+                    for (int c = j + 1; c < KM; c++) {
                         const double vc = read_lane(v, c), wc = read_lane(w, c);
                         a[c] = a[c] - __dadd_rn(__dmul_rn(v, wc), __dmul_rn(w, vc));
                     }
@@ -477,11 +481,14 @@ __device__ void tridiag_wave(double (*A)[KMAX + 1], int k, double *beta, double 
     });
     if (lane < k) {
 #pragma unroll
-        for (int c = 0; c < KMAX; c++)
+        for (int c = 0; c < KM; c++)
             if (c < k) A[r][c] = a[c];
     }
 }
 
+// KM: the register size of the unrolled steps, at least every problem's k
+// (24 covers m <= 8, 48 every block width); LDS arrays keep the KMAX layout.
+template <int KM>
 __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
     __shared__ double A[KMAX][KMAX + 1];      // lower part: reflector vectors
     __shared__ double beta[KMAX], d[KMAX], e[KMAX], ds[KMAX + 4], e2s[KMAX + 4], lam[KMAX];
@@ -534,7 +541,7 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
     // dropped for this iteration when a pivot of its column-normalised
     // projection is below P_DROP (the oracle's rank test); a second pass
     // follows when the basis was far from orthonormal.
-    if (tid < 64) wave_chol(GS, k0, Lf, scl, pvt);
+    if (tid < 64) wave_chol<KM>(GS, k0, Lf, scl, pvt);
     __syncthreads();
     if (tid == 0) {
         int k = k0;
@@ -560,14 +567,14 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
     }
     __syncthreads();
     const int k = kk;
-    tri_inverse(Lf, scl, k, Li);
+    tri_inverse<KM>(Lf, scl, k, Li);
     __syncthreads();
     if (second) {
         // Li <- L2^-1 Li with L2 L2^T = Li S^T S Li^T (Cholesky-QR twice)
         congruence(Li, GS, k, Lf, GS);
-        if (tid < 64) wave_chol(GS, k, Lf, scl, pvt);
+        if (tid < 64) wave_chol<KM>(GS, k, Lf, scl, pvt);
         __syncthreads();
-        tri_inverse(Lf, scl, k, GS);   // GS <- L2^-1 (lower)
+        tri_inverse<KM>(Lf, scl, k, GS);   // GS <- L2^-1 (lower)
         __syncthreads();
         for (int e0 = tid; e0 < k * k; e0 += 256) {
             const int i = e0 / k, j = e0 - (e0 / k) * k;
@@ -586,7 +593,7 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
     congruence(Li, A, k, Lf, A);
     // 1. tridiagonalisation, by the first wave
     __syncthreads();
-    if (tid < 64) tridiag_wave(A, k, beta, e);
+    if (tid < 64) tridiag_wave<KM>(A, k, beta, e);
     __syncthreads();
     if (tid < k) d[tid] = A[tid][tid];
     if (tid == 0) {
@@ -622,13 +629,13 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
         lo -= 1e-12 * w0 + 1e-300;
         hi += 1e-12 * w0 + 1e-300;
         const bool act = g < ne;
-        double dr[KMAX];
+        double dr[KM];
 #pragma unroll
-        for (int i = 0; i < KMAX; i++) dr[i] = ds[i];
+        for (int i = 0; i < KM; i++) dr[i] = ds[i];
         for (int round = 0; round < 64; round++) {
             const double h = (hi - lo) / (double)(NG + 1);
             const double x = fma((double)(lg + 1), h, lo);
-            const int cnt = act ? sturm_count_r(dr, e2s, x) : 0;
+            const int cnt = act ? sturm_count_r<KM>(dr, e2s, x) : 0;
             const unsigned long long bal = __ballot(act && cnt > g);
             const unsigned long long msk = (bal >> gbase) & gmask;
             if (msk == 0ull) {
@@ -827,7 +834,10 @@ void small_rr(const RRArgs *a, int count, hipStream_t s) {
         Batch<RRArgs> b;
         b.count = std::min(32, count - c0);
         for (int i = 0; i < b.count; i++) b.a[i] = a[c0 + i];
-        hipLaunchKernelGGL(k_small_rr, dim3(b.count), dim3(256), 0, s, b);
+        int kmax = 0;
+        for (int i = 0; i < b.count; i++) kmax = std::max(kmax, b.a[i].nblk * b.a[i].m);
+        if (kmax <= 24) hipLaunchKernelGGL(k_small_rr<24>, dim3(b.count), dim3(256), 0, s, b);
+        else hipLaunchKernelGGL(k_small_rr<KMAX>, dim3(b.count), dim3(256), 0, s, b);
         HIPCHK(hipGetLastError());
     }
 }
