@@ -226,6 +226,9 @@ static void build_panel(int64_t n, int64_t r0, int64_t r1, const Geom &geo, int 
     std::vector<int32_t> tr, tc;      // one tile's entries: local row, local column
     std::vector<int64_t> tp;          // and their positions in the slab
     std::vector<int32_t> colcnt((size_t)C + 1), order;
+    std::vector<uint32_t> pcode;      // one piece: codes, perm and values by position
+    std::vector<uint16_t> pperm;
+    std::vector<double> pval;
     for (int64_t g = gmin; g <= gmax; g++) {
         const int64_t cend = (g + 1) * (int64_t)C;
         tr.clear(); tc.clear(); tp.clear();
@@ -244,38 +247,30 @@ static void build_panel(int64_t n, int64_t r0, int64_t r1, const Geom &geo, int 
         const bool ext = g * (int64_t)C >= r0 + geo.R;
         if (ext) out.next++;
         // pieces of consecutive row-major entries, at most maxe positions
-        // after padding to a whole number of steps of G segments
-        const int64_t cut = (int64_t)(geo.maxe / G) * G;
+        // after padding to a whole, even number of steps of G segments
+        const int64_t cut = (int64_t)((geo.maxe / G) & ~(SPMM_STEP - 1)) * G;
         if (cut < 1) fail(HSYM_E_INVALID_ARG, "panel geometry leaves no room for a piece");
+        const int ib = geo.idx_bytes, sv = storage == HSYM_FP64 ? 8 : 4;
         for (int64_t q0 = 0; q0 < tcnt; q0 += cut) {
             const int pc = (int)std::min<int64_t>(cut, tcnt - q0);
-            const int len = (pc + G - 1) / G;
+            const int len = ((pc + G - 1) / G + SPMM_STEP - 1) / SPMM_STEP * SPMM_STEP;
             const int64_t E = (int64_t)G * len;
-            // the piece's bytes: codes (idx_bytes each), perm (2 each) and
-            // values, each part padded to a multiple of 16 bytes
-            const int ib = geo.idx_bytes, sv = storage == HSYM_FP64 ? 8 : 4;
-            const int64_t oc = 0, op = (E * ib + 15) & ~(int64_t)15, ov = op + ((E * 2 + 15) & ~(int64_t)15);
-            const int64_t bytes = ov + ((E * sv + 15) & ~(int64_t)15);
+            const PieceParts pp = piece_parts(E, ib, sv);
             const int64_t base = (int64_t)out.blob.size();
-            out.blob.resize((size_t)(base + bytes), 0);
+            out.blob.resize((size_t)(base + pp.bytes), 0);
             unsigned char *bp = out.blob.data() + base;
+            // row-major codes and values at their positions; padding positions
+            // repeat the last code with value 0
             const int64_t last = q0 + pc - 1;
             const uint32_t lastcode = ((uint32_t)tr[(size_t)last] << cb) | (uint32_t)tc[(size_t)last];
-            auto put_code = [&](int64_t at, uint32_t c) {
-                if (ib == 2) { const uint16_t h = (uint16_t)c; memcpy(bp + oc + at * 2, &h, 2); }
-                else memcpy(bp + oc + at * 4, &c, 4);
-            };
-            auto put_val = [&](int64_t at, int64_t p) {
-                if (sv == 8) { const double v = vin64 ? vin64[p] : (double)vin32[p]; memcpy(bp + ov + at * 8, &v, 8); }
-                else { const float v = vin64 ? (float)vin64[p] : vin32[p]; memcpy(bp + ov + at * 4, &v, 4); }
-            };
-            // padding positions repeat the last code with value 0
-            for (int64_t at = 0; at < E; at++) put_code(at, lastcode);
+            pcode.assign((size_t)E, lastcode);
+            pval.assign((size_t)E, 0.0);
             for (int64_t q = 0; q < pc; q++) {
                 const int64_t at = (q % len) * G + q / len;
                 const int64_t k = q0 + q;
-                put_code(at, ((uint32_t)tr[(size_t)k] << cb) | (uint32_t)tc[(size_t)k]);
-                put_val(at, tp[(size_t)k]);
+                pcode[(size_t)at] = ((uint32_t)tr[(size_t)k] << cb) | (uint32_t)tc[(size_t)k];
+                const int64_t p = tp[(size_t)k];
+                pval[(size_t)at] = vin64 ? vin64[p] : (double)vin32[p];
             }
             // column-major order of the piece (a stable counting sort by
             // column keeps rows ascending within a column)
@@ -287,15 +282,32 @@ static void build_panel(int64_t n, int64_t r0, int64_t r1, const Geom &geo, int 
             // padding positions of the column order point at a padding
             // position of the row order (value 0), which exists when E > pc
             const int64_t padpos = E > pc ? ((int64_t)pc % len) * G + pc / len : 0;
-            for (int64_t q = 0; q < E; q++) {
-                const int64_t at = (q % len) * G + q / len;
-                int64_t src = padpos;
-                if (q < pc) {
-                    const int64_t o = order[(size_t)q];
-                    src = (o % len) * G + o / len;
+            pperm.assign((size_t)E, (uint16_t)padpos);
+            for (int64_t q = 0; q < pc; q++) {
+                const int64_t o = order[(size_t)q];
+                pperm[(size_t)((q % len) * G + q / len)] = (uint16_t)((o % len) * G + o / len);
+            }
+            // the piece's bytes (piece_parts)
+            for (int64_t at = 0; at < E; at++) {
+                const uint32_t c = pcode[(size_t)at];
+                const uint16_t pm = pperm[(size_t)at];
+                const double v = pval[(size_t)at];
+                if (ib == 2) {
+                    const uint32_t w = c << 16 | pm;
+                    if (sv == 4) {
+                        const float f = (float)v;
+                        memcpy(bp + at * 8, &w, 4);
+                        memcpy(bp + at * 8 + 4, &f, 4);
+                    } else {
+                        memcpy(bp + at * 4, &w, 4);
+                        memcpy(bp + pp.val + at * 8, &v, 8);
+                    }
+                } else {
+                    memcpy(bp + at * 4, &c, 4);
+                    memcpy(bp + pp.perm + at * 2, &pm, 2);
+                    if (sv == 8) memcpy(bp + pp.val + at * 8, &v, 8);
+                    else { const float f = (float)v; memcpy(bp + pp.val + at * 4, &f, 4); }
                 }
-                const uint16_t h = (uint16_t)src;
-                memcpy(bp + op + at * 2, &h, 2);
             }
             out.positions += E;
             TileDesc td;

@@ -50,21 +50,47 @@ void check_hip(hipError_t e, const char *what);
 // chunks of C columns (C a power of two dividing R).  The strictly-upper
 // entries of one panel that fall into one chunk form a tile; a tile with more
 // than MAXE entries is cut into pieces of consecutive entries.  A piece of cnt
-// entries is padded to E = G * len positions and stored as one contiguous run
-// of bytes (16-byte aligned) holding three parts, each padded to 16 bytes:
-//   - codes: local row << cb | local column (cb = log2 C), 16-bit when
-//     R * C <= 2^16, else 32-bit, in row-major order (rows ascending, columns
-//     ascending within a row), cut into G equal segments: entry q of the
-//     row-major order is segment q / len, step q % len, and sits at position
-//     step * G + segment;
-//   - perm (16-bit): the column-major order of the same entries, cut into G
-//     segments the same way; each position holds the position of the entry in
-//     the code and value parts;
-//   - values (T), at the positions of their codes.
-// Padding positions repeat the code of the piece's last entry with value 0.
+// entries is padded to E = G * len positions (len even) and stored as one
+// contiguous run of bytes (16-byte aligned).  Its entries are known in two
+// orders, each cut into G segments of len steps, step s of segment g sitting
+// at position s * G + g:
+//   - the row-major order (rows ascending, columns ascending within a row),
+//     which holds the entries themselves: their code, local row << cb | local
+//     column (cb = log2 C), and their value (T);
+//   - the column-major order, as a perm: at each position the position of the
+//     entry in the row-major order.
+// With 16-bit codes (R * C <= 2^16) code and perm share one 32-bit word,
+// code << 16 | perm (the perm at the same position, not of the same entry):
+// fp32 values sit next to their word in 8-byte records; fp64 values follow
+// the words (a part of their own).  With 32-bit codes the codes, the perm
+// (16-bit) and the values are three parts.  Every part starts on 16 bytes
+// (piece_parts).  Padding positions repeat the code of the piece's last entry
+// with value 0.
 // A tile is "own" when its chunk lies inside the panel (its transposed half
 // lands in the panel's rows) and "external" otherwise.
 // ---------------------------------------------------------------------------
+// steps per segment are a multiple of this (the SpMM takes two per batch)
+constexpr int SPMM_STEP = 2;
+struct PieceParts {
+    int64_t perm;    // byte offset of the perm part (32-bit codes), else 0
+    int64_t val;     // byte offset of the first value
+    int64_t bytes;   // bytes of the piece (a multiple of 16)
+};
+__host__ __device__ inline PieceParts piece_parts(int64_t E, int idx_bytes, int val_bytes) {
+    PieceParts p;
+    const int64_t w16 = (4 * E + 15) & ~(int64_t)15;
+    if (idx_bytes == 2 && val_bytes == 4) {
+        p.perm = 0; p.val = 4; p.bytes = 8 * E;
+    } else if (idx_bytes == 2) {
+        p.perm = 0; p.val = w16; p.bytes = w16 + 8 * E;
+    } else {
+        p.perm = w16;
+        p.val = w16 + ((2 * E + 15) & ~(int64_t)15);
+        p.bytes = p.val + ((E * val_bytes + 15) & ~(int64_t)15);
+    }
+    return p;
+}
+
 struct TileDesc {
     int64_t base;          // first byte of the piece (a multiple of 16)
     int32_t len;           // steps per segment

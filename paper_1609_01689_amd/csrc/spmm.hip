@@ -102,6 +102,60 @@ __device__ __forceinline__ void y_add(YT *p, double v) {
     unsafeAtomicAdd(p, (YT)v);
 }
 
+// Reads of a staged piece in LDS (the three layouts of the piece format):
+// entry(e) gives the word holding the code of row-major position e (the code
+// sits CS bits up) and its value; perm(k) the row-major position of the
+// column-major position k.
+template <typename T, typename IT>
+struct Staged;
+template <>
+struct Staged<float, uint16_t> {   // 8-byte records {code << 16 | perm, value}
+    static constexpr int CS = 16;
+    const uint2 *rec;
+    __device__ Staged(const unsigned char *s, int) : rec(reinterpret_cast<const uint2 *>(s)) {}
+    __device__ __forceinline__ void entry(int e, uint32_t &w, float &v) const {
+        const uint2 r = rec[e];
+        w = r.x;
+        v = __uint_as_float(r.y);
+    }
+    __device__ __forceinline__ uint32_t word(int e) const { return rec[e].x; }
+    __device__ __forceinline__ int perm(int k) const { return (int)(rec[k].x & 0xFFFFu); }
+};
+template <>
+struct Staged<double, uint16_t> {  // words code << 16 | perm, then the values
+    static constexpr int CS = 16;
+    const uint32_t *wd;
+    const double *val;
+    __device__ Staged(const unsigned char *s, int E)
+        : wd(reinterpret_cast<const uint32_t *>(s)),
+          val(reinterpret_cast<const double *>(s + piece_parts(E, 2, 8).val)) {}
+    __device__ __forceinline__ void entry(int e, uint32_t &w, double &v) const {
+        w = wd[e];
+        v = val[e];
+    }
+    __device__ __forceinline__ uint32_t word(int e) const { return wd[e]; }
+    __device__ __forceinline__ int perm(int k) const { return (int)(wd[k] & 0xFFFFu); }
+};
+template <typename T>
+struct Staged<T, uint32_t> {       // codes, perm (16-bit), values
+    static constexpr int CS = 0;
+    const uint32_t *code;
+    const uint16_t *pm;
+    const T *val;
+    __device__ Staged(const unsigned char *s, int E) {
+        const PieceParts pp = piece_parts(E, 4, (int)sizeof(T));
+        code = reinterpret_cast<const uint32_t *>(s);
+        pm = reinterpret_cast<const uint16_t *>(s + pp.perm);
+        val = reinterpret_cast<const T *>(s + pp.val);
+    }
+    __device__ __forceinline__ void entry(int e, uint32_t &w, T &v) const {
+        w = code[e];
+        v = val[e];
+    }
+    __device__ __forceinline__ uint32_t word(int e) const { return code[e]; }
+    __device__ __forceinline__ int perm(int k) const { return (int)pm[k]; }
+};
+
 // Load a piece into registers: 16-byte units of its bytes (thread tid takes
 // units tid, tid + 1024, ...), and the X chunk of an external tile's first
 // piece (element i = tid + k * 1024 of the C x M chunk).
@@ -141,8 +195,8 @@ template <int M, typename T, typename A, typename XT, typename YT, typename IT, 
 __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, unsigned char *smem) {
     using Ly = Lay<M, A>;
     constexpr int MW = Ly::MW, L = Ly::L, GK = Ly::GK, SA = Ly::SA;
-    constexpr int IB = (int)sizeof(IT), SV = (int)sizeof(T), U = 2;
-    const int R = a.g.R, C = a.g.C, G = a.g.G, cb = a.g.cb, maxe = a.g.maxe, m = a.m;
+    constexpr int IB = (int)sizeof(IT), SV = (int)sizeof(T);
+    const int R = a.g.R, C = a.g.C, G = a.g.G, cb = a.g.cb, m = a.m;
     const uint32_t cm = (uint32_t)C - 1u;
     const int tid = threadIdx.x, grp = tid / L, q = tid - grp * L;
     // LDS layout (byte offsets): acc, ts (fp64), xp, xs (A), codes, perm, values
@@ -154,13 +208,8 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
     // the staged piece: its bytes as stored (codes, perm, values; the offsets
     // of the last two depend on the piece's size)
     unsigned char *stg = smem + (size_t)(R + C) * ((size_t)M * 8 + (size_t)XS * SA);
-    (void)maxe;
-    auto parts = [&](int len, int &op, int &ov, int &nunits) {
-        const int E = G * len;
-        op = (E * IB + 15) & ~15;
-        ov = op + ((E * 2 + 15) & ~15);
-        nunits = (ov + ((E * SV + 15) & ~15)) >> 4;
-    };
+    // 16-byte units of a piece of len steps
+    auto units = [&](int len) { return (int)(piece_parts((int64_t)G * len, IB, SV).bytes >> 4); };
 
     const XT *X = reinterpret_cast<const XT *>(a.X);
     YT *Y = reinterpret_cast<YT *>(a.Y);
@@ -203,9 +252,7 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
     TileDesc tdc{}, tdn{};
     if (t0 < t1) {
         tdc = tile_at(t0);
-        int op0, ov0, nu0;
-        parts(tdc.len, op0, ov0, nu0);
-        spmm_fetch<M, XT, KU>(a, tdc, nu0, su0, su1, su2, su3, su4, su5, su6, su7, xr0, xr1, xr2, xr3);
+        spmm_fetch<M, XT, KU>(a, tdc, units(tdc.len), su0, su1, su2, su3, su4, su5, su6, su7, xr0, xr1, xr2, xr3);
         if (t0 + 1 < t1) tdn = tile_at(t0 + 1);
     }
 
@@ -234,8 +281,7 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
         }
         const int len = td.len;
         const int64_t col0 = (int64_t)td.chunk * C;
-        int op, ov, nunits;
-        parts(len, op, ov, nunits);
+        const int nunits = units(len);
         {
             uint4 *sdst = reinterpret_cast<uint4 *>(stg);
             if (tid < nunits) sdst[tid] = su0;
@@ -260,49 +306,48 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
             }
         }
         if (t + 1 < t1) {
-            int opn, ovn, nun;
-            parts(tdn.len, opn, ovn, nun);
-            spmm_fetch<M, XT, KU>(a, tdn, nun, su0, su1, su2, su3, su4, su5, su6, su7, xr0, xr1, xr2, xr3);
+            spmm_fetch<M, XT, KU>(a, tdn, units(tdn.len), su0, su1, su2, su3, su4, su5, su6, su7, xr0, xr1, xr2, xr3);
             tdc = tdn;
             if (t + 2 < t1) tdn = tile_at(t + 2);
         }
         __syncthreads();
 
-        const IT *scode = reinterpret_cast<const IT *>(stg);
-        const uint16_t *sperm = reinterpret_cast<const uint16_t *>(stg + op);
-        const T *sval = reinterpret_cast<const T *>(stg + ov);
+        const Staged<T, IT> sp(stg, G * len);
+        constexpr int CS = Staged<T, IT>::CS;
+        const int rs = CS + cb;   // the local row sits rs bits up in a word
+        static_assert(SPMM_STEP == 2, "the passes take two steps per batch");
         // row pass: U X
         {
             const A *xsrc = td.ext ? xs : xp + (size_t)(col0 - row0) * XS;
             for (int seg = grp; seg < G; seg += GK) {
-                int cur = -1;
                 A ra[MW];
 #pragma unroll
                 for (int j = 0; j < MW; j++) ra[j] = (A)0;
-                for (int s0 = 0; s0 < len; s0 += U) {
-                    uint32_t w[U];
-                    A av[U], xv[U][MW];
+                int cur = (int)(sp.word(seg) >> rs);
+                for (int e = seg, s0 = 0; s0 < len; s0 += 2, e += 2 * G) {
+                    uint32_t w[2];
+                    A av[2], xv[2][MW];
 #pragma unroll
-                    for (int u = 0; u < U; u++) {
-                        const int s = s0 + u < len ? s0 + u : len - 1;
-                        const int e = s * G + seg;
-                        w[u] = (uint32_t)scode[e];
-                        av[u] = s0 + u < len ? (A)sval[e] : (A)0;
+                    for (int u = 0; u < 2; u++) {
+                        T v;
+                        sp.entry(e + u * G, w[u], v);
+                        av[u] = (A)v;
                     }
 #pragma unroll
-                    for (int u = 0; u < U; u++) lds_get<MW, A>(xsrc + (size_t)(w[u] & cm) * XS + q * MW, xv[u]);
+                    for (int u = 0; u < 2; u++)
+                        lds_get<MW, A>(xsrc + (size_t)((w[u] >> CS) & cm) * XS + q * MW, xv[u]);
 #pragma unroll
-                    for (int u = 0; u < U; u++) {
-                        const int r = (int)(w[u] >> cb);
+                    for (int u = 0; u < 2; u++) {
+                        const int r = (int)(w[u] >> rs);
                         if (r != cur) {
-                            if (cur >= 0) run_flush<MW, A>(acc + (size_t)cur * M + q * MW, ra);
+                            run_flush<MW, A>(acc + (size_t)cur * M + q * MW, ra);
                             cur = r;
                         }
 #pragma unroll
                         for (int j = 0; j < MW; j++) ra[j] = fma(av[u], xv[u][j], ra[j]);
                     }
                 }
-                if (cur >= 0) run_flush<MW, A>(acc + (size_t)cur * M + q * MW, ra);
+                run_flush<MW, A>(acc + (size_t)cur * M + q * MW, ra);
             }
         }
         // column pass: U^T X, into the chunk accumulator (external tile) or
@@ -310,38 +355,36 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
         {
             double *tgt = td.ext ? ts : acc + (size_t)(col0 - row0) * M;
             for (int seg = grp; seg < G; seg += GK) {
-                int cur = -1;
                 A ca[MW];
 #pragma unroll
                 for (int j = 0; j < MW; j++) ca[j] = (A)0;
-                for (int s0 = 0; s0 < len; s0 += U) {
-                    int pe[U];
-                    uint32_t w[U];
-                    A av[U], xv[U][MW];
+                int cur = (int)((sp.word(sp.perm(seg)) >> CS) & cm);
+                for (int k = seg, s0 = 0; s0 < len; s0 += 2, k += 2 * G) {
+                    int pe[2];
+                    uint32_t w[2];
+                    A av[2], xv[2][MW];
 #pragma unroll
-                    for (int u = 0; u < U; u++) {
-                        const int s = s0 + u < len ? s0 + u : len - 1;
-                        pe[u] = (int)sperm[s * G + seg];
+                    for (int u = 0; u < 2; u++) pe[u] = sp.perm(k + u * G);
+#pragma unroll
+                    for (int u = 0; u < 2; u++) {
+                        T v;
+                        sp.entry(pe[u], w[u], v);
+                        av[u] = (A)v;
                     }
 #pragma unroll
-                    for (int u = 0; u < U; u++) {
-                        w[u] = (uint32_t)scode[pe[u]];
-                        av[u] = s0 + u < len ? (A)sval[pe[u]] : (A)0;
-                    }
+                    for (int u = 0; u < 2; u++) lds_get<MW, A>(xp + (size_t)(w[u] >> rs) * XS + q * MW, xv[u]);
 #pragma unroll
-                    for (int u = 0; u < U; u++) lds_get<MW, A>(xp + (size_t)(w[u] >> cb) * XS + q * MW, xv[u]);
-#pragma unroll
-                    for (int u = 0; u < U; u++) {
-                        const int c = (int)(w[u] & cm);
+                    for (int u = 0; u < 2; u++) {
+                        const int c = (int)((w[u] >> CS) & cm);
                         if (c != cur) {
-                            if (cur >= 0) run_flush<MW, A>(tgt + (size_t)cur * M + q * MW, ca);
+                            run_flush<MW, A>(tgt + (size_t)cur * M + q * MW, ca);
                             cur = c;
                         }
 #pragma unroll
                         for (int j = 0; j < MW; j++) ca[j] = fma(av[u], xv[u][j], ca[j]);
                     }
                 }
-                if (cur >= 0) run_flush<MW, A>(tgt + (size_t)cur * M + q * MW, ca);
+                run_flush<MW, A>(tgt + (size_t)cur * M + q * MW, ca);
             }
         }
         __syncthreads();
@@ -419,7 +462,7 @@ static int check_fit(int storage, int m, const Geom &g) {
     if ((size_t)g.C * M > (size_t)SPMM_XE * SPMM_NT)
         fail(HSYM_E_UNSUPPORTED, "chunk too wide for this block width");
     const int64_t e = g.maxe, sv = storage == HSYM_FP64 ? 8 : 4;
-    const int64_t bytes = ((e * g.idx_bytes + 15) & ~15) + ((e * 2 + 15) & ~15) + ((e * sv + 15) & ~15);
+    const int64_t bytes = piece_parts(e, g.idx_bytes, (int)sv).bytes;
     const int64_t units = (bytes / 16 + SPMM_NT - 1) / SPMM_NT;
     if (units > 8) fail(HSYM_E_UNSUPPORTED, "pieces too large for the staging registers");
     return units > 4 ? 8 : 4;

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -135,18 +136,16 @@ static void replay(const hsym_matrix *H, const std::vector<double> &X, int m, st
             const TileDesc td = dt.tiles[t];
             const int64_t E = (int64_t)g.G * td.len;
             const int64_t col0 = (int64_t)td.chunk * g.C;
-            const int64_t op = (E * (int64_t)sizeof(IT) + 15) & ~(int64_t)15;
-            const int64_t ov = op + ((E * 2 + 15) & ~(int64_t)15);
-            const int64_t bytes = ov + ((E * (int64_t)sizeof(T) + 15) & ~(int64_t)15);
+            const PieceParts pp = piece_parts(E, (int)sizeof(IT), (int)sizeof(T));
+            const int64_t bytes = pp.bytes;
             REQUIRE(td.base % 16 == 0, "piece base %ld not a multiple of 16", (long)td.base);
-            REQUIRE(td.len >= 1 && E <= g.maxe, "piece of %ld positions exceeds %d", (long)E, g.maxe);
+            REQUIRE(td.len >= 1 && td.len % SPMM_STEP == 0 && E <= g.maxe, "piece of %ld positions (%d steps) exceeds %d",
+                    (long)E, td.len, g.maxe);
             REQUIRE(td.base + bytes <= total, "piece at %ld overruns the stream", (long)td.base);
             REQUIRE(td.ext == (col0 >= row0 + g.R ? 1 : 0), "external flag of chunk %d in panel %ld", td.chunk, (long)p);
             REQUIRE(col0 >= row0 && col0 < n, "chunk %d outside the panel's column range", td.chunk);
             if (!(td.base % 16 == 0 && E <= g.maxe && td.base + bytes <= total)) return;
-            const IT *idx = (const IT *)(dt.blob + td.base);
-            const uint16_t *pm = (const uint16_t *)(dt.blob + td.base + op);
-            const T *vals = (const T *)(dt.blob + td.base + ov);
+            const unsigned char *pb = dt.blob + td.base;
             if (td.flags & TILE_FIRST) {
                 REQUIRE(!open_ext, "first piece inside an open tile");
                 if (td.ext) {
@@ -164,9 +163,23 @@ static void replay(const hsym_matrix *H, const std::vector<double> &X, int m, st
             std::vector<T> sv((size_t)E);
             std::vector<int> hits((size_t)E, 0);
             for (int64_t e = 0; e < E; e++) {
-                sc[(size_t)e] = (uint32_t)idx[e];
-                sp[(size_t)e] = pm[e];
-                sv[(size_t)e] = vals[e];
+                // the layouts of the piece format: 16-bit codes share a word
+                // (code << 16 | perm) with the perm, fp32 values sit next to it
+                if (sizeof(IT) == 2) {
+                    uint32_t w;
+                    std::memcpy(&w, pb + (sizeof(T) == 4 ? 8 : 4) * e, 4);
+                    sc[(size_t)e] = w >> 16;
+                    sp[(size_t)e] = (int)(w & 0xFFFFu);
+                } else {
+                    uint32_t c;
+                    uint16_t pm;
+                    std::memcpy(&c, pb + 4 * e, 4);
+                    std::memcpy(&pm, pb + pp.perm + 2 * e, 2);
+                    sc[(size_t)e] = c;
+                    sp[(size_t)e] = pm;
+                }
+                std::memcpy(&sv[(size_t)e], pb + pp.val + (sizeof(IT) == 2 && sizeof(T) == 4 ? 8 : sizeof(T)) * e,
+                            sizeof(T));
                 const int r = (int)(sc[(size_t)e] >> g.cb), c = (int)(sc[(size_t)e] & (g.C - 1));
                 REQUIRE(r < nrow && col0 + c < n && col0 + c > row0 + r, "code %u outside the tile", sc[(size_t)e]);
                 REQUIRE(sp[(size_t)e] < E, "perm %d outside the piece", sp[(size_t)e]);
