@@ -266,7 +266,7 @@ static void build_panel(int64_t n, int64_t r0, int64_t r1, const Geom &geo, int 
             pcode.assign((size_t)E, lastcode);
             pval.assign((size_t)E, 0.0);
             for (int64_t q = 0; q < pc; q++) {
-                const int64_t at = (q % len) * G + q / len;
+                const int64_t at = piece_pos(q % len, q / len, G);
                 const int64_t k = q0 + q;
                 pcode[(size_t)at] = ((uint32_t)tr[(size_t)k] << cb) | (uint32_t)tc[(size_t)k];
                 const int64_t p = tp[(size_t)k];
@@ -281,11 +281,11 @@ static void build_panel(int64_t n, int64_t r0, int64_t r1, const Geom &geo, int 
             for (int q = 0; q < pc; q++) order[(size_t)colcnt[(size_t)tc[(size_t)(q0 + q)]]++] = q;
             // padding positions of the column order point at a padding
             // position of the row order (value 0), which exists when E > pc
-            const int64_t padpos = E > pc ? ((int64_t)pc % len) * G + pc / len : 0;
+            const int64_t padpos = E > pc ? piece_pos(pc % len, pc / len, G) : 0;
             pperm.assign((size_t)E, (uint16_t)padpos);
             for (int64_t q = 0; q < pc; q++) {
                 const int64_t o = order[(size_t)q];
-                pperm[(size_t)((q % len) * G + q / len)] = (uint16_t)((o % len) * G + o / len);
+                pperm[(size_t)piece_pos(q % len, q / len, G)] = (uint16_t)piece_pos(o % len, o / len, G);
             }
             // the piece's bytes (piece_parts)
             for (int64_t at = 0; at < E; at++) {

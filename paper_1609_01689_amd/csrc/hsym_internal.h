@@ -52,8 +52,9 @@ void check_hip(hipError_t e, const char *what);
 // than MAXE entries is cut into pieces of consecutive entries.  A piece of cnt
 // entries is padded to E = G * len positions (len even) and stored as one
 // contiguous run of bytes (16-byte aligned).  Its entries are known in two
-// orders, each cut into G segments of len steps, step s of segment g sitting
-// at position s * G + g:
+// orders, each cut into G segments of len steps, the two steps 2t and 2t + 1
+// of segment g sitting next to each other at positions 2tG + 2g and
+// 2tG + 2g + 1 (piece_pos):
 //   - the row-major order (rows ascending, columns ascending within a row),
 //     which holds the entries themselves: their code, local row << cb | local
 //     column (cb = log2 C), and their value (T);
@@ -71,6 +72,10 @@ void check_hip(hipError_t e, const char *what);
 // ---------------------------------------------------------------------------
 // steps per segment are a multiple of this (the SpMM takes two per batch)
 constexpr int SPMM_STEP = 2;
+// position of step s of segment g in a piece of G segments
+__host__ __device__ inline int64_t piece_pos(int64_t s, int64_t g, int64_t G) {
+    return (s >> 1) * 2 * G + 2 * g + (s & 1);
+}
 struct PieceParts {
     int64_t perm;    // byte offset of the perm part (32-bit codes), else 0
     int64_t val;     // byte offset of the first value

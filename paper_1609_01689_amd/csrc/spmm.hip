@@ -103,9 +103,10 @@ __device__ __forceinline__ void y_add(YT *p, double v) {
 }
 
 // Reads of a staged piece in LDS (the three layouts of the piece format):
-// entry(e) gives the word holding the code of row-major position e (the code
-// sits CS bits up) and its value; perm(k) the row-major position of the
-// column-major position k.
+// entry2(e) gives the words holding the codes of row-major positions e and
+// e + 1 (e even; the code sits CS bits up in a word) and their values;
+// perm2(k) the row-major positions of column-major positions k and k + 1;
+// word(e) the word of one position.
 template <typename T, typename IT>
 struct Staged;
 template <>
@@ -113,13 +114,21 @@ struct Staged<float, uint16_t> {   // 8-byte records {code << 16 | perm, value}
     static constexpr int CS = 16;
     const uint2 *rec;
     __device__ Staged(const unsigned char *s, int) : rec(reinterpret_cast<const uint2 *>(s)) {}
+    __device__ __forceinline__ void entry2(int e, uint32_t *w, float *v) const {
+        const uint4 r = *reinterpret_cast<const uint4 *>(rec + e);
+        w[0] = r.x; v[0] = __uint_as_float(r.y);
+        w[1] = r.z; v[1] = __uint_as_float(r.w);
+    }
     __device__ __forceinline__ void entry(int e, uint32_t &w, float &v) const {
         const uint2 r = rec[e];
         w = r.x;
         v = __uint_as_float(r.y);
     }
     __device__ __forceinline__ uint32_t word(int e) const { return rec[e].x; }
-    __device__ __forceinline__ int perm(int k) const { return (int)(rec[k].x & 0xFFFFu); }
+    __device__ __forceinline__ void perm2(int k, int *p) const {
+        p[0] = (int)(rec[k].x & 0xFFFFu);
+        p[1] = (int)(rec[k + 1].x & 0xFFFFu);
+    }
 };
 template <>
 struct Staged<double, uint16_t> {  // words code << 16 | perm, then the values
@@ -129,12 +138,22 @@ struct Staged<double, uint16_t> {  // words code << 16 | perm, then the values
     __device__ Staged(const unsigned char *s, int E)
         : wd(reinterpret_cast<const uint32_t *>(s)),
           val(reinterpret_cast<const double *>(s + piece_parts(E, 2, 8).val)) {}
+    __device__ __forceinline__ void entry2(int e, uint32_t *w, double *v) const {
+        const uint2 r = *reinterpret_cast<const uint2 *>(wd + e);
+        const double2 d = *reinterpret_cast<const double2 *>(val + e);
+        w[0] = r.x; w[1] = r.y;
+        v[0] = d.x; v[1] = d.y;
+    }
     __device__ __forceinline__ void entry(int e, uint32_t &w, double &v) const {
         w = wd[e];
         v = val[e];
     }
     __device__ __forceinline__ uint32_t word(int e) const { return wd[e]; }
-    __device__ __forceinline__ int perm(int k) const { return (int)(wd[k] & 0xFFFFu); }
+    __device__ __forceinline__ void perm2(int k, int *p) const {
+        const uint2 r = *reinterpret_cast<const uint2 *>(wd + k);
+        p[0] = (int)(r.x & 0xFFFFu);
+        p[1] = (int)(r.y & 0xFFFFu);
+    }
 };
 template <typename T>
 struct Staged<T, uint32_t> {       // codes, perm (16-bit), values
@@ -148,12 +167,21 @@ struct Staged<T, uint32_t> {       // codes, perm (16-bit), values
         pm = reinterpret_cast<const uint16_t *>(s + pp.perm);
         val = reinterpret_cast<const T *>(s + pp.val);
     }
+    __device__ __forceinline__ void entry2(int e, uint32_t *w, T *v) const {
+        const uint2 r = *reinterpret_cast<const uint2 *>(code + e);
+        w[0] = r.x; w[1] = r.y;
+        v[0] = val[e]; v[1] = val[e + 1];
+    }
     __device__ __forceinline__ void entry(int e, uint32_t &w, T &v) const {
         w = code[e];
         v = val[e];
     }
     __device__ __forceinline__ uint32_t word(int e) const { return code[e]; }
-    __device__ __forceinline__ int perm(int k) const { return (int)pm[k]; }
+    __device__ __forceinline__ void perm2(int k, int *p) const {
+        const uint32_t r = *reinterpret_cast<const uint32_t *>(pm + k);
+        p[0] = (int)(r & 0xFFFFu);
+        p[1] = (int)(r >> 16);
+    }
 };
 
 // Load a piece into registers: 16-byte units of its bytes (thread tid takes
@@ -323,16 +351,14 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
                 A ra[MW];
 #pragma unroll
                 for (int j = 0; j < MW; j++) ra[j] = (A)0;
-                int cur = (int)(sp.word(seg) >> rs);
-                for (int e = seg, s0 = 0; s0 < len; s0 += 2, e += 2 * G) {
+                int cur = (int)(sp.word(2 * seg) >> rs);
+                for (int e = 2 * seg, s0 = 0; s0 < len; s0 += 2, e += 2 * G) {
                     uint32_t w[2];
+                    T v[2];
                     A av[2], xv[2][MW];
+                    sp.entry2(e, w, v);
 #pragma unroll
-                    for (int u = 0; u < 2; u++) {
-                        T v;
-                        sp.entry(e + u * G, w[u], v);
-                        av[u] = (A)v;
-                    }
+                    for (int u = 0; u < 2; u++) av[u] = (A)v[u];
 #pragma unroll
                     for (int u = 0; u < 2; u++)
                         lds_get<MW, A>(xsrc + (size_t)((w[u] >> CS) & cm) * XS + q * MW, xv[u]);
@@ -358,13 +384,17 @@ __device__ __forceinline__ void spmm_panel_body(const SpmmArgs &a, int64_t blk, 
                 A ca[MW];
 #pragma unroll
                 for (int j = 0; j < MW; j++) ca[j] = (A)0;
-                int cur = (int)((sp.word(sp.perm(seg)) >> CS) & cm);
-                for (int k = seg, s0 = 0; s0 < len; s0 += 2, k += 2 * G) {
+                int cur;
+                {
+                    int p0[2];
+                    sp.perm2(2 * seg, p0);
+                    cur = (int)((sp.word(p0[0]) >> CS) & cm);
+                }
+                for (int k = 2 * seg, s0 = 0; s0 < len; s0 += 2, k += 2 * G) {
                     int pe[2];
                     uint32_t w[2];
                     A av[2], xv[2][MW];
-#pragma unroll
-                    for (int u = 0; u < 2; u++) pe[u] = sp.perm(k + u * G);
+                    sp.perm2(k, pe);
 #pragma unroll
                     for (int u = 0; u < 2; u++) {
                         T v;

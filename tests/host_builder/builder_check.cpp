@@ -193,7 +193,7 @@ static void replay(const hsym_matrix *H, const std::vector<double> &X, int m, st
                 int cur = -1;
                 std::vector<A_t> ra((size_t)M, (A_t)0);
                 for (int s = 0; s < td.len; s++) {
-                    const int64_t e = (int64_t)s * g.G + seg;
+                    const int64_t e = piece_pos(s, seg, g.G);
                     const int r = (int)(sc[(size_t)e] >> g.cb), c = (int)(sc[(size_t)e] & (g.C - 1));
                     if (r != cur) {
                         if (cur >= 0)
@@ -214,7 +214,7 @@ static void replay(const hsym_matrix *H, const std::vector<double> &X, int m, st
                 std::vector<A_t> ca((size_t)M, (A_t)0);
                 for (int s = 0; s < td.len; s++) {
                     const int64_t q = (int64_t)seg * td.len + s;   // position in the column order
-                    const int pe = sp[(size_t)((int64_t)s * g.G + seg)];
+                    const int pe = sp[(size_t)piece_pos(s, seg, g.G)];
                     const int r = (int)(sc[(size_t)pe] >> g.cb), c = (int)(sc[(size_t)pe] & (g.C - 1));
                     if (sv[(size_t)pe] != (T)0) {
                         REQUIRE(c > prevc || (c == prevc && r > prevr), "column order broken at %ld", (long)q);
