@@ -77,7 +77,10 @@ enum hsym_precond { HSYM_PRECOND_NONE = 0, HSYM_PRECOND_JACOBI = 1, HSYM_PRECOND
 #define HSYM_GEOM_M(m) (((m) & 0xff) << 8)
 /* Explicit panel geometry: R = 64 * r64 panel rows (1 <= r64 <= 255) and
  * C = 2^lc chunk columns (3 <= lc <= 12, C dividing R), in bits 16..27
- * (0 = chosen from the block width hint and n).  hsym_create fails with
+ * (0 = chosen from the block width hint, n and the first rows given: the
+ * tallest panels whose pieces fit the LDS with room to spare, or shorter ones
+ * whose larger pieces keep the tiles of those rows whole, whichever the
+ * library's cost model of the SpMM prefers).  hsym_create fails with
  * HSYM_E_INVALID_ARG when C does not divide R or the geometry does not fit
  * the LDS at the hinted block width; spmm_sym fails with HSYM_E_UNSUPPORTED
  * when it does not fit at the requested width.  hsym_autotune_geometry
@@ -179,7 +182,8 @@ int spmm_sym_f32(hsym_t H, int m, const float *X, int64_t ldx, float *Y, int64_t
  * same host CSR as hsym_create and a block width m.  It builds a row sample of
  * H (sample_rows rows around the middle, <= 0 for min(n, 262144); entries whose
  * column leaves the sample are dropped) once per candidate panel geometry
- * (R = 256..4096 rows, C = R/8, R/4, R/2 columns, those whose LDS footprint at
+ * (R = 256..448 rows in steps of 64, 512..960 in steps of 128, 1024..2048 in
+ * steps of 256; C = 64 or 128 columns dividing R; those whose LDS footprint at
  * width m fits 160 KB), times spmm_sym on it (3 warm-up calls, then 5 calls
  * between HIP events on a private stream) and returns in *out_flags the
  * HSYM_GEOM_M(m) | HSYM_GEOM_PANEL(..) flags of the fastest, to be or-ed into

@@ -321,6 +321,64 @@ static void build_panel(int64_t n, int64_t r0, int64_t r1, const Geom &geo, int 
     }
 }
 
+// Pieces and tiles of the strictly-upper entries of rows [0, rows) under a
+// geometry (only panels wholly inside the rows are counted).
+static void count_tiles(const Geom &g, int64_t n, int64_t rows, const int64_t *rp, const int32_t *ci,
+                        int64_t &pieces, int64_t &tiles) {
+    pieces = tiles = 0;
+    const int64_t cut = (int64_t)((g.maxe / g.G) & ~(SPMM_STEP - 1)) * g.G;
+    if (cut < 1) return;
+    std::vector<int32_t> cnt((size_t)((n + g.C - 1) / g.C), 0);
+    std::vector<int64_t> touched;
+    for (int64_t p = 0; (p + 1) * g.R <= rows; p++) {
+        touched.clear();
+        for (int64_t r = p * g.R; r < (p + 1) * g.R; r++)
+            for (int64_t q = rp[r]; q < rp[r + 1]; q++) {
+                if (ci[q] <= r || ci[q] >= n) continue;   // the panel builder reports bad columns
+                const int64_t c = ci[q] / g.C;
+                if (cnt[(size_t)c]++ == 0) touched.push_back(c);
+            }
+        for (int64_t c : touched) {
+            tiles++;
+            pieces += (cnt[(size_t)c] + cut - 1) / cut;
+            cnt[(size_t)c] = 0;
+        }
+    }
+}
+
+// Panel geometry from the first rows of the matrix when none was given: the
+// default rule's (geometry_for), or the tallest shorter panels with the same
+// chunks whose pieces hold at least 1.5 times as many entries, when on these
+// rows the taller panels cut enough tiles into several pieces.  In the SpMM a
+// piece costs about twice a tile (the per-piece staging and barriers against
+// the X chunk and transposed sums of an external tile; measured on CI-shaped
+// matrices of 2 * 10^6 rows with 150 to 800 entries per row, fp32 storage,
+// m = 16), so the shorter panels are taken when
+// 2 * (pieces_tall - pieces_short) > tiles_short - tiles_tall.
+static Geom choose_geometry(int storage, int m, int64_t n, int64_t rows, const int64_t *rp, const int32_t *ci) {
+    const Geom a = geometry_for(storage, m, n, 0, 0);
+    const int64_t sample = std::min<int64_t>(rows, 131072);
+    Geom b;
+    bool have_b = false;
+    for (int R = a.R - a.C; R >= a.C && !have_b; R -= a.C) {
+        if (R % 64) continue;
+        try {
+            b = geometry_for(storage, m, n, R / 64, a.cb);
+        } catch (Error &) {
+            continue;
+        }
+        have_b = 2 * (int64_t)b.maxe >= 3 * (int64_t)a.maxe;
+    }
+    if (!have_b || sample < 2 * (int64_t)a.R) return a;
+    int64_t pa, ta, pb, tb;
+    count_tiles(a, n, sample, rp, ci, pa, ta);
+    count_tiles(b, n, sample, rp, ci, pb, tb);
+    // compare per row: the two geometries count different numbers of whole panels
+    const double ra = (double)(sample / a.R * a.R), rb = (double)(sample / b.R * b.R);
+    const double cost_a = (2.0 * (double)pa + (double)ta) / ra, cost_b = (2.0 * (double)pb + (double)tb) / rb;
+    return cost_b < cost_a ? b : a;
+}
+
 // ---------------------------------------------------------------------------
 // growable device arrays
 // ---------------------------------------------------------------------------
@@ -352,6 +410,8 @@ struct DevVec {
 struct Builder {
     Geom geo;
     int R = 0;
+    int m = 16;
+    bool geo_pending = false;    // geometry still to be chosen from the first rows
     int storage = HSYM_FP64;
     bool b64 = false;
     DevVec<double> preq, prelam;
@@ -459,6 +519,12 @@ struct Builder {
                 fail(HSYM_E_INVALID_ARG, "rowptr decreases at row " + std::to_string(next_row + carried + i));
         const double *vd = vprec == HSYM_FP64 ? (const double *)vals : nullptr;
         const float *vf = vprec == HSYM_FP32 ? (const float *)vals : nullptr;
+        if (geo_pending) {
+            // the first rows of the matrix (nothing is built or carried yet)
+            geo = choose_geometry(storage, m, n, nrows, rp, ci);
+            R = geo.R;
+            geo_pending = false;
+        }
         int64_t slab_row0 = next_row + carried;
         if (carried > 0) {
             int64_t pc = npanels_done;
@@ -513,9 +579,12 @@ void builder_begin(hsym_matrix *H, int64_t nnz_hint) {
     std::unique_ptr<Builder> b(new Builder());
     b->n = H->n;
     b->storage = H->storage;
+    b->m = H->geom_m;
     b->b64 = (H->flags & HSYM_BUILD_BLOCK64) != 0;
     b->geo = geo;
     b->R = geo.R;
+    // without an explicit geometry the first appended rows decide the panels
+    b->geo_pending = H->geom_r64 == 0;
     b->diag.assign((size_t)H->n, 0.0);
     b->abssum.assign((size_t)H->n, 0.0);
     if (nnz_hint > 0) {
