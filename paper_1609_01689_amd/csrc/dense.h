@@ -21,7 +21,7 @@ void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s);
 size_t gram_scratch_bytes(int64_t n, int K1, int K2);
 
 struct LincombArgs {
-    const double *in[6];   // set 0: in[0..nin), set 1: in[3..3+nin)
+    const double *in[6];   // set 0: in[0..nin), set 1: in[3..3+nin) (not an output of set 0)
     double *out[4];        // set 0: out[0..nout), set 1: out[2..2+nout)
     const double *coef;    // (nin*m) x (nout*m), row stride ldc, device
     int ldc;
@@ -34,10 +34,14 @@ struct LincombArgs {
 };
 void lincomb(const LincombArgs &a, hipStream_t s);
 // workgroups of a linear combination over n rows (also its residual-norm
-// partials): at most 1024, each over lincomb_tiles_per_wg(n) tiles of 64 rows
+// partials): at most HSYM_LINCOMB_WGS, each over lincomb_tiles_per_wg(n) tiles
+// of 64 rows
+#ifndef HSYM_LINCOMB_WGS
+#define HSYM_LINCOMB_WGS 1536
+#endif
 __host__ __device__ inline int64_t lincomb_tiles_per_wg(int64_t n) {
     const int64_t nt = (n + 63) / 64;
-    const int64_t wgs = nt < 1024 ? nt : 1024;
+    const int64_t wgs = nt < HSYM_LINCOMB_WGS ? nt : HSYM_LINCOMB_WGS;
     return wgs > 0 ? (nt + wgs - 1) / wgs : 1;
 }
 __host__ __device__ inline int64_t lincomb_norm_parts(int64_t n) {

@@ -220,22 +220,37 @@ void gram(const GramArgs &g, double *out, double *scratch, hipStream_t s) {
 // Linear combinations.  For every row r (one lane per row):
 //   out_o[r, :] = sum_i in_i[r, :] C[i*m:(i+1)*m, o*m:(o+1)*m]
 // for two sets sharing the coefficients (S = [X W P] and AS = [AX AW AP]).
-// Rows are read completely before they are written, so outputs may alias
-// inputs of the same row.  With theta != NULL the kernel also forms the
+// Rows of a set are read completely before they are written, so the outputs
+// of a set may alias its inputs; an output of set 0 must not be an input of
+// set 1 (set 1's rows are read while set 0's are written).  With theta !=
+// NULL the kernel also forms the
 // residual R = out_1_0 - out_0_0 diag(theta) of the new X (set 0, output 0)
 // and its product AX (set 1, output 0), writes it to `res` and accumulates the
 // squared column norms of R per workgroup.
 // ---------------------------------------------------------------------------
 // A workgroup (4 waves) walks lincomb_tiles_per_wg(n) consecutive tiles of 64
-// rows, at most 1024 workgroups in all; each wave computes 16 rows of a tile.
-// The MFMA A operands (lane: row li, columns lk, lk+4, ...) are loaded
+// rows, at most HSYM_LINCOMB_WGS workgroups in all; each wave computes 16 rows
+// of a tile.  The MFMA A operands (lane: row li, four columns) are loaded
 // straight from the input blocks and the B operands (coefficients, a few KB,
 // cache resident) once per workgroup, so the kernel streams with no LDS
 // staging and no barrier until the fixed-order reduction of the residual norms.
+//
+// Column of an input block that lane group lk feeds to the s4-th MFMA of a
+// contraction over the block's m columns (any split of the columns into four
+// groups of four serves, the same on both operands).  V16 (m = 16, 16-byte
+// aligned blocks): columns 2lk, 2lk + 1, 8 + 2lk, 9 + 2lk, so that a lane
+// loads its four values of a row with two 16-byte loads and the four lanes of
+// a row read its first and its second 64 bytes in one instruction each.
+template <bool V16>
+__device__ __forceinline__ int lincomb_col(int s4, int lk) {
+    return V16 ? 2 * lk + (s4 & 1) + 8 * (s4 >> 1) : 4 * s4 + lk;
+}
+
+template <bool V16>
 __device__ __forceinline__ void lincomb_body(const LincombArgs &a, int64_t bx) {
     __shared__ double nred[4][4][16];
     if (a.skip && *a.skip) return;   // uniform: the flag was written by an earlier launch
-    const int m = a.m, nin = a.nin, nout = a.nout;
+    const int m = V16 ? 16 : a.m, nin = a.nin, nout = a.nout;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     // every coefficient this lane needs (MFMA B operands), loop-invariant
@@ -246,73 +261,95 @@ __device__ __forceinline__ void lincomb_body(const LincombArgs &a, int64_t bx) {
         for (int i = 0; i < 3; i++)
 #pragma unroll
             for (int s4 = 0; s4 < 4; s4++) {
-                const int kk = 4 * s4 + lk;
+                const int kk = lincomb_col<V16>(s4, lk);
                 bv[q][i][s4] = (q < nout && i < nin && kk < m && li < m)
                                    ? a.coef[(i * m + kk) * a.ldc + q * m + li] : 0.0;
             }
     double nrm = 0.0;
     const int64_t ntiles = (a.n + 63) / 64, tpw = lincomb_tiles_per_wg(a.n);
+    const int64_t t_begin = bx * tpw;
     const int64_t t_end = (bx + 1) * tpw < ntiles ? (bx + 1) * tpw : ntiles;
-    for (int64_t t = bx * tpw; t < t_end; t++) {
-        const int64_t w0 = t * 64 + 16 * wave;   // this wave's 16 rows
-        const int64_t ra = w0 + li;              // row of this lane's A values
+    // The work is a sequence of steps (tile, set), set fastest.  A step loads
+    // every input value of its set for this wave's 16 rows of the tile before
+    // its first store (a wave reads and writes only its own rows, so the
+    // outputs of a set may alias its inputs), and the next step's loads are in
+    // flight while a step is combined and stored (the outputs of set 0 are not
+    // inputs of set 1).
+    auto load = [&](double (&av)[3][4], int64_t t, int set) {
+        const int64_t ra = t * 64 + 16 * wave + li;
         const bool rok = ra < a.n;
-        double4_t xkeep = (double4_t){0.0, 0.0, 0.0, 0.0};
-        // every input value of this wave's 16 rows (both sets) is loaded
-        // before the first store: a wave reads and writes only its own rows,
-        // so outputs may alias inputs, and all the loads are in flight together
-        double av[2][3][4];
 #pragma unroll
-        for (int set = 0; set < 2; set++)
-#pragma unroll
-            for (int i = 0; i < 3; i++)
+        for (int i = 0; i < 3; i++) {
+            if constexpr (V16) {
+                double2 lo = make_double2(0.0, 0.0), hi = lo;
+                if (i < nin && rok) {
+                    const double *p = a.in[set * 3 + i] + ra * 16 + 2 * lk;
+                    lo = *reinterpret_cast<const double2 *>(p);
+                    hi = *reinterpret_cast<const double2 *>(p + 8);
+                }
+                av[i][0] = lo.x; av[i][1] = lo.y; av[i][2] = hi.x; av[i][3] = hi.y;
+            } else {
 #pragma unroll
                 for (int s4 = 0; s4 < 4; s4++) {
-                    const int kk = 4 * s4 + lk;
-                    av[set][i][s4] =
-                        (set < a.nsets && i < nin && rok && kk < m) ? a.in[set * 3 + i][ra * m + kk] : 0.0;
+                    const int kk = lincomb_col<V16>(s4, lk);
+                    av[i][s4] = (i < nin && rok && kk < m) ? a.in[set * 3 + i][ra * m + kk] : 0.0;
                 }
+            }
+        }
+    };
+    double4_t xkeep = (double4_t){0.0, 0.0, 0.0, 0.0};
+    auto work = [&](const double (&av)[3][4], int64_t t, int set) {
+        const int64_t w0 = t * 64 + 16 * wave;   // this wave's 16 rows
 #pragma unroll
-        for (int set = 0; set < 2; set++) {
-            if (set >= a.nsets) break;
+        for (int q = 0; q < 2; q++) {
+            if (q >= nout) break;
+            double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int q = 0; q < 2; q++) {
-                if (q >= nout) break;
-                double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+            for (int i = 0; i < 3; i++) {
+                if (i >= nin) break;
 #pragma unroll
-                for (int i = 0; i < 3; i++) {
-                    if (i >= nin) break;
-#pragma unroll
-                    for (int s4 = 0; s4 < 4; s4++) {
-                        if (4 * s4 >= m) break;
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[set][i][s4], bv[q][i][s4], acc, 0, 0, 0);
-                    }
+                for (int s4 = 0; s4 < 4; s4++) {
+                    if (4 * s4 >= m) break;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s4], bv[q][i][s4], acc, 0, 0, 0);
                 }
-                // accumulator register v holds row lk + 4v, column li of this wave's 16 rows
-                double *dst = a.out[set * 2 + q];
+            }
+            // accumulator register v holds row lk + 4v, column li of this wave's 16 rows
+            double *dst = a.out[set * 2 + q];
 #pragma unroll
-                for (int v = 0; v < 4; v++) {
-                    const int64_t r = w0 + lk + 4 * v;
-                    if (r < a.n && li < m) dst[r * m + li] = acc[v];
-                }
-                if (q == 0 && a.theta) {
-                    if (set == 0) {
-                        xkeep = acc;
-                    } else {
-                        const double th = li < m ? a.theta[li] : 0.0;
+            for (int v = 0; v < 4; v++) {
+                const int64_t r = w0 + lk + 4 * v;
+                if (r < a.n && li < m) dst[r * m + li] = acc[v];
+            }
+            if (q == 0 && a.theta) {
+                if (set == 0) {
+                    xkeep = acc;
+                } else {
+                    const double th = li < m ? a.theta[li] : 0.0;
 #pragma unroll
-                        for (int v = 0; v < 4; v++) {
-                            const int64_t r = w0 + lk + 4 * v;
-                            if (r < a.n && li < m) {
-                                const double rv = acc[v] - xkeep[v] * th;
-                                a.res[r * m + li] = rv;
-                                nrm += rv * rv;
-                            }
+                    for (int v = 0; v < 4; v++) {
+                        const int64_t r = w0 + lk + 4 * v;
+                        if (r < a.n && li < m) {
+                            const double rv = acc[v] - xkeep[v] * th;
+                            a.res[r * m + li] = rv;
+                            nrm += rv * rv;
                         }
                     }
                 }
             }
         }
+    };
+    const int ns = a.nsets;
+    const int64_t K = (t_end - t_begin) * ns;
+    auto tile_of = [&](int64_t k) { return t_begin + (ns == 2 ? k >> 1 : k); };
+    auto set_of = [&](int64_t k) { return ns == 2 ? (int)(k & 1) : 0; };
+    double b0[3][4], b1[3][4];
+    if (K > 0) load(b0, tile_of(0), set_of(0));
+    for (int64_t k = 0; k < K; k += 2) {
+        if (k + 1 < K) load(b1, tile_of(k + 1), set_of(k + 1));
+        work(b0, tile_of(k), set_of(k));
+        if (k + 1 >= K) break;
+        if (k + 2 < K) load(b0, tile_of(k + 2), set_of(k + 2));
+        work(b1, tile_of(k + 1), set_of(k + 1));
     }
     if (a.theta) {
         // squared column norms of R for this workgroup's rows, combined in a fixed order
@@ -327,18 +364,30 @@ __device__ __forceinline__ void lincomb_body(const LincombArgs &a, int64_t bx) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_lincomb(LincombArgs a) { lincomb_body(a, blockIdx.x); }
+// three waves per SIMD (at most 168 registers; 1536 workgroups are two full
+// rounds of the 256 CUs)
+template <bool V16>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_lincomb(LincombArgs a) {
+    lincomb_body<V16>(a, blockIdx.x);
+}
 
 __global__ __launch_bounds__(256) void k_lincomb_b(const LincombArgs *__restrict__ tab) {
     const LincombArgs a = tab[blockIdx.y];
     if ((int64_t)blockIdx.x >= lincomb_norm_parts(a.n)) return;
-    lincomb_body(a, blockIdx.x);
+    lincomb_body<false>(a, blockIdx.x);
 }
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
 void lincomb(const LincombArgs &a, hipStream_t s) {
     if (a.nin * a.m > 48 || a.nout * a.m > 32 || a.nout > 2 || a.nin > 3 || a.m > 16)
         fail(HSYM_E_UNSUPPORTED, "lincomb shape");
-    hipLaunchKernelGGL(k_lincomb, dim3((unsigned)lincomb_norm_parts(a.n)), dim3(256), 0, s, a);
+    bool v16 = a.m == 16;
+    for (int set = 0; set < a.nsets; set++)
+        for (int i = 0; i < a.nin; i++) v16 = v16 && aligned16(a.in[set * 3 + i]);
+    const dim3 grid((unsigned)lincomb_norm_parts(a.n));
+    if (v16) hipLaunchKernelGGL(k_lincomb<true>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_lincomb<false>, grid, dim3(256), 0, s, a);
     HIPCHK(hipGetLastError());
 }
 

@@ -15,7 +15,10 @@ namespace hsym {
 // read at fp64, 8 bytes at fp32), so that a run's flush issues two fp64 LDS
 // atomics per lane, the count measured fastest on gfx950 (four per lane, as
 // 32-byte fp64 or 16-byte fp32 lanes need, run at half the rate).
-__host__ __device__ constexpr int spmm_lane_elems(int M) { return M < 2 ? M : 2; }
+#ifndef HSYM_LANE_ELEMS
+#define HSYM_LANE_ELEMS 2
+#endif
+__host__ __device__ constexpr int spmm_lane_elems(int M) { return M < HSYM_LANE_ELEMS ? M : HSYM_LANE_ELEMS; }
 // 16-byte units of a staged piece per thread of the 1024-thread SpMM
 // workgroup: 8 at block widths 1 and 2 (the X rows and accumulators then leave
 // room for larger pieces and the kernel for the registers), else 4.
