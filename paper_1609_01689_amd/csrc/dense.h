@@ -124,7 +124,8 @@ void lincomb_batched(const LincombArgs *tab, int count, int64_t max_n, hipStream
 // one pass over the rows when m = 16, else the two calls
 bool lincomb_gram_fusable(const LincombArgs &l, const GramArgs &g);
 void lincomb_gram(const LincombArgs &l, const GramArgs &g, double *out, double *scratch, hipStream_t s);
-// batched fused form (all fusable, K1 = na * 16, GramJob::rpw = gram_rows)
+// batched fused form (all fusable, K1 = na * 16, GramJob::rpw = gram_rows, blocks
+// 16-byte aligned)
 void lincomb_gram_batched(const LincombArgs *lt, const GramJob *gt, int count, int na, int max_parts,
                           hipStream_t s);
 struct ColsumJob {

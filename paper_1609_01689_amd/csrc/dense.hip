@@ -410,13 +410,14 @@ __device__ __forceinline__ void lincomb_gram_body(const LincombArgs &l, const Gr
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int nin = l.nin;
-    // coefficients: loop-invariant MFMA B operands
+    // coefficients: loop-invariant MFMA B operands, the columns of the input
+    // blocks split as in the linear combination (lincomb_col<true>)
     double bv[3][4];
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int s4 = 0; s4 < 4; s4++)
-            bv[i][s4] = i < nin ? l.coef[(i * 16 + 4 * s4 + lk) * l.ldc + li] : 0.0;
+            bv[i][s4] = i < nin ? l.coef[(i * 16 + lincomb_col<true>(s4, lk)) * l.ldc + li] : 0.0;
     double4_t G[NA];
 #pragma unroll
     for (int t = 0; t < NA; t++) G[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
@@ -427,10 +428,15 @@ __device__ __forceinline__ void lincomb_gram_body(const LincombArgs &l, const Gr
         const bool rok = ra < r_end;
         double av[3][4];
 #pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int s4 = 0; s4 < 4; s4++)
-                av[i][s4] = (i < nin && rok) ? l.in[i][ra * 16 + 4 * s4 + lk] : 0.0;
+        for (int i = 0; i < 3; i++) {
+            double2 lo = make_double2(0.0, 0.0), hi = lo;
+            if (i < nin && rok) {
+                const double *p = l.in[i] + ra * 16 + 2 * lk;
+                lo = *reinterpret_cast<const double2 *>(p);
+                hi = *reinterpret_cast<const double2 *>(p + 8);
+            }
+            av[i][0] = lo.x; av[i][1] = lo.y; av[i][2] = hi.x; av[i][3] = hi.y;
+        }
         // the A blocks in the Gram layout (row w0 + lk + 4v, column li)
         double ax[NA > 1 ? NA - 1 : 1][4];
 #pragma unroll
@@ -489,9 +495,11 @@ __global__ __launch_bounds__(256) void k_lincomb_gram_b(const LincombArgs *__res
 }
 
 bool lincomb_gram_fusable(const LincombArgs &l, const GramArgs &g) {
+    bool al = true;
+    for (int i = 0; i < l.nin; i++) al = al && aligned16(l.in[i]);
     return l.m == 16 && g.m == 16 && l.nsets == 1 && l.nout == 1 && !l.theta && l.nin >= 1 && l.nin <= 3 &&
            l.ldc == 16 && g.nb == 1 && g.na >= 1 && g.na <= 3 && g.b[0] == l.out[0] && g.a[g.na - 1] == l.out[0] &&
-           l.n == g.n;
+           l.n == g.n && al;
 }
 
 void lincomb_gram(const LincombArgs &l, const GramArgs &g, double *out, double *scratch, hipStream_t s) {
@@ -902,8 +910,9 @@ void gram_batched(const GramJob *jobs, int count, int K1, int K2, int max_parts,
 }
 
 void lincomb_batched(const LincombArgs *tab, int count, int64_t max_n, hipStream_t s) {
-    // every job's workgroup count is at most min(1024, its tiles of 64 rows)
-    const int64_t gx = std::min<int64_t>(1024, (max_n + 63) / 64);
+    // every job's workgroup count (lincomb_norm_parts) is at most
+    // min(HSYM_LINCOMB_WGS, its tiles of 64 rows)
+    const int64_t gx = std::min<int64_t>(HSYM_LINCOMB_WGS, (max_n + 63) / 64);
     hipLaunchKernelGGL(k_lincomb_b, dim3((unsigned)std::max<int64_t>(gx, 1), (unsigned)count), dim3(256), 0, s, tab);
     HIPCHK(hipGetLastError());
 }

@@ -141,6 +141,43 @@ def test_batched_rounds_match_solo_solves():
         M.close()
 
 
+def test_batched_rounds_cover_every_linear_combination_workgroup():
+    """Batched rounds of contexts whose linear combinations take more than
+    1,024 workgroups (n = 70,000 and 150,000: 1,094 and 1,172 workgroups of 64
+    or 128 rows) update every row: each context ends where its solve run alone
+    ends (a launch grid short of the largest workgroup count leaves the last
+    rows of X, P and AX stale and the iteration never converges)."""
+    cases = [(70000, 21, 4, 8), (150000, 22, 3, 8)]
+    tol = 1e-8
+    mats = [hs.Matrix(hsymgen.generate(n, 40, seed), storage=hs.HSYM_FP64, geom_m=m) for n, seed, nev, m in cases]
+
+    def opts(seed):
+        return hs.default_lobpcg_opts(seed=seed, keep_history=0)
+
+    alone = []
+    for M, (n, seed, nev, m) in zip(mats, cases):
+        s, ev, rep = hs.lobpcg_solve(M.h, nev, m, tol, precond="jacobi", opts=opts(seed))
+        assert s == hs.HSYM_OK
+        alone.append((ev, rep.iters))
+    ctxs = [hs.lobpcg_ctx_create(M.h, nev, m, tol, precond="jacobi", opts=opts(seed))
+            for M, (n, seed, nev, m) in zip(mats, cases)]
+    for step in range(2000):
+        hs.lobpcg_ctx_step(ctxs, iters=1)
+        if all(hs.lobpcg_ctx_status(c, cs[2])[0] for c, cs in zip(ctxs, cases)):
+            break
+    for c, (n, seed, nev, m), (ev0, it0) in zip(ctxs, cases, alone):
+        done, s, ev, rep = hs.lobpcg_ctx_status(c, nev)
+        print("n=%d: iters %d (alone %d), batched %d, max rel diff %.2e"
+              % (n, rep.iters, it0, rep.batched_iters, np.max(np.abs(ev - ev0) / np.abs(ev0))))
+        assert done and s == hs.HSYM_OK
+        assert np.max(np.abs(ev - ev0) / np.abs(ev0)) <= 1e-9
+        assert abs(rep.iters - it0) <= 2
+        assert rep.batched_iters >= rep.iters // 2
+        hs.lobpcg_ctx_destroy(c)
+    for M in mats:
+        M.close()
+
+
 def test_batched_rounds_repair_deficient_blocks():
     """Small problems whose basis nearly fills the space (n close to 3m) lose
     rank in W during batched rounds: the round's phase B then leaves such a
