@@ -695,9 +695,14 @@ __global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W,
     // One wave per 64-row block, both products on the matrix cores
     // (v_mfma_f64_16x16x4f64; lane l: li = l & 15, lk = l >> 4; A operand
     // A[li][lk], B operand B[lk][li], accumulator v = row lk + 4v, column li):
-    //   T = Q^T R as four 16-row tiles over 16 k-steps, scaled row-wise by
-    //   1/g(lambda_i - mu_j); then W = Q T, whose B operand for k-step s is
-    //   the accumulator register s % 4 of tile s / 4 in the same lane.
+    //   T = Q^T R as four 16-row tiles over 16 k-steps, the rows of tile tt
+    //   taken in the order pi (A row li is T row 16 tt + pi(li)), so that
+    //   accumulator v of tile tt in lane (li, lk) holds T row
+    //   16 tt + 2 lk + (v & 1) + 8 (v >> 1); scaled row-wise by
+    //   1/g(lambda_i - mu_j);
+    //   then W = Q T over the k-steps (tt, v) with B operand = that
+    //   accumulator, whose A operands Q[row][16 tt + 2 lk + {0, 1, 8, 9}] a
+    //   lane loads with two 16-byte loads per row.
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t r0 = b * 64;
@@ -712,13 +717,16 @@ __global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W,
         const int k = 4 * s + lk;
         rv[s] = (col && k < rows) ? W[(r0 + k) * m + li] : 0.0;
     }
+    // pi(x) = 2 (x & 3) + ((x >> 2) & 1) + 8 (x >> 3): a permutation of 0..15
+    auto pi = [](int x) { return 2 * (x & 3) + ((x >> 2) & 1) + 8 * (x >> 3); };
+    const int pli = pi(li);
     double4_t t[4];
 #pragma unroll
     for (int tt = 0; tt < 4; tt++) {
         t[tt] = (double4_t){0.0, 0.0, 0.0, 0.0};
         double qa[16];
 #pragma unroll
-        for (int s = 0; s < 16; s++) qa[s] = Qb[(4 * s + lk) * 64 + 16 * tt + li];   // Q^T[16tt + li][4s + lk]
+        for (int s = 0; s < 16; s++) qa[s] = Qb[(4 * s + lk) * 64 + 16 * tt + pli];   // Q^T[16tt + pi(li)][4s + lk]
 #pragma unroll
         for (int s = 0; s < 16; s++) t[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[s], rv[s], t[tt], 0, 0, 0);
     }
@@ -727,15 +735,21 @@ __global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W,
     for (int tt = 0; tt < 4; tt++)
 #pragma unroll
         for (int v = 0; v < 4; v++) {
-            const int i = 16 * tt + lk + 4 * v;
+            const int i = 16 * tt + 2 * lk + (v & 1) + 8 * (v >> 1);   // = 16 tt + pi(lk + 4v)
             t[tt][v] = col ? t[tt][v] / guard_den(lam[b * 64 + i] - muj, delta) : 0.0;
         }
 #pragma unroll
     for (int tt = 0; tt < 4; tt++) {
         double qa[16];
+        const double *qrow = Qb + (16 * tt + li) * 64 + 2 * lk;
 #pragma unroll
-        for (int s = 0; s < 16; s++) qa[s] = Qb[(16 * tt + li) * 64 + 4 * s + lk];   // Q[16tt + li][4s + lk]
+        for (int q = 0; q < 4; q++) {
+            const double2 lo = *reinterpret_cast<const double2 *>(qrow + 16 * q);
+            const double2 hi = *reinterpret_cast<const double2 *>(qrow + 16 * q + 8);
+            qa[4 * q] = lo.x; qa[4 * q + 1] = lo.y; qa[4 * q + 2] = hi.x; qa[4 * q + 3] = hi.y;
+        }
         double4_t w = (double4_t){0.0, 0.0, 0.0, 0.0};
+        // k-step (q, v): Q[16tt + li][16q + 2lk + (v & 1) + 8 (v >> 1)] times T of that row
 #pragma unroll
         for (int s = 0; s < 16; s++) w = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[s], t[s >> 2][s & 3], w, 0, 0, 0);
 #pragma unroll
