@@ -415,6 +415,7 @@ struct Builder {
     int storage = HSYM_FP64;
     bool b64 = false;
     DevVec<double> preq, prelam;
+    DevVec<float> preq32;          // the factors Q at fp32 storage
     int64_t n = 0;
     int64_t next_row = 0;          // first row not yet turned into panels
     int64_t npanels_done = 0;
@@ -436,7 +437,7 @@ struct Builder {
 
     void release() {
         tiles.release(); blob.release();
-        preq.release(); prelam.release();
+        preq.release(); prelam.release(); preq32.release();
     }
 
     // turn complete panels [p0, p1) whose rows lie in the given slab into device data
@@ -488,7 +489,16 @@ struct Builder {
             }
             tiles.append(t.data(), (int64_t)t.size());
             blob.append(bl.data(), (int64_t)bl.size());
-            if (b64) { preq.append(pq.data(), (int64_t)pq.size()); prelam.append(pl.data(), (int64_t)pl.size()); }
+            if (b64) {
+                if (storage == HSYM_FP32) {
+                    // the preconditioner's factors in the storage precision
+                    std::vector<float> q32(pq.begin(), pq.end());
+                    preq32.append(q32.data(), (int64_t)q32.size());
+                } else {
+                    preq.append(pq.data(), (int64_t)pq.size());
+                }
+                prelam.append(pl.data(), (int64_t)pl.size());
+            }
             npieces += (int64_t)t.size();
             nentries += pos;
             nbytes += (int64_t)bl.size();
@@ -667,10 +677,12 @@ void builder_finish(hsym_matrix *H) {
     HIPCHK(hipMemcpy(H->diag64, b->diag.data(), sizeof(double) * (size_t)H->n, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(H->diag32, d32.data(), sizeof(float) * (size_t)H->n, hipMemcpyHostToDevice));
     if (b->b64) {
-        H->pre_q = b->preq.p; H->pre_lam = b->prelam.p;
+        H->pre_q32 = H->storage == HSYM_FP32;
+        H->pre_q = H->pre_q32 ? (void *)b->preq32.p : (void *)b->preq.p;
+        H->pre_lam = b->prelam.p;
         H->pre_nchunks = (H->n + 63) / 64;
-        dt.bytes += b->preq.cap * 8 + b->prelam.cap * 8;
-        b->preq.p = nullptr; b->prelam.p = nullptr;
+        dt.bytes += b->preq.cap * 8 + b->preq32.cap * 4 + b->prelam.cap * 8;
+        b->preq.p = nullptr; b->preq32.p = nullptr; b->prelam.p = nullptr;
     }
     double nm = 0.0;
     for (double v : b->abssum) nm = std::max(nm, v);

@@ -688,7 +688,10 @@ __global__ __launch_bounds__(256) void k_precond_jacobi_b(const JacobiJob *__res
 }
 
 // One wave per 64-row chunk: W_b = Q diag(1/g(lambda - mu_j)) Q^T R_b.
-__global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W, const double *__restrict__ Q,
+// QT: the storage of the factors Q (fp64, or fp32 for fp32-storage handles; the
+// products are fp64 either way)
+template <typename QT>
+__global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W, const QT *__restrict__ Q,
                                                          const double *__restrict__ lam,
                                                          const double *__restrict__ mu, double delta, int64_t n,
                                                          int m) {
@@ -708,7 +711,7 @@ __global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W,
     const int64_t r0 = b * 64;
     if (r0 >= n) return;   // whole wave
     const int rows = (int)((n - r0) < 64 ? (n - r0) : 64);
-    const double *Qb = Q + b * 64 * 64;
+    const QT *Qb = Q + b * 64 * 64;
     const bool col = li < m;
     // R rows 4s + lk of column li, s = 0..15
     double rv[16];
@@ -726,7 +729,7 @@ __global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W,
         t[tt] = (double4_t){0.0, 0.0, 0.0, 0.0};
         double qa[16];
 #pragma unroll
-        for (int s = 0; s < 16; s++) qa[s] = Qb[(4 * s + lk) * 64 + 16 * tt + pli];   // Q^T[16tt + pi(li)][4s + lk]
+        for (int s = 0; s < 16; s++) qa[s] = (double)Qb[(4 * s + lk) * 64 + 16 * tt + pli];   // Q^T[16tt + pi(li)][4s + lk]
 #pragma unroll
         for (int s = 0; s < 16; s++) t[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[s], rv[s], t[tt], 0, 0, 0);
     }
@@ -741,12 +744,18 @@ __global__ __launch_bounds__(256) void k_precond_block64(double *__restrict__ W,
 #pragma unroll
     for (int tt = 0; tt < 4; tt++) {
         double qa[16];
-        const double *qrow = Qb + (16 * tt + li) * 64 + 2 * lk;
+        const QT *qrow = Qb + (16 * tt + li) * 64 + 2 * lk;
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-            const double2 lo = *reinterpret_cast<const double2 *>(qrow + 16 * q);
-            const double2 hi = *reinterpret_cast<const double2 *>(qrow + 16 * q + 8);
-            qa[4 * q] = lo.x; qa[4 * q + 1] = lo.y; qa[4 * q + 2] = hi.x; qa[4 * q + 3] = hi.y;
+            if constexpr (sizeof(QT) == 8) {
+                const double2 lo = *reinterpret_cast<const double2 *>(qrow + 16 * q);
+                const double2 hi = *reinterpret_cast<const double2 *>(qrow + 16 * q + 8);
+                qa[4 * q] = lo.x; qa[4 * q + 1] = lo.y; qa[4 * q + 2] = hi.x; qa[4 * q + 3] = hi.y;
+            } else {
+                const float2 lo = *reinterpret_cast<const float2 *>(qrow + 16 * q);
+                const float2 hi = *reinterpret_cast<const float2 *>(qrow + 16 * q + 8);
+                qa[4 * q] = lo.x; qa[4 * q + 1] = lo.y; qa[4 * q + 2] = hi.x; qa[4 * q + 3] = hi.y;
+            }
         }
         double4_t w = (double4_t){0.0, 0.0, 0.0, 0.0};
         // k-step (q, v): Q[16tt + li][16q + 2lk + (v & 1) + 8 (v >> 1)] times T of that row
@@ -992,8 +1001,13 @@ void precond_apply(hsym_matrix *H, int kind, double *W, const double *mu, double
             default: fail(HSYM_E_INVALID_ARG, "block width must be 1..16");
         }
     } else if (kind == HSYM_PRECOND_BLOCK64) {
-        hipLaunchKernelGGL(k_precond_block64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, H->pre_q,
-                           H->pre_lam, mu, delta, n, m);
+        const dim3 grid((unsigned)((n + 255) / 256));
+        if (H->pre_q32)
+            hipLaunchKernelGGL(k_precond_block64<float>, grid, dim3(256), 0, s, W, (const float *)H->pre_q,
+                               H->pre_lam, mu, delta, n, m);
+        else
+            hipLaunchKernelGGL(k_precond_block64<double>, grid, dim3(256), 0, s, W, (const double *)H->pre_q,
+                               H->pre_lam, mu, delta, n, m);
     }
     HIPCHK(hipGetLastError());
 }

@@ -145,8 +145,10 @@ struct hsym_matrix {
     int geom_r64 = 0, geom_lc = 0; // explicit panel rows / 64 and log2 chunk columns (0: automatic)
     std::vector<double> d_host;   // diagonal, fp64, host copy
     std::vector<double> colsum;   // absolute column sums (streaming create)
-    // block-64 preconditioner: per 64-row chunk Q (64x64, row-major) and lambda
-    double *pre_q = nullptr;
+    // block-64 preconditioner: per 64-row chunk Q (64x64, row-major) and lambda;
+    // Q is fp32 for fp32 storage (pre_q32), else fp64
+    void *pre_q = nullptr;
+    bool pre_q32 = false;
     double *pre_lam = nullptr;
     int64_t pre_nchunks = 0;
     // diagonal group tiles (FOM preconditioner): tile t covers rows
