@@ -68,3 +68,21 @@ def test_builder_under_sanitizers(checker, case):
     print(r.stdout)
     print(r.stderr[-4000:])
     assert r.returncode == 0 and r.stdout.strip().endswith("OK"), r.stdout + r.stderr[-4000:]
+
+
+@pytest.mark.parametrize("N,rows", [(150, 512), (500, 384)])
+def test_geometry_follows_tile_fill(checker, N, rows):
+    """Without an explicit geometry the builder chooses the panels from the
+    first rows it receives (fp32 storage, m = 16, n = 140,000: the default
+    rule's 512 x 128 panels or 384 x 128 ones whose pieces hold 8,184 entries
+    instead of 5,112).  At 150 nonzeros per full row the tiles of 512 rows
+    fit one piece and the taller panels stay; at 500 they would be cut into
+    about 1.6 pieces and the shorter panels are taken.  The
+    replay of the kernel's passes checks the product either way."""
+    env = dict(os.environ, HSYM_HOST_THREADS="4", ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    r = subprocess.run([checker, "gen", "140000", str(N), "4", "1", "16", "0", "0", "0"], capture_output=True,
+                       text=True, env=env, timeout=600)
+    print(r.stdout)
+    assert r.returncode == 0 and r.stdout.strip().endswith("OK"), r.stdout + r.stderr[-4000:]
+    assert ("geometry R=%d C=128 " % rows) in r.stdout
