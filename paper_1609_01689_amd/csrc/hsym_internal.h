@@ -14,7 +14,9 @@ namespace hsym {
 // Elements of an X row that one lane of the SpMM handles: 2 (one 16-byte LDS
 // read at fp64, 8 bytes at fp32), so that a run's flush issues two fp64 LDS
 // atomics per lane, the count measured fastest on gfx950 (four per lane, as
-// 32-byte fp64 or 16-byte fp32 lanes need, run at half the rate).
+// 32-byte fp64 or 16-byte fp32 lanes need, run at half the rate; with the
+// record format of the pieces, four elements per lane measured 18-37% slower).
+// HSYM_LANE_ELEMS overrides it at build time, for such measurements.
 #ifndef HSYM_LANE_ELEMS
 #define HSYM_LANE_ELEMS 2
 #endif
@@ -75,7 +77,8 @@ void check_hip(hipError_t e, const char *what);
 // ---------------------------------------------------------------------------
 // steps per segment are a multiple of this (the SpMM takes two per batch)
 constexpr int SPMM_STEP = 2;
-// position of step s of segment g in a piece of G segments
+// position of step s of segment g in a piece of G segments (steps paired)
+static_assert(SPMM_STEP == 2, "piece_pos pairs the steps of a batch");
 __host__ __device__ inline int64_t piece_pos(int64_t s, int64_t g, int64_t G) {
     return (s >> 1) * 2 * G + 2 * g + (s & 1);
 }
