@@ -51,7 +51,8 @@ enum hsym_prec { HSYM_FP64 = 0, HSYM_FP32 = 1 };
 
 /* Preconditioners of Section 3.2 (eq. 11): none, the diagonal of H
  * ("the extreme case" of a block-diagonal approximation), the dense 64x64
- * diagonal blocks of H solved directly with fp64 factors, or the paper's own
+ * diagonal blocks of H solved directly (eigenvector factors stored in the
+ * handle's storage precision, applied with fp64 products), or the paper's own
  * choice (end of Section 3.2, Section 4.3): the diagonal tiles of the
  * many-body groups (hsym_attach_group_tiles), each shifted system solved by
  * lobpcg_opts.fom_iters steps of the full orthogonalization method per
