@@ -399,24 +399,56 @@ __device__ void tri_inverse(const double (*L)[KMAX + 1], const double *sc, int k
 }
 
 // B <- Li S Li^T (k x k, exactly symmetric) for lower-triangular Li; T is
-// scratch.  Whole workgroup.
+// scratch; B may be S.  Whole workgroup, on the matrix cores: 16 x 16 output
+// tiles dealt to the four waves, v_mfma_f64_16x16x4f64 over k-steps of 4
+// (lane: li = lane & 15, lk = lane >> 4; A operand A[li][lk], B operand
+// B[lk][li]; accumulator v holds row lk + 4v, column li), entries past k read
+// as zero.  T = Li S takes the k-steps up to the tile row's diagonal (Li is
+// lower triangular); B = T Li^T forms the tiles on and above the diagonal and
+// mirrors them (on a diagonal tile only row <= column is taken).
+typedef double rr_double4 __attribute__((ext_vector_type(4)));
 __device__ void congruence(const double (*Li)[KMAX + 1], const double (*S)[KMAX + 1], int k,
                            double (*T)[KMAX + 1], double (*B)[KMAX + 1]) {
-    const int tid = threadIdx.x;
-    for (int e0 = tid; e0 < k * k; e0 += 256) {
-        const int i = e0 / k, j = e0 - (e0 / k) * k;
-        double v = 0.0;
-        for (int q = 0; q <= i; q++) v = fma(Li[i][q], S[q][j], v);
-        T[i][j] = v;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nt = (k + 15) >> 4;
+    for (int t = wave; t < nt * nt; t += 4) {
+        const int ti = t / nt, tj = t - (t / nt) * nt;
+        const int r = 16 * ti + li, c = 16 * tj + li;
+        const int qmax = k < 16 * ti + 16 ? k : 16 * ti + 16;
+        rr_double4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int q0 = 0; q0 < qmax; q0 += 4) {
+            const int q = q0 + lk;
+            const double av = (r < k && q < k) ? Li[r][q] : 0.0;
+            const double bv = (q < k && c < k) ? S[q][c] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int row = 16 * ti + lk + 4 * v;
+            if (row < k && c < k) T[row][c] = acc[v];
+        }
     }
     __syncthreads();
-    for (int e0 = tid; e0 < k * k; e0 += 256) {
-        const int i = e0 / k, j = e0 - (e0 / k) * k;
-        if (i <= j) {
-            double v = 0.0;
-            for (int q = 0; q <= j; q++) v = fma(T[i][q], Li[j][q], v);
-            B[i][j] = v;
-            B[j][i] = v;
+    for (int t = wave; t < nt * nt; t += 4) {
+        const int ti = t / nt, tj = t - (t / nt) * nt;
+        if (ti > tj) continue;
+        const int r = 16 * ti + li, c = 16 * tj + li;
+        const int qmax = k < 16 * tj + 16 ? k : 16 * tj + 16;
+        rr_double4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int q0 = 0; q0 < qmax; q0 += 4) {
+            const int q = q0 + lk;
+            const double av = (r < k && q < k) ? T[r][q] : 0.0;
+            const double bv = (c < k && q < k) ? Li[c][q] : 0.0;   // Li^T[q][c]
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int row = 16 * ti + lk + 4 * v;
+            if (row < k && c < k && row <= c) {
+                B[row][c] = acc[v];
+                B[c][row] = acc[v];
+            }
         }
     }
     __syncthreads();
