@@ -1069,7 +1069,7 @@ __global__ __launch_bounds__(256) void k_absmax_part(const double *__restrict__ 
         red[threadIdx.x] = best;
         __syncthreads();
         for (int off = 128; off > 0; off >>= 1) {
-            if (threadIdx.x < off) {
+            if ((int)threadIdx.x < off) {
                 AbsMax o = red[threadIdx.x + off], c = red[threadIdx.x];
                 if (o.a > c.a || (o.a == c.a && o.r < c.r)) red[threadIdx.x] = o;
             }
@@ -1084,7 +1084,7 @@ __global__ __launch_bounds__(256) void k_sign_copy(const double *__restrict__ X,
                                                    const AbsMax *__restrict__ part, int nparts,
                                                    double *__restrict__ out) {
     __shared__ double sg[16];
-    if (threadIdx.x < nev) {
+    if ((int)threadIdx.x < nev) {
         AbsMax b = {-1.0, 0.0, 0};
         for (int p = 0; p < nparts; p++) {
             AbsMax o = part[(int64_t)p * nev + threadIdx.x];
