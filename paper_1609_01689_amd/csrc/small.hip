@@ -575,27 +575,34 @@ __global__ __launch_bounds__(256) void k_small_rr(Batch<RRArgs> b) {
     // follows when the basis was far from orthonormal.
     if (tid < 64) wave_chol<KM>(GS, k0, Lf, scl, pvt);
     __syncthreads();
-    if (tid == 0) {
-        int k = k0;
-        if (a.nblk == 3) {
-            for (int j = 2 * m; j < 3 * m; j++) {
-                double nn = 0.0;
-                for (int c = 2 * m; c <= j; c++) nn = fma(Lf[j][c], Lf[j][c], nn);
-                // the oracle's test on the normalised projection of P, and a
-                // P column whose angle to span[X W, earlier P] has a sine
-                // below 1e-5: the transform would amplify the rounding of the
-                // basis and of A S by more than 1e5
-                const double rel = Lf[j][j] / sqrt(fmax(nn, 1e-300));
-                if (!(rel >= 1e-4) || !(pvt[j] >= 1e-10)) k = 2 * m;
-            }
+    if (tid < 64) {
+        // one lane per basis column j (the first wave)
+        const int j = lane;
+        bool drop = false;
+        if (a.nblk == 3 && j >= 2 * m && j < 3 * m) {
+            double nn = 0.0;
+            for (int c = 2 * m; c <= j; c++) nn = fma(Lf[j][c], Lf[j][c], nn);
+            // the oracle's test on the normalised projection of P, and a
+            // P column whose angle to span[X W, earlier P] has a sine
+            // below 1e-5: the transform would amplify the rounding of the
+            // basis and of A S by more than 1e5
+            const double rel = Lf[j][j] / sqrt(fmax(nn, 1e-300));
+            drop = !(rel >= 1e-4) || !(pvt[j] >= 1e-10);
         }
-        double pmin = 1.0;
-        for (int j = 0; j < k; j++) pmin = fmin(pmin, pvt[j]);
-        for (int j = 0; j < k; j++)
-            if (!isfinite(pvt[j]) || !isfinite(scl[j])) bad = 1;
-        kk = k;
-        second = pmin < 1e-4;
-        if (a.flag) a.flag[1] = k < k0 ? 1 : 0;
+        const int k = __ballot(drop) ? 2 * m : k0;
+        // smallest pivot of the kept columns (fmin passes over NaN; lanes
+        // past k carry 1)
+        double pmin = j < k ? pvt[j] : 1.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) pmin = fmin(pmin, __shfl_xor(pmin, off));
+        const bool nonfinite = j < k && (!isfinite(pvt[j]) || !isfinite(scl[j]));
+        const bool any_bad = __ballot(nonfinite) != 0ull;
+        if (lane == 0) {
+            if (any_bad) bad = 1;
+            kk = k;
+            second = pmin < 1e-4;
+            if (a.flag) a.flag[1] = k < k0 ? 1 : 0;
+        }
     }
     __syncthreads();
     const int k = kk;
